@@ -1,0 +1,291 @@
+/*
+ * Plain CPU oracle: TEST INFRASTRUCTURE ONLY (see oracle.h for what it computes
+ * and which passages of the paper each part follows).  Built with
+ * -O2 -ffp-contract=off and no fast-math, so every double operation below is a
+ * single IEEE-754 round-to-nearest-even operation.
+ */
+#include "oracle.h"
+
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+typedef unsigned __int128 u128;
+
+static const uint64_t BLOCK = 1ULL << ORACLE_BLOCK_LOG2;
+
+/* ---- modular arithmetic with 128-bit products (Number Theory section) ---- */
+
+uint64_t oracle_mulmod(uint64_t x, uint64_t y, uint64_t m) {
+  return (uint64_t)(((u128)x * y) % m);
+}
+
+/* Repeated squaring and multiplying (Introduction: fewer than 2 log2 e products). */
+uint64_t oracle_powmod(uint64_t x, uint64_t e, uint64_t m) {
+  uint64_t result = 1 % m;
+  uint64_t base = x % m;
+  while (e) {
+    if (e & 1) result = oracle_mulmod(result, base, m);
+    base = oracle_mulmod(base, base, m);
+    e >>= 1;
+  }
+  return result;
+}
+
+uint64_t oracle_gcd(uint64_t x, uint64_t y) {
+  while (y) {
+    uint64_t t = x % y;
+    x = y;
+    y = t;
+  }
+  return x;
+}
+
+/* Extended Euclid on signed 128-bit values (eq. RSAd: d = e^-1 mod phi). */
+uint64_t oracle_inverse(uint64_t x, uint64_t m) {
+  __int128 r0 = m, r1 = x % m, t0 = 0, t1 = 1;
+  while (r1 != 0) {
+    __int128 qt = r0 / r1, tmp;
+    tmp = r0 - qt * r1; r0 = r1; r1 = tmp;
+    tmp = t0 - qt * t1; t0 = t1; t1 = tmp;
+  }
+  if (r0 != 1) return 0;
+  if (t0 < 0) t0 += m;
+  return (uint64_t)t0;
+}
+
+/* Strong-pseudoprime test to one base g (Implementation section). */
+static int strong_probable_prime(uint64_t n, uint64_t g) {
+  uint64_t d = n - 1;
+  int r = 0;
+  while ((d & 1) == 0) { d >>= 1; ++r; }
+  uint64_t x = oracle_powmod(g, d, n);
+  if (x == 1 || x == n - 1) return 1;
+  for (int j = 1; j < r; ++j) {
+    x = oracle_mulmod(x, x, n);
+    if (x == n - 1) return 1;
+  }
+  return 0;
+}
+
+int oracle_is_prime(uint64_t n) {
+  static const uint64_t bases[12] = {2, 3, 5, 7, 11, 13, 17, 19, 23, 29, 31, 37};
+  if (n < 2) return 0;
+  for (int i = 0; i < 12; ++i) {
+    if (n == bases[i]) return 1;
+    if (n % bases[i] == 0) return 0;
+  }
+  int nb = (n < (1ULL << 32)) ? 5 : 12;
+  for (int i = 0; i < nb; ++i)
+    if (!strong_probable_prime(n, bases[i])) return 0;
+  return 1;
+}
+
+static uint64_t lambda_of(uint64_t p, uint64_t q) {
+  uint64_t g = oracle_gcd(p - 1, q - 1);
+  return (p - 1) / g * (q - 1);
+}
+
+int oracle_check_params(uint64_t p, uint64_t q, uint64_t e) {
+  if (p < (1ULL << 31) || p >= (1ULL << 32) || q < (1ULL << 31) || q >= (1ULL << 32)) return -3;
+  if (!oracle_is_prime(p) || !oracle_is_prime(q)) return -1;
+  if (p == q) return -2;
+  /* A decryption exponent exists iff gcd(e, phi) = 1, equivalently gcd(e, lambda) = 1. */
+  if (e == 0 || oracle_gcd(e, lambda_of(p, q)) != 1) return -4;
+  return 0;
+}
+
+uint64_t oracle_decryption_exponent(uint64_t p, uint64_t q, uint64_t e, int use_lambda) {
+  uint64_t mod = use_lambda ? lambda_of(p, q) : (p - 1) * (q - 1);
+  return oracle_inverse(e, mod);
+}
+
+/* ---- skip generator (eq. congruentialgenerator1) ---- */
+
+uint64_t oracle_lcg_next(uint64_t s) { return oracle_mulmod(s, ORACLE_A, ORACLE_Q); }
+
+/* Q = a q1 + q2 with q2 < q1, so both a*(s mod q1) and q2*floor(s/q1) stay
+ * below Q (eq. restrictedprimitiveroots); their difference is brought into
+ * [0, Q) without going negative. */
+uint64_t oracle_lcg_next_schrage(uint64_t s) {
+  const uint64_t q1 = ORACLE_Q / ORACLE_A, q2 = ORACLE_Q % ORACLE_A;
+  uint64_t s1 = ORACLE_A * (s % q1);
+  uint64_t s2 = q2 * (s / q1);
+  return (s1 >= s2) ? s1 - s2 : ORACLE_Q - (s2 - s1);
+}
+
+uint64_t oracle_skip(uint64_t s0, uint64_t k) {
+  return oracle_mulmod(s0, oracle_powmod(ORACLE_A, k, ORACLE_Q), ORACLE_Q);
+}
+
+/* sum_{j=1..N} s0 a^j = s0 a (a^N - 1) / (a - 1) in the field Z_Q (eq. pseudoskip). */
+uint64_t oracle_block_seed(uint64_t s0, uint64_t b) {
+  uint64_t N = b << ORACLE_BLOCK_LOG2;
+  uint64_t aN = oracle_powmod(ORACLE_A, N, ORACLE_Q);
+  uint64_t num = oracle_mulmod(oracle_mulmod(s0, ORACLE_A, ORACLE_Q), (aN + ORACLE_Q - 1) % ORACLE_Q,
+                               ORACLE_Q);
+  return oracle_mulmod(num, oracle_inverse(ORACLE_A - 1, ORACLE_Q), ORACLE_Q);
+}
+
+uint64_t oracle_block_seed_walk(uint64_t s0, uint64_t b) {
+  uint64_t N = b << ORACLE_BLOCK_LOG2;
+  uint64_t s = s0;
+  u128 sum = 0;
+  for (uint64_t j = 1; j <= N; ++j) {
+    s = oracle_lcg_next(s);
+    sum += s;
+  }
+  return (uint64_t)(sum % ORACLE_Q);
+}
+
+/* ---- floating-point output (eq. CodeFloatingPointStep) ---- */
+
+double oracle_ratio(uint64_t c, uint64_t n) {
+  double r = (double)c / (double)n;
+  if (r == 1.0) r = nextafter(1.0, 0.0);
+  return r;
+}
+
+/* ---- the sequence ---- */
+
+static int instance_ok(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0) {
+  int rc = oracle_check_params(p, q, e);
+  if (rc) return rc;
+  if (m0 >= p * q) return -5;
+  if (s0 == 0 || s0 >= ORACLE_Q) return -5;
+  return 0;
+}
+
+/* Walk the message sequence over [k0, k0+count), calling back with (k, m_k). */
+static int walk(uint64_t p, uint64_t q, uint64_t m0, uint64_t s0, uint64_t k0, uint64_t count,
+                void (*emit)(void*, uint64_t, uint64_t), void* ctx) {
+  if (count == 0) return 0;
+  if ((u128)k0 + count > ((u128)1 << 64)) return -6;
+  uint64_t n = p * q;
+  uint64_t b = k0 >> ORACLE_BLOCK_LOG2;
+  uint64_t k = b << ORACLE_BLOCK_LOG2;
+  uint64_t s = oracle_skip(s0, k);
+  uint64_t m = (uint64_t)(((u128)m0 + oracle_block_seed(s0, b)) % n);
+  uint64_t last = k0 + (count - 1);
+  for (;;) {
+    if (k >= k0) emit(ctx, k, m);
+    if (k == last) break;
+    ++k;
+    s = oracle_lcg_next(s);
+    if ((k & (BLOCK - 1)) == 0)
+      m = (uint64_t)(((u128)m0 + oracle_block_seed(s0, k >> ORACLE_BLOCK_LOG2)) % n);
+    else
+      m = (uint64_t)(((u128)m + s) % n);
+  }
+  return 0;
+}
+
+struct gen_ctx {
+  uint64_t n, e, k0;
+  uint64_t* c;
+  double* r;
+  uint64_t* m;
+  oracle_stats* st;
+};
+
+static void emit_gen(void* vp, uint64_t k, uint64_t m) {
+  struct gen_ctx* g = (struct gen_ctx*)vp;
+  uint64_t c = oracle_powmod(m, g->e, g->n);
+  if (g->c) g->c[k - g->k0] = c;
+  if (g->r) g->r[k - g->k0] = oracle_ratio(c, g->n);
+}
+
+static void emit_msg(void* vp, uint64_t k, uint64_t m) {
+  struct gen_ctx* g = (struct gen_ctx*)vp;
+  g->m[k - g->k0] = m;
+}
+
+int oracle_generate(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
+                    uint64_t count, uint64_t* c_out, double* r_out) {
+  int rc = instance_ok(p, q, e, m0, s0);
+  if (rc) return rc;
+  struct gen_ctx g = {p * q, e, k0, c_out, r_out, NULL, NULL};
+  return walk(p, q, m0, s0, k0, count, emit_gen, &g);
+}
+
+int oracle_messages(uint64_t p, uint64_t q, uint64_t m0, uint64_t s0, uint64_t k0, uint64_t count,
+                    uint64_t* m_out) {
+  int rc = instance_ok(p, q, 1, m0, s0);
+  if (rc) return rc;
+  struct gen_ctx g = {p * q, 1, k0, NULL, NULL, m_out, NULL};
+  return walk(p, q, m0, s0, k0, count, emit_msg, &g);
+}
+
+/* ---- algorithm (1): the paper's own CRT formulation ---- */
+
+/* Exponentiation modulo a 32-bit prime with native 64-bit products. */
+static uint64_t powmod32(uint64_t x, uint64_t e, uint64_t m) {
+  uint64_t result = 1 % m, base = x % m;
+  while (e) {
+    if (e & 1) result = result * base % m;
+    base = base * base % m;
+    e >>= 1;
+  }
+  return result;
+}
+
+int oracle_paper_algorithm1(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
+                            uint64_t count, uint64_t* c_out, double* r_out) {
+  int rc = instance_ok(p, q, e, m0, s0);
+  if (rc) return rc;
+  uint64_t n = p * q;
+  uint64_t qinv = oracle_inverse(q % p, p); /* precomputed q^-1 mod p */
+  uint64_t s = s0, mp = m0 % p, mq = m0 % q;
+  for (uint64_t i = 0; i < count; ++i) {
+    s = oracle_lcg_next_schrage(s);         /* skip step, 64-bit only */
+    mp = (mp + s) % p;                      /* CRT residues of the message */
+    mq = (mq + s) % q;
+    uint64_t cp = powmod32(mp, e, p);
+    uint64_t cq = powmod32(mq, e, q);
+    uint64_t diff = (cp + p - cq % p) % p;  /* (c_p - c_q) mod p, kept non-negative */
+    uint64_t c = (diff * qinv % p) * q + cq; /* Garner */
+    if (c_out) c_out[i] = c;
+    if (r_out) r_out[i] = oracle_ratio(c, n);
+  }
+  return 0;
+}
+
+void oracle_encrypt_array(uint64_t n, uint64_t e, const uint64_t* m, uint64_t* c, uint64_t count) {
+  for (uint64_t i = 0; i < count; ++i) c[i] = oracle_powmod(m[i], e, n);
+}
+
+/* ---- statistics ---- */
+
+static void stats_add(oracle_stats* st, double r) {
+  st->hist[(int)(r * 1024.0)]++;
+  if (r < 0.5) st->lt_half++;
+  if (r > 0.0) {
+    double v = ldexp(r, 128); /* exact: a power-of-two scaling */
+    u128 x = (u128)v;         /* r >= 2^-75 makes v an integer below 2^128 */
+    u128 lo = ((u128)st->sum_fx[1] << 64) | st->sum_fx[0];
+    u128 nlo = lo + x;
+    if (nlo < lo) st->sum_fx[2]++;
+    st->sum_fx[0] = (uint64_t)nlo;
+    st->sum_fx[1] = (uint64_t)(nlo >> 64);
+  }
+}
+
+void oracle_stats_of(const double* r, uint64_t count, oracle_stats* st) {
+  memset(st, 0, sizeof(*st));
+  for (uint64_t i = 0; i < count; ++i) stats_add(st, r[i]);
+}
+
+static void emit_stats(void* vp, uint64_t k, uint64_t m) {
+  struct gen_ctx* g = (struct gen_ctx*)vp;
+  (void)k;
+  stats_add(g->st, oracle_ratio(oracle_powmod(m, g->e, g->n), g->n));
+}
+
+int oracle_consume(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
+                   uint64_t count, oracle_stats* st) {
+  int rc = instance_ok(p, q, e, m0, s0);
+  if (rc) return rc;
+  memset(st, 0, sizeof(*st));
+  struct gen_ctx g = {p * q, e, k0, NULL, NULL, NULL, st};
+  return walk(p, q, m0, s0, k0, count, emit_stats, &g);
+}
