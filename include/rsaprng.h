@@ -1,0 +1,270 @@
+/*
+ * rsaprng.h -- C ABI of the MI355X (gfx950) implementation of the
+ * non-cryptographic RSA-exponentiation pseudorandom generator of
+ * Datephanyawat & Beale (arXiv:1811.11629).
+ *
+ * The generator (paper: Introduction eq. encrypt2, Pseudorandom skips,
+ * Implementation algorithm (1)):
+ *   skips     s_j = s0 * a^j mod Q,  Q = 2^63 - 25, a = 2307085864
+ *   messages  m_k = (m_{k-1} + s_k) mod n inside each block of 2^20 indices;
+ *             at a block start bB the message is re-seeded to
+ *             (m0 + (s_1 + ... + s_bB mod Q)) mod n, which makes every index
+ *             reachable by a jump (the paper's closed form, eq. pseudoskip,
+ *             is evaluated exactly for the skips; the re-seeding is this
+ *             library's reading of how to jump the message sum)
+ *   outputs   c_k = m_k^e mod n   (n = p q, p and q 32-bit primes, e small odd)
+ *             r_k = RN(RN(c_k) / RN(n)) in IEEE binary64, with 1 - 2^-53
+ *             returned where that quotient rounds to 1.0 (the guard the paper
+ *             asks for after algorithm (1)).
+ * Every output is a pure function of (p, q, e, m0, s0, k): it does not depend
+ * on streams, tiling, batch composition, kernel variant or device.
+ *
+ * Conventions
+ *  - Functions returning int return RSAPRNG_OK (0) or a negative status.
+ *  - Output buffers and stats records are DEVICE pointers owned by the caller,
+ *    8-byte aligned; any output pointer may be NULL to skip that output.
+ *  - Streams are hipStream_t values passed as void* (NULL = default stream).
+ *  - Generation calls only enqueue work on the stream.  Launch errors return
+ *    RSAPRNG_E_HIP; a fault is reported when the caller synchronises.  A
+ *    kernel-detected error (a bounded wait that expired) is returned by the
+ *    next rsaprng_check_device_error() on the same stream.
+ *  - Handles are immutable after creation and may be shared by threads; each
+ *    stream gets its own launch scratch, so concurrent launches must use
+ *    different streams (launches on one stream are ordered).
+ *  - No function here allocates on the hot path except where stated
+ *    (first use of a stream grows its scratch; batch/server creation).
+ */
+#ifndef RSAPRNG_H
+#define RSAPRNG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RSAPRNG_BLOCK_LOG2 20                 /* output-defining: block of the re-seeding */
+#define RSAPRNG_Q 9223372036854775783ULL      /* skip modulus 2^63 - 25 (Implementation) */
+#define RSAPRNG_A 2307085864ULL               /* skip multiplier, a primitive root mod Q */
+
+enum rsaprng_status {
+  RSAPRNG_OK = 0,
+  RSAPRNG_E_NOT_PRIME = -1,      /* p or q fails deterministic Miller-Rabin */
+  RSAPRNG_E_EQUAL_PRIMES = -2,   /* p == q */
+  RSAPRNG_E_PRIME_RANGE = -3,    /* p or q outside [2^31, 2^32) */
+  RSAPRNG_E_BAD_EXPONENT = -4,   /* e == 0 or gcd(e, lambda(n)) != 1 (covers even e) */
+  RSAPRNG_E_BAD_SEED = -5,       /* create_ex: m0 >= n, or s0 not in [1, Q-1] */
+  RSAPRNG_E_RANGE = -6,          /* k0 + count > 2^64, or a launch larger than 2^32 tiles */
+  RSAPRNG_E_NULL = -7,           /* required pointer is NULL */
+  RSAPRNG_E_ALIGN = -8,          /* device pointer not 8-byte aligned */
+  RSAPRNG_E_OOM = -9,            /* device or host allocation failed */
+  RSAPRNG_E_HIP = -10,           /* a HIP runtime call failed */
+  RSAPRNG_E_BUSY = -11,          /* server: arena full or queue full */
+  RSAPRNG_E_ARG = -12,           /* other invalid argument */
+  RSAPRNG_E_DEVICE = -13,        /* a kernel reported an error (bounded wait expired) */
+  RSAPRNG_E_NO_DEVICE = -14      /* no usable gfx950 device */
+};
+
+/* ---------------------------------------------------------------------------
+ * Instance parameters (host only; no device needed).
+ * rsaprng_params_init validates (p, q, e) by the paper's rules -- both 32-bit
+ * primes by deterministic Miller-Rabin (five bases below 2^32, Implementation
+ * section), p != q, gcd(e, lambda(n)) = 1 so the decryption exponent exists
+ * (Number Theory, eq. RSAd) -- and fills the per-instance constants the
+ * kernels use.  Returns a status; *out is written only on success.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t n;        /* p q */
+  uint64_t m0;       /* message seed, < n */
+  uint64_t s0;       /* skip seed, in [1, Q-1] */
+  uint64_t ce;       /* R^e mod n, R = 2^64 (Montgomery correction) */
+  uint32_t ninv;     /* -n^-1 mod 2^32 */
+  uint32_t e, p, q;
+  double nd;         /* RN(n) */
+  double pd, qd;     /* p, q */
+  double pinv, qinv; /* RN(1/p), RN(1/q) */
+  double qinvp;      /* q^-1 mod p (Garner's constant, Number Theory section) */
+  double kp, kq;     /* 2^32 mod p, 2^32 mod q */
+  uint64_t reserved[2];
+} rsaprng_params;    /* 128 bytes; the device-side instance record */
+
+int rsaprng_params_init(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
+                        rsaprng_params* out);
+
+/* Deterministic Miller-Rabin for any 64-bit n (twelve bases), as the library
+ * uses it for validation.  Host only. */
+int rsaprng_is_prime(uint64_t n);
+
+/* s0 * a^k mod Q and the block seed (s_1 + ... + s_{bB}) mod Q, B = 2^20, as
+ * the host library computes them (eqs. congruentialgenerator1, pseudoskip).
+ * Host only; exposed for tests. */
+uint64_t rsaprng_skip_at(uint64_t s0, uint64_t k);
+uint64_t rsaprng_block_seed(uint64_t s0, uint64_t b);
+
+/* ---------------------------------------------------------------------------
+ * Single instances.
+ * rsaprng_create: m0 = seed mod n, s0 = 1.  rsaprng_create_ex sets both.
+ * Return NULL on error; rsaprng_last_error() (thread-local) gives the status.
+ * rsaprng_destroy: the caller must have synchronised streams that use h.
+ * ------------------------------------------------------------------------ */
+typedef struct rsaprng_s* rsaprng_t;
+rsaprng_t rsaprng_create(uint64_t p, uint64_t q, uint64_t e, uint64_t seed);
+rsaprng_t rsaprng_create_ex(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0);
+int rsaprng_last_error(void);
+const char* rsaprng_strerror(int code);
+void rsaprng_destroy(rsaprng_t h);
+int rsaprng_get_params(rsaprng_t h, rsaprng_params* out);
+
+/* out_u64[j] = c_{k0+j}, out_f64[j] = r_{k0+j} for j < count (eqs. encrypt2
+ * and CodeFloatingPointStep).  count == 0 is a no-op.  k0 + count <= 2^64. */
+int rsaprng_generate(rsaprng_t h, uint64_t k0, uint64_t count, uint64_t* out_u64,
+                     double* out_f64, void* stream);
+
+/* Many instances in one launch: request i writes c_{k0+j}, r_{k0+j} of reqs[i].h
+ * to out_u64[out_off + j], out_f64[out_off + j].  reqs is a host array. */
+typedef struct {
+  rsaprng_t h;
+  uint64_t k0, count, out_off;
+} rsaprng_req;
+int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u64,
+                           double* out_f64, void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Fused consume (statistics instead of stores).
+ * Over k in [k0, k0+count): the exact sum of r_k as a 192-bit fixed-point
+ * number with LSB 2^-128 (every r_k is a multiple of 2^-116, so the sum is
+ * exact and independent of order), the count of r_k < 0.5, and the 1024-bin
+ * histogram hist[floor(1024 r_k)] -- the paper's one-dimensional frequency
+ * and half-split statistics (Tests section).  *out is a DEVICE record; it is
+ * overwritten (not accumulated).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+  uint64_t sum_fx[3];   /* normalised exact sum, little-endian limbs, LSB 2^-128 */
+  uint64_t lt_half;     /* number of r_k < 0.5 */
+  uint64_t count;       /* number of outputs reduced */
+  double sum;           /* the exact sum rounded once to binary64 */
+  uint64_t acc32[6];    /* internal: sum * 2^128 = sum_i acc32[i] 2^(32 i) */
+  uint64_t hist[1024];
+} rsaprng_stats;
+int rsaprng_consume(rsaprng_t h, uint64_t k0, uint64_t count, rsaprng_stats* out_dev,
+                    void* stream);
+
+/* ---------------------------------------------------------------------------
+ * Pools: device-resident tables of many instances (the paper's
+ * parameterisation, one modulus per stream: Parallelization section).
+ * seed[i] gives m0 = seed mod n; s0 may be NULL (all 1).  On error returns NULL
+ * and sets rsaprng_last_error(); err_index (may be NULL) receives the first
+ * bad instance.
+ * ------------------------------------------------------------------------ */
+typedef struct rsaprng_pool_s* rsaprng_pool_t;
+rsaprng_pool_t rsaprng_pool_create(size_t n, const uint64_t* p, const uint64_t* q,
+                                   const uint64_t* e, const uint64_t* seed, const uint64_t* s0,
+                                   size_t* err_index);
+void rsaprng_pool_destroy(rsaprng_pool_t pool);
+size_t rsaprng_pool_size(rsaprng_pool_t pool);
+
+typedef struct {
+  uint32_t inst;        /* pool index */
+  uint32_t reserved;
+  uint64_t k0, count;
+  uint64_t out_off;     /* generate: output element offset; consume: stats record index */
+} rsaprng_pool_req;
+
+/* Kernel configuration.  Outputs never depend on it. */
+typedef struct {
+  int variant;          /* 0 auto, 1 Montgomery-64 integer path, 2 CRT with binary64 residues */
+  int lanes_per_tile;   /* work-group size: 0 default, else 128 or 256 */
+  int per_lane;         /* outputs per lane: 0 default, else 8 or 16 */
+  int persistent;       /* 1: grid of resident work-groups looping over an atomic tile queue */
+  int wg_per_cu;        /* persistent grid size per compute unit (0 = default) */
+  int order;            /* 0 request order, 1 longest-first by exponent cost */
+} rsaprng_config;
+
+/* One-shot batched launches over a pool (reqs is a host array). */
+int rsaprng_pool_generate(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
+                          uint64_t* out_u64, double* out_f64, const rsaprng_config* cfg,
+                          void* stream);
+int rsaprng_pool_consume(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
+                         rsaprng_stats* stats_dev, const rsaprng_config* cfg, void* stream);
+
+/* Prepared batches: the request table and tile plan are uploaded once and the
+ * launch (queue reset + persistent kernel) is captured in a hipGraph on the
+ * given stream; rsaprng_batch_run replays it.  Outputs go to the buffers given
+ * at creation.  mode 0 = generate (out_u64/out_f64), 1 = consume (stats_dev). */
+typedef struct rsaprng_batch_s* rsaprng_batch_t;
+int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
+                         uint64_t* out_u64, double* out_f64, rsaprng_stats* stats_dev,
+                         const rsaprng_config* cfg, void* stream, rsaprng_batch_t* out);
+int rsaprng_batch_run(rsaprng_batch_t b, void* stream);
+/* RSAPRNG_E_DEVICE if a replay flagged an error since the last call (the caller
+ * must have synchronised the stream of the replays), else RSAPRNG_OK. */
+int rsaprng_batch_check(rsaprng_batch_t b);
+void rsaprng_batch_destroy(rsaprng_batch_t b);
+
+/* Autotuner: times every kernel configuration in its search space on this
+ * request set, checks that all of them produce byte-identical outputs, and
+ * writes the fastest to *best (and its time per launch in ms to *best_ms).
+ * If cache_path is non-NULL the result is stored there (JSON lines keyed by a
+ * workload signature) and reused on the next call with the same signature. */
+int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
+                     uint64_t* out_u64, double* out_f64, rsaprng_stats* stats_dev,
+                     const char* cache_path, void* stream, rsaprng_config* best, double* best_ms);
+
+/* ---------------------------------------------------------------------------
+ * Server: continuous batching over a pool kept resident on the device.
+ * Requests are admitted while the output arena (arena_bytes of device memory
+ * owned by the server) has room for 16 * count bytes; every iteration launches
+ * one batch over the next tiles of all admitted requests, so requests that
+ * arrive while others run join at the next iteration.  Completed requests'
+ * outputs stay in the arena until released.  A background thread drives the
+ * loop; submit/poll/release are thread-safe.
+ * ------------------------------------------------------------------------ */
+typedef struct rsaprng_server_s* rsaprng_server_t;
+typedef struct {
+  size_t arena_bytes;         /* device output arena */
+  uint64_t iter_outputs;      /* max outputs per iteration (0 = default 2^26) */
+  uint64_t chunk_outputs;     /* max outputs of one request per iteration (0 = default 2^22) */
+  size_t max_queue;           /* max waiting requests (0 = 1<<20) */
+  rsaprng_config cfg;
+} rsaprng_server_opts;
+typedef struct {
+  uint64_t tag;
+  const uint64_t* c;          /* device pointers into the arena */
+  const double* r;
+  uint64_t count;
+  double t_submit, t_admit, t_done;   /* seconds on the server's monotonic clock */
+} rsaprng_completion;
+int rsaprng_server_create(rsaprng_pool_t pool, const rsaprng_server_opts* opts,
+                          rsaprng_server_t* out);
+int rsaprng_server_submit(rsaprng_server_t s, uint32_t inst, uint64_t k0, uint64_t count,
+                          uint64_t tag);
+/* Returns the number of completions written (>= 0) or a status. */
+int rsaprng_server_poll(rsaprng_server_t s, rsaprng_completion* out, size_t max);
+int rsaprng_server_release(rsaprng_server_t s, uint64_t tag);
+double rsaprng_server_now(rsaprng_server_t s);
+/* Iterations run, outputs produced, and requests waiting/active, for reports. */
+int rsaprng_server_stats(rsaprng_server_t s, uint64_t* iterations, uint64_t* outputs,
+                         uint64_t* waiting, uint64_t* active);
+void rsaprng_server_destroy(rsaprng_server_t s);
+
+/* ---------------------------------------------------------------------------
+ * Checks and test entry points.
+ * ------------------------------------------------------------------------ */
+/* Returns RSAPRNG_E_DEVICE if a kernel on this stream's scratch flagged an
+ * error since the last call (synchronises the stream), else RSAPRNG_OK. */
+int rsaprng_check_device_error(void* stream);
+
+/* c[i] = m[i]^e mod n (and r[i]) for any odd primes p != q below 2^32 with
+ * gcd(e, lambda) = 1, using the chosen variant's exponentiation; m, c, r are
+ * device arrays (c or r may be NULL).  For bijection checks with small primes. */
+int rsaprng_debug_encrypt(uint64_t p, uint64_t q, uint64_t e, int variant, const uint64_t* m,
+                          uint64_t* c, double* r, uint64_t count, void* stream);
+
+/* Library version string. */
+const char* rsaprng_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RSAPRNG_H */

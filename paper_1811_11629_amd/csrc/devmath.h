@@ -1,0 +1,205 @@
+// Device arithmetic for gfx950: the skip recurrence mod Q = 2^63 - 25, the
+// message update mod n, 64-bit Montgomery multiplication from 32-bit limbs,
+// and the CRT form of the exponentiation with residues held in binary64.
+//
+// On gfx950 v_mad_u64_u32, v_mul_lo_u32 and v_mul_hi_u32 issue at the full
+// VALU rate (as do binary64 fma/mul/rndne), so the 64-bit products below are
+// written as 32x32->64 multiply-adds that the compiler maps onto
+// v_mad_u64_u32; every bound on an intermediate is stated where it is formed.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rsaprng {
+
+typedef uint64_t u64;
+typedef uint32_t u32;
+
+constexpr u64 kQ = 9223372036854775783ull;  // 2^63 - 25 (Implementation section)
+constexpr u64 kA = 2307085864ull;           // skip multiplier
+constexpr u64 kMask63 = 0x7fffffffffffffffull;
+
+__device__ __forceinline__ u32 lo32(u64 x) { return (u32)x; }
+__device__ __forceinline__ u32 hi32(u64 x) { return (u32)(x >> 32); }
+__device__ __forceinline__ u64 mad32(u32 a, u32 b, u64 c) { return (u64)a * b + c; }
+
+// Reduce r < 2^63 + 2^40 modulo Q, using 2^63 = 25 (mod Q): r >= Q exactly when
+// r + 25 >= 2^63, and then r - Q = (r + 25) - 2^63.
+__device__ __forceinline__ u64 reduce_q_small(u64 r) {
+  u64 r2 = r + 25;
+  return (r2 >> 63) ? (r2 & kMask63) : r;
+}
+
+// One skip step s -> a s mod Q (eq. congruentialgenerator1).  a < 2^32 and
+// s < 2^63, so a s < 2^95 = t1 2^32 + lo32(t0); splitting it as H 2^63 + L gives
+// a s = 25 H + L (mod Q) with H < 2^32.  Three full-rate v_mad_u64_u32.
+__device__ __forceinline__ u64 lcg_next(u64 s) {
+  u64 t0 = (u64)(u32)kA * lo32(s);
+  u64 t1 = mad32((u32)kA, hi32(s), hi32(t0));  // < 2^63: hi32(s) < 2^31
+  u32 H = (u32)(t1 >> 31);
+  u64 L = ((t1 & 0x7fffffffull) << 32) | lo32(t0);
+  return reduce_q_small(mad32(H, 25u, L));     // < 2^63 + 2^37
+}
+
+// Full 64x64 -> 128 product.
+__device__ __forceinline__ void mul_wide(u64 x, u64 y, u64& lo, u64& hi) {
+  u64 p00 = (u64)lo32(x) * lo32(y);
+  u64 p01 = mad32(lo32(x), hi32(y), hi32(p00));
+  u64 p10 = mad32(hi32(x), lo32(y), lo32(p01));
+  hi = mad32(hi32(x), hi32(y), hi32(p01)) + hi32(p10);  // x y < 2^128: no wrap
+  lo = ((u64)lo32(p10) << 32) | lo32(p00);
+}
+
+// x y mod Q for x, y < Q (jumps).  P = H 2^63 + L = 25 H + L; 25 H < 2^68 is
+// folded once more the same way.
+__device__ __forceinline__ u64 mulmod_q(u64 x, u64 y) {
+  u64 lo, hi;
+  mul_wide(x, y, lo, hi);
+  u64 H = (hi << 1) | (lo >> 63);               // < 2^63
+  u64 L = lo & kMask63;
+  u64 u0 = mad32(lo32(H), 25u, L);              // < 2^37 + 2^63
+  u64 u1 = mad32(hi32(H), 25u, hi32(u0));       // V = u1 2^32 + lo32(u0) < 2^69
+  u32 H2 = (u32)(u1 >> 31);
+  u64 L2 = ((u1 & 0x7fffffffull) << 32) | lo32(u0);
+  return reduce_q_small(mad32(H2, 25u, L2));    // < 2^63 + 2^11
+}
+
+// (x + y) mod n for x, y < n < 2^64 (the message update m_k = m_{k-1} + s_k).
+__device__ __forceinline__ u64 addmod(u64 x, u64 y, u64 n) {
+  u64 s = x + y;
+  bool carry = s < x;
+  return (carry || s >= n) ? s - n : s;
+}
+
+// A skip s < Q < 2^63 <= 2n (n >= 2^62) reduced to [0, n) with one subtraction.
+__device__ __forceinline__ u64 skip_mod_n(u64 s, u64 n) { return s >= n ? s - n : s; }
+
+// ---------------------------------------------------------------------------
+// Montgomery multiplication, R = 2^64, digit-serial REDC with 32-bit digits.
+// For odd n < 2^64 and a, b < n returns a b R^-1 mod n in [0, n).
+// The pre-subtraction value (a b + u n) / R is below 2n < 2^65, so its 65th
+// bit is carried explicitly.  Ten 32-bit multiplies (all v_mad_u64_u32 /
+// v_mul_lo_u32).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u64 mont_mul(u64 a, u64 b, u64 n, u32 ninv) {
+  const u32 a0 = lo32(a), a1 = hi32(a), b0 = lo32(b), b1 = hi32(b);
+  const u32 n0 = lo32(n), n1 = hi32(n);
+  // T = a b = th 2^64 + t1 2^32 + t0
+  u64 p00 = (u64)a0 * b0;
+  u64 p01 = mad32(a0, b1, hi32(p00));
+  u64 p10 = mad32(a1, b0, lo32(p01));
+  u64 th = mad32(a1, b1, hi32(p01)) + hi32(p10);
+  u32 t0 = lo32(p00), t1 = lo32(p10);
+  // digit 0: u = t0 (-n^-1) mod 2^32, T += u n, drop the zero digit
+  u32 u = t0 * ninv;
+  u64 q0 = mad32(u, n0, t0);                       // lo32(q0) == 0
+  u64 q1 = mad32(u, n1, (u64)t1 + hi32(q0));       // <= 2^64 - 1
+  u64 w = th + hi32(q1);
+  u32 c = w < th;                                  // bit 2^128 of T + u n
+  u32 d1 = lo32(q1);
+  // digit 1
+  u32 v = d1 * ninv;
+  u64 r0 = mad32(v, n0, d1);                       // lo32(r0) == 0
+  u64 r1 = mad32(v, n1, (u64)lo32(w) + hi32(r0));  // <= 2^64 - 1
+  u64 top = (u64)hi32(w) + hi32(r1) + ((u64)c << 32);  // result = top 2^32 + lo32(r1) < 2n
+  u64 res = (top << 32) | lo32(r1);
+  bool c65 = (top >> 32) != 0;
+  return (c65 || res >= n) ? res - n : res;
+}
+
+// Left-to-right square-and-multiply on plain (non-Montgomery) m: after the
+// ladder x = m^E R^-(E-1) mod n; one more product with ce = R^E mod n gives
+// m^E mod n.  L(E) + 1 products (Introduction: fewer than 2 log2 e).
+template <u32 E>
+__device__ __forceinline__ u64 mont_encrypt(u64 m, u64 n, u32 ninv, u64 ce) {
+  static_assert(E >= 1, "exponent");
+  u64 x = m;
+  constexpr int top = 31 - __builtin_clz(E);
+#pragma unroll
+  for (int bit = top - 1; bit >= 0; --bit) {
+    x = mont_mul(x, x, n, ninv);
+    if ((E >> bit) & 1u) x = mont_mul(x, m, n, ninv);
+  }
+  return mont_mul(x, ce, n, ninv);
+}
+
+__device__ __forceinline__ u64 mont_encrypt_rt(u64 m, u64 n, u32 ninv, u64 ce, u32 e) {
+  u64 x = m;
+  int top = 31 - __builtin_clz(e);
+  for (int bit = top - 1; bit >= 0; --bit) {
+    x = mont_mul(x, x, n, ninv);
+    if ((e >> bit) & 1u) x = mont_mul(x, m, n, ninv);
+  }
+  return mont_mul(x, ce, n, ninv);
+}
+
+// ---------------------------------------------------------------------------
+// CRT with binary64 residues (Number Theory, eqs. CRTimplementation).
+// A residue modulo a prime P < 2^32 is an integer-valued double in (-P, P).
+// fmm(x, y): with |x|, |y| < P (or |x y| < 2^65 for Garner's product):
+//   h = RN(x y), l = x y - h exactly (fma), qt = rint(h / P) within one of
+//   round(x y / P), and h - qt P + l = x y - qt P is an integer of magnitude
+//   below P that the fma and the add produce exactly.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fmm(double x, double y, double P, double Pinv) {
+  double h = x * y;
+  double l = __fma_rn(x, y, -h);
+  double qt = __builtin_rint(h * Pinv);
+  return __fma_rn(-qt, P, h) + l;
+}
+
+// m mod P from m = mh 2^32 + ml: (mh (2^32 mod P) + ml) reduced, in (-P, P).
+__device__ __forceinline__ double residue(u64 m, double P, double Pinv, double K) {
+  double t = fmm((double)hi32(m), K, P, Pinv);
+  double t2 = t + (double)lo32(m);                // exact, |t2| < 2^33
+  double qt = __builtin_rint(t2 * Pinv);
+  return __fma_rn(-qt, P, t2);
+}
+
+template <u32 E>
+__device__ __forceinline__ double fp_pow(double x, double P, double Pinv) {
+  double y = x;
+  constexpr int top = 31 - __builtin_clz(E);
+#pragma unroll
+  for (int bit = top - 1; bit >= 0; --bit) {
+    y = fmm(y, y, P, Pinv);
+    if ((E >> bit) & 1u) y = fmm(y, x, P, Pinv);
+  }
+  return y;
+}
+
+__device__ __forceinline__ double fp_pow_rt(double x, double P, double Pinv, u32 e) {
+  double y = x;
+  int top = 31 - __builtin_clz(e);
+  for (int bit = top - 1; bit >= 0; --bit) {
+    y = fmm(y, y, P, Pinv);
+    if ((e >> bit) & 1u) y = fmm(y, x, P, Pinv);
+  }
+  return y;
+}
+
+// Garner's recombination c = ((c_p - c_q) q^-1 mod p) q + c_q.  Returns the
+// integer c and RN(c) (one rounding of t q + c_q by the fma).
+__device__ __forceinline__ u64 garner(double cp, double cq, double pd, double qd, double pinv,
+                                      double qinvp, u32 q, double& cd) {
+  double cqn = cq < 0.0 ? cq + qd : cq;            // [0, q)
+  double d = cp - cqn;                             // exact, |d| < 2^33
+  double t = fmm(d, qinvp, pd, pinv);              // (-p, p)
+  t = t < 0.0 ? t + pd : t;                        // [0, p)
+  cd = __fma_rn(t, qd, cqn);
+  return mad32((u32)t, q, (u64)(u32)cqn);
+}
+
+// RN(c) for a 64-bit integer: both halves are exact doubles and the fma rounds
+// hi 2^32 + lo once.
+__device__ __forceinline__ double u64_to_f64_rn(u64 c) {
+  return __fma_rn((double)hi32(c), 4294967296.0, (double)lo32(c));
+}
+
+// r = RN(RN(c) / RN(n)) with the guard against 1.0 (eq. CodeFloatingPointStep).
+__device__ __forceinline__ double ratio(double cd, double nd) {
+  double r = cd / nd;
+  return r == 1.0 ? 0x1.fffffffffffffp-1 : r;
+}
+
+}  // namespace rsaprng

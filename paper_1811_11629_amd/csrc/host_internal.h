@@ -1,0 +1,66 @@
+// Host-library internals shared by host.cpp and server.cpp.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace rsaprng {
+
+typedef unsigned long long u64h;
+
+void set_last_error(int e);
+bool h_is_prime(u64h n);
+u64h h_mulmod(u64h a, u64h b, u64h m);
+u64h h_powmod(u64h b, u64h e, u64h m);
+u64h h_skip_at(u64h s0, u64h k);
+u64h h_block_seed(u64h s0, u64h b);
+int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng_params* out);
+
+struct Device;
+int device_get(Device** out);
+
+// Launch scratch (see host.cpp).
+struct Scratch {
+  struct Slot {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t ev = nullptr;
+  };
+  DevCtl* ctl = nullptr;
+  uint64_t* lb = nullptr;
+  u64h lb_tiles = 0;
+  std::vector<Slot> slots = std::vector<Slot>(4);
+  int next_slot = 0;
+  ~Scratch();
+  int init();
+  int ensure_tiles(u64h ntiles, void* stream);
+  int upload(const void* data, size_t bytes, void* stream, void** dev_out, int* slot_out);
+  int mark(int slot, void* stream);
+};
+int scratch_for_stream(void* stream, Scratch** out);
+
+// A request before planning.
+struct PlanIn {
+  uint32_t inst;
+  uint32_t e;
+  u64h k0, count, out_off;
+  u64h S;          // continuation scan start (flags & kReqContinue)
+  uint32_t slot;
+  uint32_t flags;
+};
+
+rsaprng_config resolve_config(const rsaprng_config* cfg);
+u64h tile_size(const rsaprng_config& c);
+int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, std::vector<Req>& out,
+                  u64h* ntiles_out);
+int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
+                   const rsaprng_params* inst, const Req* req, uint32_t nreq, u64h ntiles,
+                   uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
+                   ChainState* state, void* stream);
+const rsaprng_params* pool_dev(rsaprng_pool_t pool);
+const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i);
+
+}  // namespace rsaprng

@@ -1,0 +1,411 @@
+"""ctypes binding of librsaprng.so (argument marshalling only).
+
+Every function named ``rsaprng_*`` here calls the C function of the same name
+declared in include/rsaprng.h.  Device buffers are torch tensors on a ROCm
+device (their data_ptr() is passed through); streams are torch.cuda.Stream
+objects or raw hipStream_t integers.  Nothing is computed in Python: if the
+shared library is missing the import of a function raises, there is no
+fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from typing import Iterable, List, Optional, Sequence
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librsaprng.so")
+
+BLOCK_LOG2 = 20
+Q = 9223372036854775783
+A = 2307085864
+
+OK = 0
+STATUS = {
+    0: "RSAPRNG_OK", -1: "RSAPRNG_E_NOT_PRIME", -2: "RSAPRNG_E_EQUAL_PRIMES",
+    -3: "RSAPRNG_E_PRIME_RANGE", -4: "RSAPRNG_E_BAD_EXPONENT", -5: "RSAPRNG_E_BAD_SEED",
+    -6: "RSAPRNG_E_RANGE", -7: "RSAPRNG_E_NULL", -8: "RSAPRNG_E_ALIGN", -9: "RSAPRNG_E_OOM",
+    -10: "RSAPRNG_E_HIP", -11: "RSAPRNG_E_BUSY", -12: "RSAPRNG_E_ARG", -13: "RSAPRNG_E_DEVICE",
+    -14: "RSAPRNG_E_NO_DEVICE",
+}
+VARIANT_AUTO, VARIANT_MONT, VARIANT_CRT = 0, 1, 2
+MODE_GENERATE, MODE_CONSUME = 0, 1
+
+
+class RsaprngError(RuntimeError):
+    def __init__(self, code: int, what: str = ""):
+        self.code = code
+        super().__init__("%s: %s (%d)" % (what, STATUS.get(code, "?"), code))
+
+
+class rsaprng_params(C.Structure):
+    _fields_ = [("n", C.c_uint64), ("m0", C.c_uint64), ("s0", C.c_uint64), ("ce", C.c_uint64),
+                ("ninv", C.c_uint32), ("e", C.c_uint32), ("p", C.c_uint32), ("q", C.c_uint32),
+                ("nd", C.c_double), ("pd", C.c_double), ("qd", C.c_double),
+                ("pinv", C.c_double), ("qinv", C.c_double), ("qinvp", C.c_double),
+                ("kp", C.c_double), ("kq", C.c_double), ("reserved", C.c_uint64 * 2)]
+
+
+class rsaprng_req(C.Structure):
+    _fields_ = [("h", C.c_void_p), ("k0", C.c_uint64), ("count", C.c_uint64),
+                ("out_off", C.c_uint64)]
+
+
+class rsaprng_pool_req(C.Structure):
+    _fields_ = [("inst", C.c_uint32), ("reserved", C.c_uint32), ("k0", C.c_uint64),
+                ("count", C.c_uint64), ("out_off", C.c_uint64)]
+
+
+class rsaprng_config(C.Structure):
+    _fields_ = [("variant", C.c_int), ("lanes_per_tile", C.c_int), ("per_lane", C.c_int),
+                ("persistent", C.c_int), ("wg_per_cu", C.c_int), ("order", C.c_int)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+class rsaprng_server_opts(C.Structure):
+    _fields_ = [("arena_bytes", C.c_size_t), ("iter_outputs", C.c_uint64),
+                ("chunk_outputs", C.c_uint64), ("max_queue", C.c_size_t),
+                ("cfg", rsaprng_config)]
+
+
+class rsaprng_completion(C.Structure):
+    _fields_ = [("tag", C.c_uint64), ("c", C.c_void_p), ("r", C.c_void_p), ("count", C.c_uint64),
+                ("t_submit", C.c_double), ("t_admit", C.c_double), ("t_done", C.c_double)]
+
+
+STATS_WORDS = 3 + 1 + 1 + 1 + 6 + 1024   # uint64 words of rsaprng_stats
+STATS_BYTES = STATS_WORDS * 8
+
+_lock = threading.Lock()
+_lib = None
+
+_u64, _u32, _i32, _dbl, _sz, _vp = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_size_t, C.c_void_p
+_SIGS = {
+    "rsaprng_params_init": (_i32, [_u64, _u64, _u64, _u64, _u64, C.POINTER(rsaprng_params)]),
+    "rsaprng_is_prime": (_i32, [_u64]),
+    "rsaprng_skip_at": (_u64, [_u64, _u64]),
+    "rsaprng_block_seed": (_u64, [_u64, _u64]),
+    "rsaprng_create": (_vp, [_u64, _u64, _u64, _u64]),
+    "rsaprng_create_ex": (_vp, [_u64, _u64, _u64, _u64, _u64]),
+    "rsaprng_last_error": (_i32, []),
+    "rsaprng_strerror": (C.c_char_p, [_i32]),
+    "rsaprng_destroy": (None, [_vp]),
+    "rsaprng_get_params": (_i32, [_vp, C.POINTER(rsaprng_params)]),
+    "rsaprng_generate": (_i32, [_vp, _u64, _u64, _vp, _vp, _vp]),
+    "rsaprng_generate_batch": (_i32, [C.POINTER(rsaprng_req), _sz, _vp, _vp, _vp]),
+    "rsaprng_consume": (_i32, [_vp, _u64, _u64, _vp, _vp]),
+    "rsaprng_pool_create": (_vp, [_sz, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
+                                  C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_sz)]),
+    "rsaprng_pool_destroy": (None, [_vp]),
+    "rsaprng_pool_size": (_sz, [_vp]),
+    "rsaprng_pool_generate": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp, _vp,
+                                     C.POINTER(rsaprng_config), _vp]),
+    "rsaprng_pool_consume": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp,
+                                    C.POINTER(rsaprng_config), _vp]),
+    "rsaprng_batch_create": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _i32, _vp, _vp, _vp,
+                                    C.POINTER(rsaprng_config), _vp, C.POINTER(_vp)]),
+    "rsaprng_batch_run": (_i32, [_vp, _vp]),
+    "rsaprng_batch_check": (_i32, [_vp]),
+    "rsaprng_batch_destroy": (None, [_vp]),
+    "rsaprng_autotune": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _i32, _vp, _vp, _vp,
+                                C.c_char_p, _vp, C.POINTER(rsaprng_config), C.POINTER(_dbl)]),
+    "rsaprng_server_create": (_i32, [_vp, C.POINTER(rsaprng_server_opts), C.POINTER(_vp)]),
+    "rsaprng_server_submit": (_i32, [_vp, _u32, _u64, _u64, _u64]),
+    "rsaprng_server_poll": (_i32, [_vp, C.POINTER(rsaprng_completion), _sz]),
+    "rsaprng_server_release": (_i32, [_vp, _u64]),
+    "rsaprng_server_now": (_dbl, [_vp]),
+    "rsaprng_server_stats": (_i32, [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
+                                    C.POINTER(_u64)]),
+    "rsaprng_server_destroy": (None, [_vp]),
+    "rsaprng_check_device_error": (_i32, [_vp]),
+    "rsaprng_debug_encrypt": (_i32, [_u64, _u64, _u64, _i32, _vp, _vp, _vp, _u64, _vp]),
+    "rsaprng_version": (C.c_char_p, []),
+}
+
+
+def lib():
+    """Load librsaprng.so; raises if it has not been built (no fallback)."""
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise ImportError("librsaprng.so not built: run __graft_entry__.build() "
+                                  "or python paper_1811_11629_amd/build.py")
+            L = C.CDLL(LIB_PATH)
+            for name, (res, args) in _SIGS.items():
+                f = getattr(L, name)
+                f.restype = res
+                f.argtypes = args
+            _lib = L
+    return _lib
+
+
+def _check(rc: int, what: str) -> None:
+    if rc != OK:
+        raise RsaprngError(rc, what)
+
+
+def _ptr(t) -> Optional[int]:
+    """Device pointer of a torch tensor (or None / an int passed through)."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _stream(s) -> Optional[int]:
+    if s is None:
+        try:
+            import torch
+            return torch.cuda.current_stream().cuda_stream
+        except Exception:
+            return None
+    if isinstance(s, int):
+        return s
+    return s.cuda_stream
+
+
+def _u64arr(vals: Sequence[int]):
+    arr = (C.c_uint64 * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def config(variant=0, lanes_per_tile=0, per_lane=0, persistent=0, wg_per_cu=0, order=0):
+    return rsaprng_config(variant, lanes_per_tile, per_lane, persistent, wg_per_cu, order)
+
+
+# --------------------------------------------------------------------------
+# functions with the C names
+# --------------------------------------------------------------------------
+
+def rsaprng_params_init(p, q, e, m0, s0=1) -> rsaprng_params:
+    out = rsaprng_params()
+    _check(lib().rsaprng_params_init(p, q, e, m0, s0, C.byref(out)), "rsaprng_params_init")
+    return out
+
+
+def rsaprng_is_prime(n: int) -> bool:
+    return bool(lib().rsaprng_is_prime(n))
+
+
+def rsaprng_skip_at(s0: int, k: int) -> int:
+    return lib().rsaprng_skip_at(s0, k)
+
+
+def rsaprng_block_seed(s0: int, b: int) -> int:
+    return lib().rsaprng_block_seed(s0, b)
+
+
+def rsaprng_strerror(code: int) -> str:
+    return lib().rsaprng_strerror(code).decode()
+
+
+def rsaprng_version() -> str:
+    return lib().rsaprng_version().decode()
+
+
+class Generator:
+    """An rsaprng_t handle (one instance)."""
+
+    def __init__(self, handle: int):
+        self.h = handle
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rsaprng_destroy(self.h)
+            self.h = None
+
+    @property
+    def params(self) -> rsaprng_params:
+        out = rsaprng_params()
+        _check(lib().rsaprng_get_params(self.h, C.byref(out)), "rsaprng_get_params")
+        return out
+
+
+def rsaprng_create(p, q, e, seed) -> Generator:
+    h = lib().rsaprng_create(p, q, e, seed)
+    if not h:
+        raise RsaprngError(lib().rsaprng_last_error(), "rsaprng_create")
+    return Generator(h)
+
+
+def rsaprng_create_ex(p, q, e, m0, s0=1) -> Generator:
+    h = lib().rsaprng_create_ex(p, q, e, m0, s0)
+    if not h:
+        raise RsaprngError(lib().rsaprng_last_error(), "rsaprng_create_ex")
+    return Generator(h)
+
+
+def rsaprng_generate(gen: Generator, k0: int, count: int, out_u64=None, out_f64=None,
+                     stream=None) -> None:
+    _check(lib().rsaprng_generate(gen.h, k0, count, _ptr(out_u64), _ptr(out_f64), _stream(stream)),
+           "rsaprng_generate")
+
+
+def rsaprng_generate_batch(reqs: Sequence, out_u64=None, out_f64=None, stream=None) -> None:
+    """reqs: sequence of (Generator, k0, count, out_off)."""
+    arr = (rsaprng_req * len(reqs))(*[rsaprng_req(g.h, k0, cnt, off) for g, k0, cnt, off in reqs])
+    _check(lib().rsaprng_generate_batch(arr, len(reqs), _ptr(out_u64), _ptr(out_f64),
+                                        _stream(stream)), "rsaprng_generate_batch")
+
+
+def rsaprng_consume(gen: Generator, k0: int, count: int, stats, stream=None) -> None:
+    _check(lib().rsaprng_consume(gen.h, k0, count, _ptr(stats), _stream(stream)), "rsaprng_consume")
+
+
+def rsaprng_check_device_error(stream=None) -> None:
+    _check(lib().rsaprng_check_device_error(_stream(stream)), "rsaprng_check_device_error")
+
+
+def rsaprng_debug_encrypt(p, q, e, variant, m, c=None, r=None, stream=None) -> None:
+    _check(lib().rsaprng_debug_encrypt(p, q, e, variant, _ptr(m), _ptr(c), _ptr(r), m.numel(),
+                                       _stream(stream)), "rsaprng_debug_encrypt")
+
+
+class Pool:
+    """An rsaprng_pool_t: a device-resident table of instances."""
+
+    def __init__(self, p: Sequence[int], q: Sequence[int], e: Sequence[int], seed: Sequence[int],
+                 s0: Optional[Sequence[int]] = None):
+        n = len(p)
+        err = C.c_size_t(0)
+        h = lib().rsaprng_pool_create(n, _u64arr(p), _u64arr(q), _u64arr(e), _u64arr(seed),
+                                      _u64arr(s0) if s0 is not None else None, C.byref(err))
+        if not h:
+            raise RsaprngError(lib().rsaprng_last_error(), "rsaprng_pool_create[%d]" % err.value)
+        self.h = h
+        self.size = n
+
+    @classmethod
+    def from_instances(cls, insts) -> "Pool":
+        return cls([i.p for i in insts], [i.q for i in insts], [i.e for i in insts],
+                   [i.m0 for i in insts], [i.s0 for i in insts])
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rsaprng_pool_destroy(self.h)
+            self.h = None
+
+
+def pool_reqs(reqs: Iterable) -> "C.Array":
+    """(inst, k0, count, out_off) tuples -> rsaprng_pool_req array."""
+    reqs = list(reqs)
+    return (rsaprng_pool_req * len(reqs))(*[rsaprng_pool_req(i, 0, k0, c, o) for i, k0, c, o in reqs])
+
+
+def rsaprng_pool_generate(pool: Pool, reqs, out_u64=None, out_f64=None, cfg=None, stream=None):
+    arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
+    _check(lib().rsaprng_pool_generate(pool.h, arr, len(arr), _ptr(out_u64), _ptr(out_f64),
+                                       C.byref(cfg) if cfg is not None else None, _stream(stream)),
+           "rsaprng_pool_generate")
+
+
+def rsaprng_pool_consume(pool: Pool, reqs, stats, cfg=None, stream=None):
+    arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
+    _check(lib().rsaprng_pool_consume(pool.h, arr, len(arr), _ptr(stats),
+                                      C.byref(cfg) if cfg is not None else None, _stream(stream)),
+           "rsaprng_pool_consume")
+
+
+class Batch:
+    """An rsaprng_batch_t: a prepared, graph-captured launch."""
+
+    def __init__(self, pool: Pool, reqs, mode=MODE_GENERATE, out_u64=None, out_f64=None,
+                 stats=None, cfg=None, stream=None):
+        arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
+        h = C.c_void_p()
+        _check(lib().rsaprng_batch_create(pool.h, arr, len(arr), mode, _ptr(out_u64), _ptr(out_f64),
+                                          _ptr(stats), C.byref(cfg) if cfg is not None else None,
+                                          _stream(stream), C.byref(h)), "rsaprng_batch_create")
+        self.h = h.value
+        self.pool = pool          # keep the pool alive
+        self._keep = (out_u64, out_f64, stats)
+
+    def run(self, stream=None):
+        _check(lib().rsaprng_batch_run(self.h, _stream(stream)), "rsaprng_batch_run")
+
+    def check(self):
+        _check(lib().rsaprng_batch_check(self.h), "rsaprng_batch_check")
+
+    def __del__(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rsaprng_batch_destroy(self.h)
+            self.h = None
+
+
+def rsaprng_autotune(pool: Pool, reqs, mode=MODE_GENERATE, out_u64=None, out_f64=None, stats=None,
+                     cache_path: Optional[str] = None, stream=None):
+    arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
+    best = rsaprng_config()
+    ms = C.c_double(0)
+    _check(lib().rsaprng_autotune(pool.h, arr, len(arr), mode, _ptr(out_u64), _ptr(out_f64),
+                                  _ptr(stats), cache_path.encode() if cache_path else None,
+                                  _stream(stream), C.byref(best), C.byref(ms)), "rsaprng_autotune")
+    return best, ms.value
+
+
+def stats_tensor(n: int, device="cuda"):
+    import torch
+    return torch.zeros((n, STATS_WORDS), dtype=torch.int64, device=device)
+
+
+def stats_decode(t) -> List[dict]:
+    """Host copy of rsaprng_stats records -> dicts (sum_fx as a Python int)."""
+    import numpy as np
+    a = t.detach().cpu().numpy().view(np.uint64).reshape(-1, STATS_WORDS)
+    out = []
+    for row in a:
+        fx = int(row[0]) | (int(row[1]) << 64) | (int(row[2]) << 128)
+        out.append({"sum_fx": fx, "lt_half": int(row[3]), "count": int(row[4]),
+                    "sum": float(row[5:6].view(np.float64)[0]),
+                    "hist": row[12:12 + 1024].copy()})
+    return out
+
+
+class Server:
+    """An rsaprng_server_t (continuous batching over a pool)."""
+
+    def __init__(self, pool: Pool, arena_bytes: int, iter_outputs=0, chunk_outputs=0, max_queue=0,
+                 cfg=None):
+        opts = rsaprng_server_opts(arena_bytes, iter_outputs, chunk_outputs, max_queue,
+                                   cfg if cfg is not None else rsaprng_config())
+        h = C.c_void_p()
+        _check(lib().rsaprng_server_create(pool.h, C.byref(opts), C.byref(h)),
+               "rsaprng_server_create")
+        self.h = h.value
+        self.pool = pool
+
+    def submit(self, inst: int, k0: int, count: int, tag: int) -> int:
+        return lib().rsaprng_server_submit(self.h, inst, k0, count, tag)
+
+    def poll(self, max_n: int = 1024) -> List[rsaprng_completion]:
+        buf = (rsaprng_completion * max_n)()
+        n = lib().rsaprng_server_poll(self.h, buf, max_n)
+        if n < 0:
+            raise RsaprngError(n, "rsaprng_server_poll")
+        return [buf[i] for i in range(n)]
+
+    def release(self, tag: int) -> None:
+        _check(lib().rsaprng_server_release(self.h, tag), "rsaprng_server_release")
+
+    def now(self) -> float:
+        return lib().rsaprng_server_now(self.h)
+
+    def stats(self):
+        it, outs, w, a = C.c_uint64(), C.c_uint64(), C.c_uint64(), C.c_uint64()
+        _check(lib().rsaprng_server_stats(self.h, C.byref(it), C.byref(outs), C.byref(w),
+                                          C.byref(a)), "rsaprng_server_stats")
+        return {"iterations": it.value, "outputs": outs.value, "waiting": w.value,
+                "active": a.value}
+
+    def close(self):
+        if getattr(self, "h", None) and _lib is not None:
+            _lib.rsaprng_server_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,270 @@
+"""GPU parity: the HIP path (called through the C ABI) against the CPU oracle.
+
+Every comparison is bit-exact: c_k as integers and r_k as IEEE bit patterns.
+Each case logs its name before touching the GPU.
+"""
+import math
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from tests.gpu_helpers import (assert_same, dev_f64, dev_u64, host_f64, host_u64, log, oracle_gen,
+                               oracle_stats)
+
+pytestmark = pytest.mark.gpu
+
+B = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    from paper_1811_11629_amd import rsaprng
+    assert torch.cuda.is_available()
+    rsaprng.lib()
+    return rsaprng
+
+
+def _variants(R):
+    return [(R.VARIANT_MONT, "mont64"), (R.VARIANT_CRT, "crt-fp64")]
+
+
+def _gen_pool(R, insts, ranges, cfg):
+    """Generate through a pool: ranges = [(inst_index, k0, count)] packed back to back."""
+    total = sum(c for _, _, c in ranges)
+    oc, orr = dev_u64(total), dev_f64(total)
+    reqs, off = [], 0
+    for i, k0, c in ranges:
+        reqs.append((i, k0, c, off))
+        off += c
+    pool = R.Pool.from_instances(insts)
+    R.rsaprng_pool_generate(pool, reqs, oc, orr, cfg=cfg)
+    R.rsaprng_check_device_error()
+    return host_u64(oc, total), host_f64(orr, total), reqs
+
+
+def _check_ranges(insts, ranges, c, r, what):
+    off = 0
+    for i, k0, cnt in ranges:
+        cref, rref = oracle_gen(insts[i], k0, cnt)
+        assert_same(c[off:off + cnt], r[off:off + cnt], cref, rref, "%s inst %d k0 %d" % (what, i, k0))
+        off += cnt
+
+
+def test_config1_full_block(R):
+    inst = inputs.config1()
+    log("config1 full block 2^20 via rsaprng_generate", inst)
+    g = R.rsaprng_create(inst.p, inst.q, inst.e, inst.m0)
+    oc, orr = dev_u64(B), dev_f64(B)
+    R.rsaprng_generate(g, 0, B, oc, orr)
+    R.rsaprng_check_device_error()
+    cref, rref = oracle_gen(inst, 0, B)
+    assert_same(host_u64(oc), host_f64(orr), cref, rref, "config1")
+
+
+@pytest.mark.parametrize("k0,count", [
+    (0, 1), (1, 1), (4095, 2), (4096, 4096), (B - 5, 10), (3 * B + 7, 3 * 4096 + 5),
+    (B - 4096 * 3 - 1, 4096 * 6 + 3), ((1 << 40) + 123, 10000), ((1 << 40) - 1, 70000),
+    ((1 << 64) - 3000, 3000), ((1 << 63) + 12345, 5000),
+])
+def test_ragged_ranges_both_variants(R, k0, count):
+    inst = inputs.config1()
+    cref, rref = oracle_gen(inst, k0, count)
+    for var, name in _variants(R):
+        for shape in ((256, 16), (256, 8), (128, 16)):
+            log("ragged", name, shape, k0, count)
+            cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1])
+            c, r, _ = _gen_pool(R, [inst], [(0, k0, count)], cfg)
+            assert_same(c, r, cref, rref, "%s %s k0=%d" % (name, shape, k0))
+
+
+def test_edge_moduli_and_cribs(R):
+    insts = inputs.edge_instances()
+    extra = []
+    for i in insts:
+        n = i.n
+        for m0 in (0, 1, n - 1, n - 2):
+            extra.append(inputs.Instance(i.p, i.q, i.e, m0))
+    allv = insts + extra
+    ranges = [(j, k0, 5000) for j in range(len(allv)) for k0 in (0, 7 * B - 100)]
+    for var, name in _variants(R):
+        log("edge moduli / cribs", name)
+        c, r, _ = _gen_pool(R, allv, ranges, R.config(variant=var))
+        _check_ranges(allv, ranges, c, r, "edge " + name)
+        # the cribs m0 = 0, 1, n - 1 encrypt to themselves at k = 0 (Pseudorandom skips)
+        for j, i in enumerate(allv):
+            if i.m0 in (0, 1, i.n - 1):
+                assert int(c[2 * j * 5000]) == i.m0
+
+
+def test_every_exponent(R):
+    base = inputs.config3(2)
+    es = [1, 3, 5, 7, 17, 257, 65537, 9, 11, 13, 101, 2 ** 31 + 11]
+    insts = []
+    for b in base:
+        for e in es:
+            lam = (b.p - 1) * (b.q - 1) // math.gcd(b.p - 1, b.q - 1)
+            if math.gcd(e, lam) == 1:
+                insts.append(inputs.Instance(b.p, b.q, e, b.m0))
+    ranges = [(j, k0, 3000) for j in range(len(insts)) for k0 in (0, 5 * B + 17)]
+    for var, name in _variants(R):
+        log("every exponent", name, len(insts))
+        c, r, _ = _gen_pool(R, insts, ranges, R.config(variant=var))
+        _check_ranges(insts, ranges, c, r, "exponents " + name)
+
+
+def test_exponent_one_is_message(R):
+    inst = inputs.config1()
+    i1 = inputs.Instance(inst.p, inst.q, 1, inst.m0)
+    log("e = 1")
+    c, r, _ = _gen_pool(R, [i1], [(0, 0, 20000), (0, 3 * B - 5000, 10000)], R.config())
+    m = np.concatenate([oracle.messages(i1.p, i1.q, i1.m0, 1, 0, 20000),
+                        oracle.messages(i1.p, i1.q, i1.m0, 1, 3 * B - 5000, 10000)])
+    assert np.array_equal(c, m)
+
+
+def test_generate_batch_handles(R):
+    insts = inputs.config2(6) + inputs.edge_instances()
+    gens = [R.rsaprng_create_ex(i.p, i.q, i.e, i.m0, 1) for i in insts]
+    ranges = [(j, (j * 7919 * 4096 + j * 13) % (1 << 36), 4096 * (j % 3) + 777 * j + 1)
+              for j in range(len(insts))]
+    total = sum(c for _, _, c in ranges)
+    oc, orr = dev_u64(total), dev_f64(total)
+    reqs, off = [], 0
+    for j, k0, cnt in ranges:
+        reqs.append((gens[j], k0, cnt, off))
+        off += cnt
+    log("rsaprng_generate_batch", len(reqs))
+    R.rsaprng_generate_batch(reqs, oc, orr)
+    R.rsaprng_check_device_error()
+    _check_ranges(insts, ranges, host_u64(oc, total), host_f64(orr, total), "generate_batch")
+
+
+def test_substreams_config2_subset_all_shapes(R):
+    # 8 instances of the multi-instance workload, each split into 256 substreams of
+    # 4096 starting at k0 = j 2^12; every kernel configuration must give the oracle's bytes.
+    insts = inputs.config2(8)
+    ranges = [(i, j * 4096, 4096) for i in range(len(insts)) for j in range(256)]
+    refs = [oracle_gen(i, 0, B) for i in insts]
+    cref = np.concatenate([x[0] for x in refs])
+    rref = np.concatenate([x[1] for x in refs])
+    from paper_1811_11629_amd import rsaprng
+    for var in (R.VARIANT_MONT, R.VARIANT_CRT):
+        for shape in ((256, 16), (256, 8), (128, 16)):
+            for pers in (0, 1):
+                log("config2 subset", var, shape, pers)
+                cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                               persistent=pers, order=pers)
+                c, r, _ = _gen_pool(R, insts, ranges, cfg)
+                assert_same(c, r, cref, rref, "config2 %s %s %s" % (var, shape, pers))
+
+
+def test_consume_matches_oracle(R):
+    import torch
+    insts = inputs.config3(3)
+    cases = []
+    for i in insts:
+        for e in (3, 17, 65537):
+            cases.append(inputs.Instance(i.p, i.q, e, i.m0))
+    ranges = [(j, k0, cnt) for j in range(len(cases))
+              for k0, cnt in ((0, 1 << 18), (B - 3000, 9000), ((1 << 40) + 5, 4097))]
+    pool = R.Pool.from_instances(cases)
+    for var, name in _variants(R):
+        log("consume", name)
+        st = R.stats_tensor(len(ranges))
+        R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx) for idx, (j, k0, cnt) in enumerate(ranges)],
+                               st, cfg=R.config(variant=var))
+        R.rsaprng_check_device_error()
+        got = R.stats_decode(st)
+        for idx, (j, k0, cnt) in enumerate(ranges):
+            ref = oracle_stats(cases[j], k0, cnt)
+            g = got[idx]
+            assert g["count"] == cnt
+            assert g["sum_fx"] == ref["sum_fx"], (name, idx)
+            assert g["lt_half"] == ref["lt_half"]
+            assert np.array_equal(g["hist"], ref["hist"])
+            # the double is the exact sum rounded once (Fraction -> float rounds correctly)
+            assert g["sum"] == float(Fraction(ref["sum_fx"], 1 << 128))
+
+
+def test_consume_single_handle(R):
+    inst = inputs.config1()
+    g = R.rsaprng_create(inst.p, inst.q, inst.e, inst.m0)
+    st = R.stats_tensor(1)
+    log("rsaprng_consume single")
+    R.rsaprng_consume(g, 12345, 300000, st)
+    R.rsaprng_check_device_error()
+    got = R.stats_decode(st)[0]
+    ref = oracle_stats(inst, 12345, 300000)
+    assert got["sum_fx"] == ref["sum_fx"] and np.array_equal(got["hist"], ref["hist"])
+    assert got["lt_half"] == ref["lt_half"] and got["count"] == 300000
+
+
+def test_graph_batch_replays(R):
+    import torch
+    insts = inputs.config2(4)
+    ranges = [(i, k0, 50000) for i in range(4) for k0 in (0, 2 * B + 33)]
+    total = sum(c for _, _, c in ranges)
+    pool = R.Pool.from_instances(insts)
+    reqs, off = [], 0
+    for i, k0, c in ranges:
+        reqs.append((i, k0, c, off))
+        off += c
+    oc, orr = dev_u64(total), dev_f64(total)
+    for var in (R.VARIANT_MONT, R.VARIANT_CRT):
+        log("graph batch", var)
+        b = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr, cfg=R.config(variant=var, persistent=1))
+        for rep in range(3):
+            oc.fill_(-1)
+            orr.fill_(-1.0)
+            torch.cuda.synchronize()
+            b.run()
+            torch.cuda.synchronize()
+            b.check()
+            _check_ranges(insts, ranges, host_u64(oc, total), host_f64(orr, total),
+                          "graph replay %d" % rep)
+            x = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
+            assert math.isfinite(x)
+
+
+def test_debug_encrypt_bijection(R):
+    import torch
+    for bits in (12, 13):
+        for inst in inputs.small_instances(500 + bits, 2, bits=bits):
+            n = inst.n
+            m = torch.arange(n, dtype=torch.int64, device="cuda")
+            for var, name in _variants(R):
+                log("bijection", bits, name, n)
+                c = torch.empty_like(m)
+                R.rsaprng_debug_encrypt(inst.p, inst.q, inst.e, var, m, c)
+                torch.cuda.synchronize()
+                srt, _ = torch.sort(c)
+                assert torch.equal(srt, m)
+                sample = np.arange(0, n, max(1, n // 5000), dtype=np.uint64)
+                ref = oracle.encrypt_array(n, inst.e, sample)
+                got = c.cpu().numpy().view(np.uint64)[sample.astype(np.int64)]
+                assert np.array_equal(got, ref)
+
+
+def test_errors(R):
+    import torch
+    inst = inputs.config1()
+    with pytest.raises(R.RsaprngError) as ei:
+        R.rsaprng_create(inst.p, inst.p, 3, 1)
+    assert ei.value.code == -2
+    with pytest.raises(R.RsaprngError) as ei:
+        R.rsaprng_create(inst.p, inst.q, 2, 1)
+    assert ei.value.code == -4
+    g = R.rsaprng_create(inst.p, inst.q, inst.e, 5)
+    buf = torch.empty(1000, dtype=torch.int64, device="cuda")
+    with pytest.raises(R.RsaprngError) as ei:
+        R.rsaprng_generate(g, 0, 10, buf.data_ptr() + 4, None)
+    assert ei.value.code == -8
+    with pytest.raises(R.RsaprngError) as ei:
+        R.rsaprng_generate(g, (1 << 64) - 5, 10, buf, None)
+    assert ei.value.code == -6
+    R.rsaprng_generate(g, 0, 0, buf, None)   # no-op
+    torch.cuda.synchronize()
