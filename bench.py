@@ -1,0 +1,335 @@
+#!/usr/bin/env python3
+"""Benchmark of the RSA-exponentiation generator on one MI355X.
+
+Headline (one "step"): the multi-instance workload -- 1024 independent seeded
+prime pairs, e = 3, each split into 256 substreams of 2^12 starting at
+k0 = j 2^12, 2^30 outputs written to HBM as uint64 c_k and binary64 r_k -- run
+as one prepared (hipGraph-captured) batch with the autotuned kernel
+configuration.  value = outputs per second of the whole step, in Gnumbers/s.
+
+Also reported (not the headline): the same work as plain per-instance
+rsaprng_generate launches round-robin over 4 streams; the exponent sweep in
+fused-consume mode (4096 instances x 2^18 outputs per e, no HBM write); the
+batched uneven workload (10,000 instances, lengths log-uniform in [2^8, 2^22],
+start indices below 2^40) as one graph-captured persistent launch, beside its
+plain per-request launches; the roofline of the tile kernel; and the CPU
+oracle timed on the host's cores on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X published HBM3E bandwidth
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-operations/s: 256 CUs x 64 lanes x 2.4 GHz
+B = 1 << 20
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_1811_11629_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        if f.endswith((".hip", ".h")):
+            with open(os.path.join(d, f), "rb") as fh:
+                h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profiles(workload: str):
+    """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
+    taken on the current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "tile_kernel_traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+    except (OSError, ValueError):
+        return None
+    ent = rec.get(workload)
+    if not ent or ent.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return ent.get("hbm_bytes_per_launch")
+
+
+def time_graph(batch, stream, steps, warmup, torch):
+    for _ in range(warmup):
+        batch.run(stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        batch.run(stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = [a.elapsed_time(b) for a, b in evs]
+    return wall, kms
+
+
+def config2_requests():
+    import inputs
+    reqs = []
+    for i in range(1024):
+        for j in range(inputs.CONFIG2_SUBSTREAMS):
+            k0 = j * inputs.CONFIG2_SUBSTREAM_LEN
+            reqs.append((i, k0, inputs.CONFIG2_SUBSTREAM_LEN, i * B + k0))
+    return reqs
+
+
+def verify_config2(insts, oc, orr, n_full=3, n_samples=48):
+    """Untimed: whole outputs of a few instances, single samples of others."""
+    import numpy as np
+
+    import oracle
+    rng = np.random.default_rng(7)
+    ok = True
+    full = rng.choice(len(insts), n_full, replace=False)
+    for i in full:
+        inst = insts[int(i)]
+        c, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, 0, B)
+        cg = oc[int(i) * B:(int(i) + 1) * B].cpu().numpy().view(np.uint64)
+        rg = orr[int(i) * B:(int(i) + 1) * B].cpu().numpy()
+        ok &= bool(np.array_equal(cg, c) and np.array_equal(rg.view(np.uint64), r.view(np.uint64)))
+    for _ in range(n_samples):
+        i = int(rng.integers(len(insts)))
+        k = int(rng.integers(B))
+        inst = insts[i]
+        c, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k, 1)
+        cg = int(oc[i * B + k].item()) & ((1 << 64) - 1)
+        rg = float(orr[i * B + k].item())
+        ok &= (cg == int(c[0]) and rg == float(r[0]))
+    return ok
+
+
+def cpu_baseline(insts, budget_outputs):
+    """The oracle, unmodified, over whole instances of the workload on the host's cores."""
+    import concurrent.futures as cf
+
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    n_inst = max(threads, budget_outputs // B)
+    sample = insts[:n_inst]
+    oracle.lib()
+
+    def one(inst):
+        oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, 0, B)
+        return B
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        done = sum(ex.map(one, sample))
+    dt = time.perf_counter() - t0
+    return {"value": done / dt / 1e9, "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
+            "sample": "%d of the 1024 multi-instance workload's instances, each k in [0, 2^20) "
+                      "(c_k and r_k), %d host threads, %.1f s wall" % (len(sample), threads, dt)}
+
+
+def run_plain_config2(R, gens, oc, orr, torch, reps=2):
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    for g in gens[:8]:
+        R.rsaprng_generate(g, 0, B, oc, orr, stream=streams[0])
+    torch.cuda.synchronize()
+    best = 1e30
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        for i, g in enumerate(gens):
+            R.rsaprng_generate(g, 0, B, oc[i * B:], orr[i * B:], stream=streams[i % 4])
+        torch.cuda.synchronize()
+        best = min(best, time.perf_counter() - t0)
+    for s in streams:
+        R.rsaprng_check_device_error(s)
+    return best
+
+
+def run_consume_sweep(R, torch, stream, steps):
+    import inputs
+    base = inputs.config3()
+    out = {}
+    st = R.stats_tensor(len(base))
+    for e in inputs.SWEEP_EXPONENTS:
+        insts = [inputs.Instance(i.p, i.q, e, i.m0) for i in base]
+        pool = R.Pool.from_instances(insts)
+        reqs = [(i, 0, 1 << 18, i) for i in range(len(insts))]
+        best, _ = R.rsaprng_autotune(pool, reqs, R.MODE_CONSUME, stats=st, stream=stream)
+        b = R.Batch(pool, reqs, R.MODE_CONSUME, stats=st, cfg=best, stream=stream)
+        wall, kms = time_graph(b, stream, max(2, steps // 4), 1, torch)
+        b.check()
+        n = len(insts) << 18
+        ms = sum(kms) / len(kms)
+        out["e%d" % e] = {"gnumbers_per_s": n / (ms / 1e3) / 1e9, "ms_per_launch": ms,
+                          "variant": int(best.variant), "config": best.as_dict()}
+        log("consume e=%d: %.1f Gnum/s (%.3f ms)" % (e, out["e%d" % e]["gnumbers_per_s"], ms))
+        del b, pool
+    return out
+
+
+def run_batched_uneven(R, torch, stream, steps):
+    import inputs
+    t0 = time.perf_counter()
+    insts, reqs4 = inputs.config4()
+    log("batched workload drawn in %.1f s" % (time.perf_counter() - t0))
+    total = sum(r.count for r in reqs4)
+    reqs, off = [], 0
+    for r in reqs4:
+        reqs.append((r.inst, r.k0, r.count, off))
+        off += r.count
+    oc = torch.empty(total, dtype=torch.int64, device="cuda")
+    orr = torch.empty(total, dtype=torch.float64, device="cuda")
+    pool = R.Pool.from_instances(insts)
+    best, _ = R.rsaprng_autotune(pool, reqs, R.MODE_GENERATE, oc, orr, stream=stream)
+    b = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr, cfg=best, stream=stream)
+    wall, kms = time_graph(b, stream, max(2, steps // 4), 1, torch)
+    b.check()
+    ms = sum(kms) / len(kms)
+    batched = total / (ms / 1e3) / 1e9
+    # plain per-request launches, round-robin over 4 streams
+    gens = [R.rsaprng_create_ex(i.p, i.q, i.e, i.m0, i.s0) for i in insts]
+    streams = [torch.cuda.Stream() for _ in range(4)]
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for j, (i, k0, cnt, o) in enumerate(reqs):
+        R.rsaprng_generate(gens[i], k0, cnt, oc[o:], orr[o:], stream=streams[j % 4])
+    torch.cuda.synchronize()
+    plain_s = time.perf_counter() - t1
+    for s in streams:
+        R.rsaprng_check_device_error(s)
+    # spot check against the oracle (untimed)
+    import numpy as np
+
+    import oracle
+    ok = True
+    rng = np.random.default_rng(11)
+    for j in rng.choice(len(reqs), 24, replace=False):
+        i, k0, cnt, o = reqs[int(j)]
+        kk = int(rng.integers(cnt))
+        inst = insts[i]
+        c, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0 + kk, 1)
+        ok &= (int(oc[o + kk].item()) & ((1 << 64) - 1)) == int(c[0])
+        ok &= float(orr[o + kk].item()) == float(r[0])
+    res = {"workload": "10000 instances, e from {3,5,7,17,257,65537}, lengths log-uniform in "
+                       "[2^8, 2^22], k0 < 2^40, %d outputs u64+f64" % total,
+           "batched_gnumbers_per_s": batched, "batched_ms": ms,
+           "plain_per_request_gnumbers_per_s": total / plain_s / 1e9,
+           "batched_vs_plain": (total / (ms / 1e3)) / (total / plain_s),
+           "config": best.as_dict(), "verified_samples": bool(ok)}
+    log("batched uneven: %.1f Gnum/s graph vs %.1f plain" % (batched, res["plain_per_request_gnumbers_per_s"]))
+    del b, oc, orr
+    torch.cuda.empty_cache()
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="headline only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--config", default="",
+                    help="fixed kernel configuration 'variant,lanes,per_lane,persistent[,prefix]' "
+                         "instead of the autotuner (variant 1 = Montgomery-64, 2 = CRT; prefix 0 "
+                         "= two passes, 1 = single pass with look-back)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the generator "
+              "shards by instance or index range with no exchange; see the design notes). "
+              "Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import inputs
+    from paper_1811_11629_amd import rsaprng as R
+
+    R.lib()
+    torch.cuda.set_device(0)
+    stream = torch.cuda.Stream()
+    insts = inputs.config2()
+    pool = R.Pool.from_instances(insts)
+    reqs = R.pool_reqs(config2_requests())
+    N = 1024 * B
+    oc = torch.empty(N, dtype=torch.int64, device="cuda")
+    orr = torch.empty(N, dtype=torch.float64, device="cuda")
+
+    if args.config:
+        f = [int(x) for x in args.config.split(",")] + [0]
+        v, lanes, per, pers, prefix = f[:5]
+        best = R.config(variant=v, lanes_per_tile=lanes, per_lane=per, persistent=pers, order=pers,
+                        prefix=prefix)
+        log("fixed config", best.as_dict())
+    else:
+        cache = os.environ.get("RSAPRNG_TUNE_CACHE")
+        log("autotuning the multi-instance workload")
+        best, best_ms = R.rsaprng_autotune(pool, reqs, R.MODE_GENERATE, oc, orr, cache_path=cache,
+                                           stream=stream)
+        log("best config", best.as_dict(), "%.3f ms" % best_ms)
+    batch = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr, cfg=best, stream=stream)
+    wall, kms = time_graph(batch, stream, args.steps, args.warmup, torch)
+    batch.check()
+    ms_step = wall / args.steps * 1e3
+    value = N / (wall / args.steps) / 1e9
+    k_ms = sum(kms) / len(kms)
+    log("multi-instance: %.3f ms/step, %.1f Gnum/s; kernel avg %.3f ms" % (ms_step, value, k_ms))
+    verified = verify_config2(insts, oc, orr)
+    log("verified against oracle:", verified)
+
+    alg_bytes = 16 * N                                      # 8 B c_k + 8 B r_k per output
+    achieved = alg_bytes / (k_ms / 1e3) / 1e9
+    traffic = traffic_from_profiles("multi_instance_e3")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "k_tiles (generate, variant %d)" % best.variant,
+                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": k_ms}
+
+    extras = {}
+    if not args.no_extras:
+        gens = [R.rsaprng_create_ex(i.p, i.q, i.e, i.m0, i.s0) for i in insts]
+        plain_s = run_plain_config2(R, gens, oc, orr, torch)
+        extras["multi_instance_plain_per_instance"] = {
+            "gnumbers_per_s": N / plain_s / 1e9, "ms": plain_s * 1e3,
+            "launches": 1024, "streams": 4}
+        extras["multi_instance_batched_vs_plain"] = (N / (wall / args.steps)) / (N / plain_s)
+        del gens
+        del batch, oc, orr
+        torch.cuda.empty_cache()
+        extras["exponent_sweep_consume"] = run_consume_sweep(R, torch, stream, args.steps)
+        extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
+
+    cpu = None if args.no_cpu else cpu_baseline(insts, 512 * B)
+    if cpu:
+        log("cpu oracle: %.3f Gnum/s on %d threads" % (cpu["value"], cpu["cores"]))
+
+    out = {
+        "metric": "Gnumbers/s (u64+FP64) and % of INT-VALU/HBM roofline; batched & served vs plain",
+        "value": value, "unit": "Gnumbers/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
+        "config": {"workload": "multi-instance: 1024 seeded prime pairs, e=3, 256 substreams of "
+                               "2^12 per instance (k0 = j*2^12), 2^30 outputs as uint64 c_k and "
+                               "binary64 r_k, one graph-captured batch",
+                   "instances": 1024, "outputs_per_step": N, "exponent": 3,
+                   "kernel_config": best.as_dict(), "parallelism": "single GPU"},
+        "roofline": roofline, "cpu_baseline": cpu, "verified": bool(verified),
+        "paper_context": "paper: >1e8 numbers/s per 24-core Xeon E5-2680 v3 node (other hardware)",
+        "kernel_source_hash": kernel_source_hash(),
+    }
+    out.update(extras)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

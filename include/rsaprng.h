@@ -86,7 +86,8 @@ typedef struct {
   double pinv, qinv; /* RN(1/p), RN(1/q) */
   double qinvp;      /* q^-1 mod p (Garner's constant, Number Theory section) */
   double kp, kq;     /* 2^32 mod p, 2^32 mod q */
-  uint64_t reserved[2];
+  double nrcp;       /* RN(1 / RN(n)) */
+  uint64_t reserved;
 } rsaprng_params;    /* 128 bytes; the device-side instance record */
 
 int rsaprng_params_init(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
@@ -176,9 +177,11 @@ typedef struct {
   int variant;          /* 0 auto, 1 Montgomery-64 integer path, 2 CRT with binary64 residues */
   int lanes_per_tile;   /* work-group size: 0 default, else 128 or 256 */
   int per_lane;         /* outputs per lane: 0 default, else 8 or 16 */
-  int persistent;       /* 1: grid of resident work-groups looping over an atomic tile queue */
+  int persistent;       /* 1: grid of resident work-groups looping over the tiles */
   int wg_per_cu;        /* persistent grid size per compute unit (0 = default) */
   int order;            /* 0 request order, 1 longest-first by exponent cost */
+  int prefix;           /* 0 two passes (tile sums, scan, generate); 1 one pass with a
+                           decoupled look-back over the preceding tiles */
 } rsaprng_config;
 
 /* One-shot batched launches over a pool (reqs is a host array). */

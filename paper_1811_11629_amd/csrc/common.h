@@ -38,9 +38,38 @@ struct alignas(16) ChainState {
   uint64_t s_at;       // s_S
 };
 
-// Per-launch scratch owned by the library (one per stream / batch / server).
+// A chain: the tiles of one request inside one 2^20 block.  Its scan starts at
+// S (a block start, or for the first chain of a continued request the index
+// whose state is in state[slot]); tiles are T-aligned from S.  The request's
+// output range [k0, last] and offset are repeated in every chain.
+struct alignas(16) Chain {
+  uint64_t S;
+  uint64_t k0;
+  uint64_t last;
+  uint64_t out_off;
+  uint32_t inst;
+  uint32_t first;      // first tile id
+  uint32_t ntiles;
+  uint32_t slot;       // chain-state slot or stats record
+  uint32_t flags;      // kChainFromState | kChainWriteEnd
+  uint32_t pad[3];
+};
+static_assert(sizeof(Chain) == 64, "Chain layout");
+
+enum ChainFlags : uint32_t {
+  kChainFromState = 1u,  // skip and message before S come from state[slot]
+  kChainWriteEnd = 2u,   // the tile holding `last` writes state[slot]
+};
+
+// Computed on the device per chain: the skip at S and the message before S.
+struct alignas(16) ChainStart {
+  uint64_t s_S;
+  uint64_t m_base;
+};
+
+// Per-launch control words owned by the library (one per stream / batch / server).
 struct DevCtl {
-  uint32_t counter;    // atomic tile queue
+  uint32_t counter;    // atomic tile queue (single-pass kernel)
   uint32_t epoch;      // tag of this launch's look-back words
   uint32_t err;        // set by a kernel whose bounded wait expired
   uint32_t pad;
@@ -48,22 +77,31 @@ struct DevCtl {
 
 enum Variant : int { kVariantAuto = 0, kVariantMont = 1, kVariantCrt = 2 };
 enum Mode : int { kModeGenerate = 0, kModeConsume = 1 };
+enum Prefix : int { kPrefixTwoPass = 0, kPrefixLookback = 1 };
 
 struct LaunchArgs {
   const rsaprng_params* inst;
-  const Req* req;
-  uint32_t nreq;
+  const Chain* chain;
+  uint32_t nchain;
   uint32_t ntiles;
+  uint32_t tile_log2;      // T = 2^tile_log2 indices per tile
+  uint32_t spin_limit;
+  uint32_t* tile_chain;    // per tile: owning chain (k_chain_setup)
+  ChainStart* cstart;      // per chain (k_chain_setup)
+  uint64_t* s_tile;        // per tile: skip at the tile start (k_sums)
+  uint64_t* agg;           // per tile: sum of its skips mod n (k_sums)
+  uint64_t* excl;          // per tile: message before the tile (k_scan)
+  uint64_t* lb;            // single pass: 4 tagged words per tile
   uint64_t* out_c;
   double* out_r;
   rsaprng_stats* stats;
   ChainState* state;
   DevCtl* ctl;
-  uint64_t* lb;        // 4 tagged words per tile
-  const uint64_t* pow2;  // a^(2^i) mod Q, i < 64
-  const uint64_t* powv;  // a^(V l) mod Q, l < lanes per tile, for this launch's V
-  uint64_t gc;           // a (a - 1)^-1 mod Q: block seed G_b = s0 gc (a^{bB} - 1)
-  uint32_t spin_limit;
+  const uint64_t* pow2;    // a^(2^i) mod Q, i < 64
+  const uint64_t* at;      // a^(j T) mod Q, j < 2^20 / T
+  const uint64_t* pl;      // a^((T/64) l) mod Q, l < 64
+  const uint64_t* powv;    // a^(V l) mod Q, l < lanes per tile
+  uint64_t gc;             // a (a - 1)^-1 mod Q: block seed G_b = s0 gc (a^{bB} - 1)
 };
 
 // Host-callable launchers (kernels.hip).
@@ -72,14 +110,19 @@ struct KernelShape {
   int wg;        // 128 or 256
   int v;         // 8 or 16
   int mode;      // kModeGenerate or kModeConsume
-  int grid;      // number of work-groups (persistent if < ntiles)
+  int prefix;    // kPrefixTwoPass or kPrefixLookback
+  int grid;      // number of work-groups (they loop if fewer than tiles)
 };
 int launch_begin(DevCtl* ctl, void* stream);
+int launch_chain_setup(const LaunchArgs& args, void* stream);
+int launch_sums(const LaunchArgs& args, void* stream);
+int launch_scan(const LaunchArgs& args, void* stream);
 int launch_tiles(const KernelShape& shape, const LaunchArgs& args, void* stream);
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_stats_finalize(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t* m, uint64_t* c,
                          double* r, uint64_t count, void* stream);
 int kernel_max_grid(const KernelShape& shape, int* wg_per_cu);
+int launch_checksum(const uint64_t* p, uint64_t n, uint64_t* out_dev, void* stream);
 
 }  // namespace rsaprng

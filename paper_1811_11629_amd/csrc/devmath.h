@@ -156,6 +156,18 @@ __device__ __forceinline__ double residue(u64 m, double P, double Pinv, double K
   return __fma_rn(-qt, P, t2);
 }
 
+// m mod P without the final reduction: h + l = mh (2^32 mod P) exactly, and
+// h - rint(h/P) P + l + ml is an integer of magnitude below 2^33.  Valid as
+// the input of a squaring (|x|^2 < 2^66 keeps every fmm step exact: h < 2^67,
+// |l| <= 2^14, |h - qt P| < P).
+__device__ __forceinline__ double residue_lazy(u64 m, double P, double Pinv, double K) {
+  const double mh = (double)hi32(m);
+  double h = mh * K;
+  double l = __fma_rn(mh, K, -h);
+  double qt = __builtin_rint(h * Pinv);
+  return (__fma_rn(-qt, P, h) + l) + (double)lo32(m);
+}
+
 template <u32 E>
 __device__ __forceinline__ double fp_pow(double x, double P, double Pinv) {
   double y = x;
@@ -197,8 +209,17 @@ __device__ __forceinline__ double u64_to_f64_rn(u64 c) {
 }
 
 // r = RN(RN(c) / RN(n)) with the guard against 1.0 (eq. CodeFloatingPointStep).
-__device__ __forceinline__ double ratio(double cd, double nd) {
-  double r = cd / nd;
+// The quotient uses y = RN(1/nd) and two corrections (Markstein):
+//   q0 = RN(cd y) lies within 1.5 ulp of cd/nd (y has relative error <= 2^-53);
+//   q1 = RN(q0 + RN(cd - q0 nd) y) lies within 1 ulp, so cd - q1 nd is exactly
+//   representable and the fma returns it exactly; with y within half an ulp of
+//   1/nd, q2 = RN(q1 + (cd - q1 nd) y) is the correctly rounded cd/nd
+//   (Markstein's theorem, IBM J. Res. Dev. 1990).  0 <= cd <= nd, no
+//   underflow or overflow is possible.
+__device__ __forceinline__ double ratio(double cd, double nd, double y) {
+  const double q0 = cd * y;
+  const double q1 = __fma_rn(__fma_rn(-q0, nd, cd), y, q0);
+  const double r = __fma_rn(__fma_rn(-q1, nd, cd), y, q1);
   return r == 1.0 ? 0x1.fffffffffffffp-1 : r;
 }
 

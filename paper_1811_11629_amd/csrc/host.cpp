@@ -136,6 +136,7 @@ int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng
   P.qinvp = (double)h_inv_prime(q % p, p);
   P.kp = (double)((1ull << 32) % p);
   P.kq = (double)((1ull << 32) % q);
+  P.nrcp = 1.0 / P.nd;
   *out = P;
   return RSAPRNG_OK;
 }
@@ -146,11 +147,33 @@ int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng
 struct Device {
   int id = -1;
   int ncu = 0;
-  uint64_t* pow2 = nullptr;   // a^(2^i) mod Q
-  uint64_t* powv8 = nullptr;  // a^(8 l) mod Q, l < 256
-  uint64_t* powv16 = nullptr; // a^(16 l) mod Q, l < 256
+  uint64_t* pow2 = nullptr;    // a^(2^i) mod Q, i < 64
+  uint64_t* powv8 = nullptr;   // a^(8 l) mod Q, l < 256
+  uint64_t* powv16 = nullptr;  // a^(16 l) mod Q, l < 256
+  uint64_t* at2048 = nullptr;  // a^(2048 j) mod Q, j < 512
+  uint64_t* at4096 = nullptr;  // a^(4096 j) mod Q, j < 256
+  uint64_t* pl2048 = nullptr;  // a^(32 l) mod Q, l < 64
+  uint64_t* pl4096 = nullptr;  // a^(64 l) mod Q, l < 64
   u64h gc = 0;
 };
+
+static int upload_table(uint64_t** dst, const std::vector<uint64_t>& v) {
+  if (hipMalloc(dst, v.size() * 8) != hipSuccess) return RSAPRNG_E_OOM;
+  if (hipMemcpy(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice) != hipSuccess)
+    return RSAPRNG_E_HIP;
+  return RSAPRNG_OK;
+}
+
+static std::vector<uint64_t> power_table(u64h step, size_t count) {
+  std::vector<uint64_t> t(count);
+  const u64h g = h_powmod(kAh, step, kQh);
+  u64h x = 1;
+  for (size_t i = 0; i < count; ++i) {
+    t[i] = x;
+    x = h_mulmod(x, g, kQh);
+  }
+  return t;
+}
 
 static std::mutex g_mu;
 static std::map<int, Device*> g_devices;
@@ -171,26 +194,23 @@ int device_get(Device** out) {
   d->id = dev;
   d->ncu = prop.multiProcessorCount;
   d->gc = h_gc();
-  std::vector<uint64_t> t2(64), t8(256), t16(256);
+  std::vector<uint64_t> t2(64);
   u64h x = kAh;
   for (int i = 0; i < 64; ++i) {
     t2[i] = x;
     x = h_mulmod(x, x, kQh);
   }
-  for (int l = 0; l < 256; ++l) {
-    t8[l] = h_powmod(kAh, 8ull * l, kQh);
-    t16[l] = h_powmod(kAh, 16ull * l, kQh);
-  }
-  if (hipMalloc(&d->pow2, 64 * 8) != hipSuccess || hipMalloc(&d->powv8, 256 * 8) != hipSuccess ||
-      hipMalloc(&d->powv16, 256 * 8) != hipSuccess) {
+  int rc = RSAPRNG_OK;
+  if (!rc) rc = upload_table(&d->pow2, t2);
+  if (!rc) rc = upload_table(&d->powv8, power_table(8, 256));
+  if (!rc) rc = upload_table(&d->powv16, power_table(16, 256));
+  if (!rc) rc = upload_table(&d->at2048, power_table(2048, kBlock / 2048));
+  if (!rc) rc = upload_table(&d->at4096, power_table(4096, kBlock / 4096));
+  if (!rc) rc = upload_table(&d->pl2048, power_table(2048 / 64, 64));
+  if (!rc) rc = upload_table(&d->pl4096, power_table(4096 / 64, 64));
+  if (rc) {
     delete d;
-    return RSAPRNG_E_OOM;
-  }
-  if (hipMemcpy(d->pow2, t2.data(), 64 * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(d->powv8, t8.data(), 256 * 8, hipMemcpyHostToDevice) != hipSuccess ||
-      hipMemcpy(d->powv16, t16.data(), 256 * 8, hipMemcpyHostToDevice) != hipSuccess) {
-    delete d;
-    return RSAPRNG_E_HIP;
+    return rc;
   }
   g_devices[dev] = d;
   *out = d;
@@ -206,6 +226,8 @@ Scratch::~Scratch() {
     if (s.dev) (void)hipFree(s.dev);
   }
   if (lb) (void)hipFree(lb);
+  if (tiles) (void)hipFree(tiles);
+  if (cstart) (void)hipFree(cstart);
   if (ctl) (void)hipFree(ctl);
 }
 
@@ -216,19 +238,32 @@ int Scratch::init() {
   return RSAPRNG_OK;
 }
 
-int Scratch::ensure_tiles(u64h ntiles, void* stream) {
-  if (ntiles <= lb_tiles) return RSAPRNG_OK;
-  u64h want = std::max<u64h>(ntiles, lb_tiles * 2);
-  want = std::max<u64h>(want, 4096);
-  if (lb) {
-    if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSAPRNG_E_HIP;
-    (void)hipFree(lb);
+// Per-tile arrays (tile -> chain, start skip, sum, prefix, look-back words)
+// and per-chain starts.  Growing them synchronises the stream first.
+int Scratch::ensure_tiles(u64h ntiles, u64h nchains, void* stream) {
+  if (ntiles <= tiles_cap && nchains <= chains_cap) return RSAPRNG_OK;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSAPRNG_E_HIP;
+  if (ntiles > tiles_cap) {
+    u64h want = std::max<u64h>(std::max<u64h>(ntiles, tiles_cap * 2), 4096);
+    if (tiles) (void)hipFree(tiles);
+    if (lb) (void)hipFree(lb);
+    tiles = nullptr;
     lb = nullptr;
-    lb_tiles = 0;
+    tiles_cap = 0;
+    // tile_chain (4 B, padded to 8) + s_tile + agg + excl
+    if (hipMalloc(&tiles, want * 32) != hipSuccess) return RSAPRNG_E_OOM;
+    if (hipMalloc(&lb, want * 32) != hipSuccess) return RSAPRNG_E_OOM;
+    if (hipMemset(lb, 0, want * 32) != hipSuccess) return RSAPRNG_E_HIP;
+    tiles_cap = want;
   }
-  if (hipMalloc(&lb, want * 32) != hipSuccess) return RSAPRNG_E_OOM;
-  if (hipMemset(lb, 0, want * 32) != hipSuccess) return RSAPRNG_E_HIP;
-  lb_tiles = want;
+  if (nchains > chains_cap) {
+    u64h want = std::max<u64h>(std::max<u64h>(nchains, chains_cap * 2), 1024);
+    if (cstart) (void)hipFree(cstart);
+    cstart = nullptr;
+    chains_cap = 0;
+    if (hipMalloc(&cstart, want * sizeof(ChainStart)) != hipSuccess) return RSAPRNG_E_OOM;
+    chains_cap = want;
+  }
   return RSAPRNG_OK;
 }
 
@@ -305,6 +340,8 @@ rsaprng_config resolve_config(const rsaprng_config* cfg) {
   if (c.lanes_per_tile != 128 && c.lanes_per_tile != 256) c.lanes_per_tile = 256;
   if (c.per_lane != 8 && c.per_lane != 16) c.per_lane = 16;
   if (c.lanes_per_tile == 128) c.per_lane = 16;
+  if (c.prefix != kPrefixTwoPass && c.prefix != kPrefixLookback)
+    c.prefix = env_int("RSAPRNG_PREFIX", kPrefixTwoPass);
   return c;
 }
 
@@ -320,9 +357,30 @@ static u64h e_cost(uint32_t e) {
 // ---------------------------------------------------------------------------
 // planning: requests -> Req table with tile ranges
 // ---------------------------------------------------------------------------
-int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, std::vector<Req>& out,
-                  u64h* ntiles_out) {
+int plan_requests(const PlanIn* in_raw, size_t nreq_raw, const rsaprng_config& c, int mode,
+                  std::vector<Req>& out, u64h* ntiles_out) {
   const u64h T = tile_size(c);
+  // Requests of one instance that continue each other -- next k0 = previous end,
+  // and (generate) next output offset = previous end, or (consume) the same
+  // statistics record -- are one contiguous range: they share one scan chain.
+  std::vector<PlanIn> merged;
+  merged.reserve(nreq_raw);
+  for (size_t i = 0; i < nreq_raw; ++i) {
+    const PlanIn& r = in_raw[i];
+    if (!merged.empty()) {
+      PlanIn& m = merged.back();
+      const bool plain = !(m.flags | r.flags);
+      const bool adj_k = m.count && r.k0 == m.k0 + m.count && r.k0 > m.k0;
+      const bool adj_o = mode == kModeConsume ? r.slot == m.slot : r.out_off == m.out_off + m.count;
+      if (plain && r.inst == m.inst && adj_k && adj_o && r.count) {
+        m.count += r.count;
+        continue;
+      }
+    }
+    merged.push_back(r);
+  }
+  const PlanIn* in = merged.data();
+  const size_t nreq = merged.size();
   std::vector<size_t> order(nreq);
   for (size_t i = 0; i < nreq; ++i) order[i] = i;
   if (c.order == 1) {
@@ -364,54 +422,111 @@ int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, std::v
   return RSAPRNG_OK;
 }
 
+// Requests -> chains: one chain per (request, 2^20 block) with the tiles of
+// the request inside that block.
+int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode,
+                std::vector<Chain>& chains, u64h* ntiles_out) {
+  std::vector<Req> reqs;
+  u64h ntiles = 0;
+  int rc = plan_requests(in, nreq, c, mode, reqs, &ntiles);
+  if (rc) return rc;
+  const u64h T = tile_size(c);
+  chains.clear();
+  chains.reserve(reqs.size());
+  for (const Req& r : reqs) {
+    const u64h last = r.k0 + (r.count - 1);
+    u64h x = r.S;
+    u64h first = r.tile_begin;
+    for (;;) {
+      const u64h be = (x & ~(kBlock - 1)) + (kBlock - 1);
+      const u64h chain_last = std::min(last, be);
+      const u64h nt = (chain_last - x) / T + 1;
+      Chain ch;
+      std::memset(&ch, 0, sizeof(ch));
+      ch.S = x;
+      ch.k0 = r.k0;
+      ch.last = last;
+      ch.out_off = r.out_off;
+      ch.inst = r.inst;
+      ch.first = (uint32_t)first;
+      ch.ntiles = (uint32_t)nt;
+      ch.slot = r.slot;
+      ch.flags = ((r.flags & kReqContinue) && x == r.S ? kChainFromState : 0u) |
+                 ((r.flags & kReqWriteEnd) && last <= be ? kChainWriteEnd : 0u);
+      chains.push_back(ch);
+      first += nt;
+      if (last <= be) break;
+      x = be + 1;
+    }
+  }
+  *ntiles_out = ntiles;
+  return RSAPRNG_OK;
+}
+
 static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c, u64h ntiles) {
-  if (!c.persistent) return (int)std::min<u64h>(ntiles, 0x7fffffff);
+  // The dispatch packet counts work-items in 32 bits; work-groups loop over the
+  // tile queue, so any grid covers every tile.
+  if (!c.persistent) return (int)std::min<u64h>(ntiles, (1ull << 24));
   int occ = 1;
   if (kernel_max_grid(shape, &occ)) occ = 1;
   int per = c.wg_per_cu > 0 ? std::min(c.wg_per_cu, occ) : occ;
   return (int)std::min<u64h>(ntiles, (u64h)per * d->ncu);
 }
 
-// Enqueue [begin, tiles] (+ zero/finalize for consume).  `inst` and `req` are
-// device pointers.
+// Enqueue one launch: chain setup, then either [sums, scan, generate] (two
+// passes) or [queue reset, single-pass generate]; consume mode adds the zero
+// and finalize kernels around it.  `inst` and `chains` are device pointers.
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
-                   const rsaprng_params* inst, const Req* req, uint32_t nreq, u64h ntiles,
+                   const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream) {
+  int rc;
+  if (mode == kModeConsume && nstats && (rc = launch_stats_zero(stats, nstats, stream))) return rc;
   if (ntiles == 0) {
-    if (mode == kModeConsume && nstats) {
-      int rc = launch_stats_zero(stats, nstats, stream);
-      if (rc) return rc;
-      return launch_stats_finalize(stats, nstats, stream);
-    }
+    if (mode == kModeConsume && nstats) return launch_stats_finalize(stats, nstats, stream);
     return RSAPRNG_OK;
   }
-  int rc = sc->ensure_tiles(ntiles, stream);
-  if (rc) return rc;
+  if ((rc = sc->ensure_tiles(ntiles, nchain, stream))) return rc;
+  const u64h T = tile_size(c);
   KernelShape shape;
   shape.variant = c.variant;
   shape.wg = c.lanes_per_tile;
   shape.v = c.per_lane;
   shape.mode = mode;
+  shape.prefix = c.prefix;
   shape.grid = grid_for(d, shape, c, ntiles);
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
   a.inst = inst;
-  a.req = req;
-  a.nreq = nreq;
+  a.chain = chains;
+  a.nchain = nchain;
   a.ntiles = (uint32_t)ntiles;
+  a.tile_log2 = (uint32_t)__builtin_ctzll(T);
+  a.spin_limit = (uint32_t)env_int("RSAPRNG_SPIN_LIMIT", 1 << 22);
+  const u64h cap = sc->tiles_cap;
+  a.tile_chain = reinterpret_cast<uint32_t*>(sc->tiles);
+  a.s_tile = sc->tiles + cap / 2;
+  a.agg = sc->tiles + cap / 2 + cap;
+  a.excl = sc->tiles + cap / 2 + 2 * cap;
+  a.cstart = sc->cstart;
+  a.lb = sc->lb;
   a.out_c = out_c;
   a.out_r = out_r;
   a.stats = stats;
   a.state = state;
   a.ctl = sc->ctl;
-  a.lb = sc->lb;
   a.pow2 = d->pow2;
+  a.at = T == 2048 ? d->at2048 : d->at4096;
+  a.pl = T == 2048 ? d->pl2048 : d->pl4096;
   a.powv = c.per_lane == 8 ? d->powv8 : d->powv16;
   a.gc = d->gc;
-  a.spin_limit = (uint32_t)env_int("RSAPRNG_SPIN_LIMIT", 1 << 22);
-  if (mode == kModeConsume && (rc = launch_stats_zero(stats, nstats, stream))) return rc;
-  if ((rc = launch_begin(sc->ctl, stream))) return rc;
+  if ((rc = launch_chain_setup(a, stream))) return rc;
+  if (c.prefix == kPrefixTwoPass) {
+    if ((rc = launch_sums(a, stream))) return rc;
+    if ((rc = launch_scan(a, stream))) return rc;
+  } else {
+    if ((rc = launch_begin(sc->ctl, stream))) return rc;
+  }
   if ((rc = launch_tiles(shape, a, stream))) return rc;
   if (mode == kModeConsume && (rc = launch_stats_finalize(stats, nstats, stream))) return rc;
   return RSAPRNG_OK;
@@ -536,14 +651,15 @@ int rsaprng_generate(rsaprng_t h, uint64_t k0, uint64_t count, uint64_t* out_u64
   if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
   rsaprng_config c = resolve_config(nullptr);
   PlanIn in{0, h->prm.e, k0, count, 0, 0, 0, 0};
-  std::vector<Req> reqs;
+  std::vector<Chain> chains;
   u64h ntiles;
-  if ((rc = plan_requests(&in, 1, c, reqs, &ntiles))) return rc;
-  void* dreq;
+  if ((rc = plan_chains(&in, 1, c, kModeGenerate, chains, &ntiles))) return rc;
+  void* dch;
   int slot;
-  if ((rc = sc->upload(reqs.data(), sizeof(Req), stream, &dreq, &slot))) return rc;
-  rc = enqueue_launch(d, sc, c, kModeGenerate, h->dev, (const Req*)dreq, 1, ntiles, out_u64,
-                      out_f64, nullptr, 0, nullptr, stream);
+  if ((rc = sc->upload(chains.data(), chains.size() * sizeof(Chain), stream, &dch, &slot)))
+    return rc;
+  rc = enqueue_launch(d, sc, c, kModeGenerate, h->dev, (const Chain*)dch, (uint32_t)chains.size(),
+                      ntiles, out_u64, out_f64, nullptr, 0, nullptr, stream);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -559,16 +675,17 @@ int rsaprng_consume(rsaprng_t h, uint64_t k0, uint64_t count, rsaprng_stats* out
   if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
   rsaprng_config c = resolve_config(nullptr);
   PlanIn in{0, h->prm.e, k0, count, 0, 0, 0, 0};
-  std::vector<Req> reqs;
+  std::vector<Chain> chains;
   u64h ntiles;
-  if ((rc = plan_requests(&in, 1, c, reqs, &ntiles))) return rc;
-  if (reqs.empty()) return enqueue_launch(d, sc, c, kModeConsume, h->dev, nullptr, 0, 0, nullptr,
-                                          nullptr, out_dev, 1, nullptr, stream);
-  void* dreq;
+  if ((rc = plan_chains(&in, 1, c, kModeConsume, chains, &ntiles))) return rc;
+  if (chains.empty()) return enqueue_launch(d, sc, c, kModeConsume, h->dev, nullptr, 0, 0, nullptr,
+                                            nullptr, out_dev, 1, nullptr, stream);
+  void* dch;
   int slot;
-  if ((rc = sc->upload(reqs.data(), sizeof(Req), stream, &dreq, &slot))) return rc;
-  rc = enqueue_launch(d, sc, c, kModeConsume, h->dev, (const Req*)dreq, 1, ntiles, nullptr,
-                      nullptr, out_dev, 1, nullptr, stream);
+  if ((rc = sc->upload(chains.data(), chains.size() * sizeof(Chain), stream, &dch, &slot)))
+    return rc;
+  rc = enqueue_launch(d, sc, c, kModeConsume, h->dev, (const Chain*)dch, (uint32_t)chains.size(),
+                      ntiles, nullptr, nullptr, out_dev, 1, nullptr, stream);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -600,11 +717,11 @@ int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u
     }
     in[i] = PlanIn{id, reqs[i].h->prm.e, reqs[i].k0, reqs[i].count, reqs[i].out_off, 0, 0, 0};
   }
-  std::vector<Req> plan;
+  std::vector<Chain> plan;
   u64h ntiles;
-  if ((rc = plan_requests(in.data(), nreq, c, plan, &ntiles))) return rc;
+  if ((rc = plan_chains(in.data(), nreq, c, kModeGenerate, plan, &ntiles))) return rc;
   if (plan.empty()) return RSAPRNG_OK;
-  const size_t ib = insts.size() * sizeof(rsaprng_params), rb = plan.size() * sizeof(Req);
+  const size_t ib = insts.size() * sizeof(rsaprng_params), rb = plan.size() * sizeof(Chain);
   std::vector<char> buf(ib + rb);
   std::memcpy(buf.data(), insts.data(), ib);
   std::memcpy(buf.data() + ib, plan.data(), rb);
@@ -612,7 +729,7 @@ int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u
   int slot;
   if ((rc = sc->upload(buf.data(), buf.size(), stream, &dbuf, &slot))) return rc;
   rc = enqueue_launch(d, sc, c, kModeGenerate, (const rsaprng_params*)dbuf,
-                      (const Req*)((char*)dbuf + ib), (uint32_t)plan.size(), ntiles, out_u64,
+                      (const Chain*)((char*)dbuf + ib), (uint32_t)plan.size(), ntiles, out_u64,
                       out_f64, nullptr, 0, nullptr, stream);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
@@ -676,7 +793,7 @@ const rsaprng_params* pool_dev(rsaprng_pool_t pool) { return pool->dev; }
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i) { return pool->host[i]; }
 
 int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
-              const rsaprng_config& c, std::vector<Req>& plan, u64h* ntiles) {
+              const rsaprng_config& c, std::vector<Chain>& plan, u64h* ntiles) {
   std::vector<PlanIn> in(nreq);
   const size_t np = pool->host.size();
   for (size_t i = 0; i < nreq; ++i) {
@@ -686,7 +803,7 @@ int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, in
                    mode == kModeConsume ? (uint32_t)reqs[i].out_off : 0u, 0};
     if (mode == kModeConsume && reqs[i].out_off > 0xffffffffull) return RSAPRNG_E_ARG;
   }
-  return plan_requests(in.data(), nreq, c, plan, ntiles);
+  return plan_chains(in.data(), nreq, c, mode, plan, ntiles);
 }
 
 static size_t stats_records(const rsaprng_pool_req* reqs, size_t nreq) {
@@ -707,7 +824,7 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   int rc;
   if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
   rsaprng_config c = resolve_config(cfg);
-  std::vector<Req> plan;
+  std::vector<Chain> plan;
   u64h ntiles;
   if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
   const size_t nst = mode == kModeConsume ? stats_records(reqs, nreq) : 0;
@@ -716,8 +833,8 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
                           nullptr, stream);
   void* dreq;
   int slot;
-  if ((rc = sc->upload(plan.data(), plan.size() * sizeof(Req), stream, &dreq, &slot))) return rc;
-  rc = enqueue_launch(d, sc, c, mode, pool->dev, (const Req*)dreq, (uint32_t)plan.size(), ntiles,
+  if ((rc = sc->upload(plan.data(), plan.size() * sizeof(Chain), stream, &dreq, &slot))) return rc;
+  rc = enqueue_launch(d, sc, c, mode, pool->dev, (const Chain*)dreq, (uint32_t)plan.size(), ntiles,
                       out_u64, out_f64, stats, nst, nullptr, stream);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
@@ -770,16 +887,16 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   int rc;
   if ((rc = device_get(&d))) return rc;
   rsaprng_config c = resolve_config(cfg);
-  std::vector<Req> plan;
+  std::vector<Chain> plan;
   u64h ntiles;
   if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
   auto b = std::make_unique<rsaprng_batch_s>();
   b->pool = pool;
   if ((rc = b->sc.init())) return rc;
-  if ((rc = b->sc.ensure_tiles(ntiles, stream))) return rc;
+  if ((rc = b->sc.ensure_tiles(ntiles, plan.size(), stream))) return rc;
   if (!plan.empty()) {
-    if (hipMalloc(&b->dreq, plan.size() * sizeof(Req)) != hipSuccess) return RSAPRNG_E_OOM;
-    if (hipMemcpy(b->dreq, plan.data(), plan.size() * sizeof(Req), hipMemcpyHostToDevice) !=
+    if (hipMalloc(&b->dreq, plan.size() * sizeof(Chain)) != hipSuccess) return RSAPRNG_E_OOM;
+    if (hipMemcpy(b->dreq, plan.data(), plan.size() * sizeof(Chain), hipMemcpyHostToDevice) !=
         hipSuccess)
       return RSAPRNG_E_HIP;
   }
@@ -788,7 +905,7 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   const size_t nst = mode == kModeConsume ? stats_records(reqs, nreq) : 0;
   if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return RSAPRNG_E_HIP;
-  rc = enqueue_launch(d, &b->sc, c, mode, pool->dev, (const Req*)b->dreq, (uint32_t)plan.size(),
+  rc = enqueue_launch(d, &b->sc, c, mode, pool->dev, (const Chain*)b->dreq, (uint32_t)plan.size(),
                       ntiles, out_u64, out_f64, stats_dev, nst, nullptr, b->cap_stream);
   hipGraph_t g = nullptr;
   hipError_t e1 = hipStreamEndCapture(b->cap_stream, &g);
@@ -844,36 +961,34 @@ static std::string signature(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, 
   return os.str();
 }
 
-static int hash_device_buffer(const void* dev, size_t bytes, std::vector<uint64_t>& out) {
-  out.resize((bytes + 7) / 8);
-  if (bytes == 0) return RSAPRNG_OK;
-  return hipMemcpy(out.data(), dev, bytes, hipMemcpyDeviceToHost) == hipSuccess ? RSAPRNG_OK
-                                                                              : RSAPRNG_E_HIP;
-}
-
-static uint64_t fnv(const std::vector<uint64_t>& v) {
-  uint64_t h = 1469598103934665603ull;
-  for (uint64_t x : v) {
-    h ^= x;
-    h *= 1099511628211ull;
-  }
-  return h;
+// Fingerprint of a device buffer of 64-bit words, computed on the device.
+static int device_fingerprint(const void* dev, size_t words, void* stream, uint64_t* out) {
+  uint64_t* d = nullptr;
+  if (hipMalloc(&d, 8) != hipSuccess) return RSAPRNG_E_OOM;
+  int rc = launch_checksum((const uint64_t*)dev, words, d, stream);
+  if (!rc && hipMemcpyAsync(out, d, 8, hipMemcpyDeviceToHost, (hipStream_t)stream) != hipSuccess)
+    rc = RSAPRNG_E_HIP;
+  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = RSAPRNG_E_HIP;
+  (void)hipFree(d);
+  return rc;
 }
 
 std::vector<rsaprng_config> tune_space() {
   std::vector<rsaprng_config> out;
   for (int var : {kVariantCrt, kVariantMont})
     for (int shape = 0; shape < 3; ++shape)
-      for (int pers : {0, 1}) {
-        rsaprng_config c;
-        std::memset(&c, 0, sizeof(c));
-        c.variant = var;
-        c.lanes_per_tile = shape == 2 ? 128 : 256;
-        c.per_lane = shape == 1 ? 8 : 16;
-        c.persistent = pers;
-        c.order = pers;
-        out.push_back(c);
-      }
+      for (int pers : {0, 1})
+        for (int prefix : {kPrefixTwoPass, kPrefixLookback}) {
+          rsaprng_config c;
+          std::memset(&c, 0, sizeof(c));
+          c.variant = var;
+          c.lanes_per_tile = shape == 2 ? 128 : 256;
+          c.per_lane = shape == 1 ? 8 : 16;
+          c.persistent = pers;
+          c.order = pers;
+          c.prefix = prefix;
+          out.push_back(c);
+        }
   return out;
 }
 
@@ -897,9 +1012,9 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
       if (std::sscanf(line.c_str(),
                       "{\"sig\": \"%1023[^\"]\", \"variant\": %d, \"lanes_per_tile\": %d, "
                       "\"per_lane\": %d, \"persistent\": %d, \"wg_per_cu\": %d, \"order\": %d, "
-                      "\"ms\": %lf}",
+                      "\"prefix\": %d, \"ms\": %lf}",
                       sbuf, &c.variant, &c.lanes_per_tile, &c.per_lane, &c.persistent,
-                      &c.wg_per_cu, &c.order, &ms) == 8 &&
+                      &c.wg_per_cu, &c.order, &c.prefix, &ms) == 9 &&
           sig == sbuf) {
         *best = c;
         if (best_ms) *best_ms = ms;
@@ -925,20 +1040,13 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
     if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = RSAPRNG_E_HIP;
     // byte identity across configurations
     if (!rc) {
-      std::vector<uint64_t> v;
-      uint64_t hsh = 0;
+      uint64_t hsh = 0, h2 = 0;
       if (mode == kModeConsume) {
-        rc = hash_device_buffer(stats_dev, nst * sizeof(rsaprng_stats), v);
-        hsh = fnv(v);
+        rc = device_fingerprint(stats_dev, nst * sizeof(rsaprng_stats) / 8, stream, &hsh);
       } else {
-        if (out_u64) {
-          rc = hash_device_buffer(out_u64, total_out * 8, v);
-          hsh ^= fnv(v);
-        }
-        if (!rc && out_f64) {
-          rc = hash_device_buffer(out_f64, total_out * 8, v);
-          hsh ^= fnv(v) * 3;
-        }
+        if (out_u64) rc = device_fingerprint(out_u64, total_out, stream, &hsh);
+        if (!rc && out_f64) rc = device_fingerprint(out_f64, total_out, stream, &h2);
+        hsh ^= h2 * 3;
       }
       if (!rc) {
         if (!have_ref) {
@@ -961,6 +1069,11 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
     rsaprng_batch_destroy(b);
     if (rc) break;
     double ms = ms_tot / reps;
+    if (std::getenv("RSAPRNG_TUNE_LOG"))
+      std::fprintf(stderr,
+                   "[autotune] variant=%d lanes=%d per_lane=%d persistent=%d order=%d prefix=%d: "
+                   "%.3f ms\n",
+                   c.variant, c.lanes_per_tile, c.per_lane, c.persistent, c.order, c.prefix, ms);
     if (ms < best_t) {
       best_t = ms;
       *best = c;
@@ -976,7 +1089,8 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
     f << "{\"sig\": \"" << sig << "\", \"variant\": " << best->variant
       << ", \"lanes_per_tile\": " << best->lanes_per_tile << ", \"per_lane\": " << best->per_lane
       << ", \"persistent\": " << best->persistent << ", \"wg_per_cu\": " << best->wg_per_cu
-      << ", \"order\": " << best->order << ", \"ms\": " << best_t << "}\n";
+      << ", \"order\": " << best->order << ", \"prefix\": " << best->prefix
+      << ", \"ms\": " << best_t << "}\n";
   }
   return RSAPRNG_OK;
 }

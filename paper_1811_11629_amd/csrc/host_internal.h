@@ -30,13 +30,15 @@ struct Scratch {
     hipEvent_t ev = nullptr;
   };
   DevCtl* ctl = nullptr;
-  uint64_t* lb = nullptr;
-  u64h lb_tiles = 0;
+  uint64_t* lb = nullptr;        // look-back words, 32 B per tile
+  uint64_t* tiles = nullptr;     // tile_chain | s_tile | agg | excl, 32 B per tile
+  ChainStart* cstart = nullptr;
+  u64h tiles_cap = 0, chains_cap = 0;
   std::vector<Slot> slots = std::vector<Slot>(4);
   int next_slot = 0;
   ~Scratch();
   int init();
-  int ensure_tiles(u64h ntiles, void* stream);
+  int ensure_tiles(u64h ntiles, u64h nchains, void* stream);
   int upload(const void* data, size_t bytes, void* stream, void** dev_out, int* slot_out);
   int mark(int slot, void* stream);
 };
@@ -54,10 +56,12 @@ struct PlanIn {
 
 rsaprng_config resolve_config(const rsaprng_config* cfg);
 u64h tile_size(const rsaprng_config& c);
-int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, std::vector<Req>& out,
-                  u64h* ntiles_out);
+int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode,
+                  std::vector<Req>& out, u64h* ntiles_out);
+int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode,
+                std::vector<Chain>& chains, u64h* ntiles_out);
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
-                   const rsaprng_params* inst, const Req* req, uint32_t nreq, u64h ntiles,
+                   const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream);
 const rsaprng_params* pool_dev(rsaprng_pool_t pool);

@@ -6,6 +6,90 @@
 
 namespace rsaprng {
 
+static int hip_rc(hipError_t e) { return e == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP; }
+
+// ---------------------------------------------------------------------------
+// chain setup, sums, scan
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_chain_setup(LaunchArgs a) {
+  const int lane = threadIdx.x & 63;
+  const u32 c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= a.nchain) return;
+  const Chain C = a.chain[c];
+  const rsaprng_params P = a.inst[C.inst];
+  const u64 n = P.n;
+  u64 s_S, m_base;
+  if (C.flags & kChainFromState) {
+    const ChainState cs = a.state[C.slot];
+    s_S = cs.s_at;
+    m_base = cs.m_prev;
+  } else {
+    // a^S by the product over the set bits of S of a^(2^i), one bit per lane
+    u64 f = ((C.S >> lane) & 1ull) ? a.pow2[lane] : 1ull;
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) f = mulmod_q(f, __shfl_xor(f, m, 64));
+    s_S = mulmod_q(P.s0, f);
+    // S is a block start bB: m_bB = m0 + G_b, and the message "before" S is
+    // m_bB - s_S so that adding the skip at S reproduces m_bB.
+    const u64 G = mulmod_q(mulmod_q(P.s0, a.gc), f - 1);
+    const u64 m_bs = addmod(P.m0, skip_mod_n(G, n), n);
+    m_base = submod(m_bs, skip_mod_n(s_S, n), n);
+  }
+  if (lane == 0) {
+    ChainStart cs;
+    cs.s_S = s_S;
+    cs.m_base = m_base;
+    a.cstart[c] = cs;
+  }
+  for (u32 i = lane; i < C.ntiles; i += 64) a.tile_chain[C.first + i] = c;
+}
+
+// One wave per tile: T/64 consecutive skips per lane.
+__global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
+  const int lane = threadIdx.x & 63;
+  const u32 t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (t >= a.ntiles) return;
+  const u32 c = uniform(a.tile_chain[t]);
+  const Chain C = a.chain[c];
+  const u64 n = a.inst[C.inst].n;
+  const u32 j = t - C.first;
+  const u64 s_tile = mulmod_q(a.cstart[c].s_S, a.at[j]);
+  u64 s = mulmod_q(s_tile, a.pl[lane]);
+  const int per = 1 << (a.tile_log2 - 6);
+  u64 x = skip_mod_n(s, n);
+  for (int i = 1; i < per; ++i) {
+    s = lcg_next(s);
+    x = addmod(x, skip_mod_n(s, n), n);
+  }
+  x = wave_sum_mod(x, n);
+  if (lane == 0) {
+    a.agg[t] = x;
+    a.s_tile[t] = s_tile;
+  }
+}
+
+// One wave per chain: excl[tile] = message before the tile.
+__global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
+  const int lane = threadIdx.x & 63;
+  const u32 c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (c >= a.nchain) return;
+  const Chain C = a.chain[c];
+  const u64 n = a.inst[C.inst].n;
+  u64 E = a.cstart[c].m_base;
+  for (u32 base = 0; base < C.ntiles; base += 64) {
+    const u32 i = base + lane;
+    const u64 v = i < C.ntiles ? a.agg[C.first + i] : 0;
+    u64 incl = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      u64 y = __shfl_up(incl, d, 64);
+      if (lane >= d) incl = addmod(incl, y, n);
+    }
+    if (i < C.ntiles) a.excl[C.first + i] = addmod(E, submod(incl, v, n), n);
+    E = addmod(E, __shfl(incl, 63, 64), n);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // small kernels
 // ---------------------------------------------------------------------------
@@ -37,6 +121,8 @@ __global__ void k_stats_finalize(rsaprng_stats* st, size_t nrec) {
     carry = v >> 32;
   }
   for (int j = 0; j < 3; ++j) limb[j] = ((u64)dig[2 * j + 1] << 32) | dig[2 * j];
+  // canonical digits, so that the record does not depend on how the sum was split
+  for (int j = 0; j < 6; ++j) s->acc32[j] = dig[j];
   s->sum_fx[0] = limb[0];
   s->sum_fx[1] = limb[1];
   s->sum_fx[2] = limb[2];
@@ -63,6 +149,31 @@ __global__ void k_stats_finalize(rsaprng_stats* st, size_t nrec) {
   s->sum = d;
 }
 
+// Position-dependent fingerprint of a buffer of 64-bit words (order-independent
+// sum of mixed (index, value) pairs), used to check that kernel configurations
+// produce identical bytes without copying outputs to the host.
+__device__ __forceinline__ u64 mix64(u64 z) {
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+  return z ^ (z >> 31);
+}
+
+__global__ void k_checksum(const u64* p, u64 n, u64* out) {
+  u64 acc = 0;
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+    acc += mix64(p[i] ^ mix64(i + 0x9e3779b97f4a7c15ull));
+  for (int m = 1; m < 64; m <<= 1) acc += __shfl_xor(acc, m, 64);
+  if ((threadIdx.x & 63) == 0) atomicAdd((unsigned long long*)out, (unsigned long long)acc);
+}
+
+__global__ void k_zero1(u64* p) { *p = 0; }
+
+int launch_checksum(const uint64_t* p, uint64_t n, uint64_t* out_dev, void* stream) {
+  hipLaunchKernelGGL(k_zero1, dim3(1), dim3(1), 0, (hipStream_t)stream, out_dev);
+  if (n) hipLaunchKernelGGL(k_checksum, dim3(2048), dim3(256), 0, (hipStream_t)stream, p, n, out_dev);
+  return hip_rc(hipGetLastError());
+}
+
 template <int VAR>
 __global__ void k_debug_encrypt(rsaprng_params P, const u64* m, u64* c, double* r, u64 count) {
   u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x;
@@ -70,16 +181,33 @@ __global__ void k_debug_encrypt(rsaprng_params P, const u64* m, u64* c, double* 
   double cd;
   u64 v = encrypt<VAR, 0>(m[i], P, cd);
   if (c) c[i] = v;
-  if (r) r[i] = ratio(cd, P.nd);
+  if (r) r[i] = ratio(cd, P.nd, P.nrcp);
 }
 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-static int hip_rc(hipError_t e) { return e == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP; }
 
 int launch_begin(DevCtl* ctl, void* stream) {
   hipLaunchKernelGGL(k_begin, dim3(1), dim3(1), 0, (hipStream_t)stream, ctl);
+  return hip_rc(hipGetLastError());
+}
+
+int launch_chain_setup(const LaunchArgs& a, void* stream) {
+  if (!a.nchain) return RSAPRNG_OK;
+  hipLaunchKernelGGL(k_chain_setup, dim3((a.nchain + 3) / 4), dim3(256), 0, (hipStream_t)stream, a);
+  return hip_rc(hipGetLastError());
+}
+
+int launch_sums(const LaunchArgs& a, void* stream) {
+  if (!a.ntiles) return RSAPRNG_OK;
+  hipLaunchKernelGGL(k_sums, dim3((a.ntiles + 3) / 4), dim3(256), 0, (hipStream_t)stream, a);
+  return hip_rc(hipGetLastError());
+}
+
+int launch_scan(const LaunchArgs& a, void* stream) {
+  if (!a.nchain) return RSAPRNG_OK;
+  hipLaunchKernelGGL(k_scan, dim3((a.nchain + 3) / 4), dim3(256), 0, (hipStream_t)stream, a);
   return hip_rc(hipGetLastError());
 }
 

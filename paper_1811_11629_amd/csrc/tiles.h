@@ -1,27 +1,44 @@
 // gfx950 kernels of the RSA-exponentiation generator.
 //
-// One work-group processes one tile of T = WG * V consecutive indices of one
-// request (V per lane).  Per tile:
-//   1. jump   : s at the tile start, s0 a^K mod Q, by a product tree of the
-//               table a^(2^i) across the 64 lanes of wave 0 (eq. pseudoskip for
-//               the skips); at a block start also the block seed
-//               G_b = s0 a (a^{bB} - 1) / (a - 1) mod Q;
-//   2. walk   : each lane steps its V skips (eq. congruentialgenerator1) and
-//               keeps their running sums mod n in registers;
-//   3. scan   : wave scan + LDS across waves gives each lane's offset and the
-//               tile aggregate; the message before the tile comes from a
-//               decoupled look-back over the preceding tiles of the same block
-//               (tagged 64-bit words, relaxed agent-scope atomics, bounded wait);
-//   4. encrypt: c = m^e mod n per element (Montgomery-64 or CRT/binary64),
-//               r = RN(c)/RN(n) with the 1.0 guard;
-//   5. store  : c, r to HBM (generate) or fold into exact statistics (consume).
-// Tile ids come from an atomic counter, so a tile only ever waits on tiles that
-// were claimed before it by resident work-groups, and every wait is bounded.
+// The work of a launch is a list of chains (the tiles of one request inside
+// one 2^20 block) and T = WG * V consecutive indices per tile.
+//
+//   k_chain_setup  one wave per chain: the skip at the chain start,
+//                  s0 a^S mod Q, by a product tree of the table a^(2^i) over
+//                  the 64 lanes (eq. pseudoskip for the skips); for a block
+//                  start also the block seed G_b = s0 a (a^{bB} - 1)/(a - 1),
+//                  giving the message before the chain; fills tile -> chain.
+//   k_sums         (two-pass) one wave per tile: the tile's skips
+//                  (eq. congruentialgenerator1) summed mod n.
+//   k_scan         (two-pass) one wave per chain: exclusive prefix of the tile
+//                  sums, i.e. the message before every tile (m_k = m_{k-1} + s_k).
+//   k_gen          one work-group per tile: V skips per lane from the tile's
+//                  start skip, running sums in registers, wave + LDS scan, then
+//                  per element c = m^e mod n (Montgomery-64 or CRT with
+//                  binary64 residues) and r = RN(c)/RN(n) with the 1.0 guard,
+//                  stored to HBM (generate) or folded into exact statistics
+//                  (consume).  Two-pass: the message before the tile comes from
+//                  k_scan.  Single pass: tiles are claimed from an atomic queue
+//                  and the prefix comes from a decoupled look-back over the
+//                  preceding tiles of the chain (tagged 64-bit words, relaxed
+//                  agent-scope atomics, bounded wait).
 #pragma once
 #include "common.h"
 #include "devmath.h"
 
 namespace rsaprng {
+
+__device__ __forceinline__ u64 wave_sum_mod(u64 v, u64 n) {
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) v = addmod(v, __shfl_xor(v, m, 64), n);
+  return v;
+}
+
+__device__ __forceinline__ u64 submod(u64 x, u64 y, u64 n) {
+  return x >= y ? x - y : x + (n - y);
+}
+
+__device__ __forceinline__ u32 uniform(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
 
 // ---------------------------------------------------------------------------
 // look-back words: (tag << 32) | half, two words per 64-bit value
@@ -41,15 +58,9 @@ __device__ __forceinline__ bool try_read(const u64* w, u32 tag, u64& v) {
   return true;
 }
 
-__device__ __forceinline__ u64 wave_sum_mod(u64 v, u64 n) {
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) v = addmod(v, __shfl_xor(v, m, 64), n);
-  return v;
-}
-
 // Exclusive prefix (mod n) of tile t: the inclusive value of the nearest
-// predecessor that has one plus the aggregates in between.  Executed by one
-// full wave; the chain's first tile always publishes an inclusive value.
+// predecessor that has one plus the aggregates in between.  One full wave;
+// the chain's first tile always publishes an inclusive value.
 __device__ u64 look_back(const LaunchArgs& a, u32 t, u32 first, u32 tag, u64 n, int lane) {
   u64 acc = 0;
   long pos = (long)t - 1;
@@ -70,7 +81,7 @@ __device__ u64 look_back(const LaunchArgs& a, u32 t, u32 first, u32 tag, u64 n, 
         if (lane == 0) atomicOr(&a.ctl->err, 1u);
         return acc;
       }
-      __builtin_amdgcn_s_sleep(2);
+      __builtin_amdgcn_s_sleep(1);
     }
     u64 imask = __ballot(valid && hasI);
     int stop = imask ? __ffsll((unsigned long long)imask) - 1 : 64;
@@ -96,8 +107,14 @@ __device__ __forceinline__ u64 encrypt(u64 m, const rsaprng_params& P, double& c
     cd = u64_to_f64_rn(c);
     return c;
   } else {
-    double mp = residue(m, P.pd, P.pinv, P.kp);
-    double mq = residue(m, P.qd, P.qinv, P.kq);
+    double mp, mq;
+    if constexpr (E >= 2) {  // the ladder starts with a squaring
+      mp = residue_lazy(m, P.pd, P.pinv, P.kp);
+      mq = residue_lazy(m, P.qd, P.qinv, P.kq);
+    } else {
+      mp = residue(m, P.pd, P.pinv, P.kp);
+      mq = residue(m, P.qd, P.qinv, P.kq);
+    }
     double cp, cq;
     if constexpr (E != 0) {
       cp = fp_pow<E>(mp, P.pd, P.pinv);
@@ -110,7 +127,7 @@ __device__ __forceinline__ u64 encrypt(u64 m, const rsaprng_params& P, double& c
   }
 }
 
-// r * 2^128 as a 128-bit integer (r = 0 or 2^-64 <= r < 1, so the shift is in [12, 75]).
+// r * 2^128 as a 128-bit integer (r = 0 or 2^-64 <= r < 1: the shift is in [12, 75]).
 __device__ __forceinline__ void fixed128(double r, u64& lo, u64& hi) {
   u64 bits = (u64)__double_as_longlong(r);
   int ex = (int)(bits >> 52);
@@ -128,69 +145,49 @@ __device__ __forceinline__ void fixed128(double r, u64& lo, u64& hi) {
   }
 }
 
-template <int V>
-__device__ __forceinline__ void store_lane(u64* oc, double* orr, const u64 (&c)[V],
-                                           const double (&r)[V]) {
-  if (oc) {
-    if (((uintptr_t)oc & 15) == 0) {
-#pragma unroll
-      for (int i = 0; i < V; i += 2)
-        *reinterpret_cast<ulonglong2*>(oc + i) = make_ulonglong2(c[i], c[i + 1]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < V; ++i) oc[i] = c[i];
-    }
-  }
-  if (orr) {
-    if (((uintptr_t)orr & 15) == 0) {
-#pragma unroll
-      for (int i = 0; i < V; i += 2)
-        *reinterpret_cast<double2*>(orr + i) = make_double2(r[i], r[i + 1]);
-    } else {
-#pragma unroll
-      for (int i = 0; i < V; ++i) orr[i] = r[i];
-    }
-  }
-}
-
 template <int WG, int MODE>
 struct TileShared {
   u32 tile;
-  u64 s_tile;
   u64 pre;
   u64 wave_tot[WG / 64];
   u64 red[MODE == kModeConsume ? (WG / 64) * 6 : 1];
   u32 hist[MODE == kModeConsume ? 1024 : 1];
 };
 
-// Encryption, output and end-state phase of one tile for exponent E (0 = any).
-template <int WG, int V, int VAR, int MODE, u32 E>
+// Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
+// every index of the tile is requested and both outputs are 16-byte aligned at
+// every lane's first index, so pairs are stored without predicates.
+template <int WG, int V, int VAR, int MODE, u32 E, bool FAST>
 __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
-                                             const Req& R, const rsaprng_params& P, u64 pre,
+                                             const Chain& C, const rsaprng_params& P, u64 pre,
                                              const u64 (&X)[V], u64 laneStart) {
   const u64 n = P.n;
-  const u64 last = R.k0 + (R.count - 1);
-  const bool full = laneStart >= R.k0 && laneStart + (V - 1) <= last;
+  const bool full = FAST || (laneStart >= C.k0 && laneStart + (V - 1) <= C.last);
   if constexpr (MODE == kModeGenerate) {
-    u64 c[V];
-    double r[V];
+    u64* const oc = a.out_c;
+    double* const orr = a.out_r;
+    if constexpr (FAST) {
+      const u64 off0 = C.out_off + (laneStart - C.k0);
 #pragma unroll
-    for (int i = 0; i < V; ++i) {
-      double cd;
-      c[i] = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
-      r[i] = ratio(cd, P.nd);
-    }
-    if (full) {
-      u64 off = R.out_off + (laneStart - R.k0);
-      store_lane<V>(a.out_c ? a.out_c + off : nullptr, a.out_r ? a.out_r + off : nullptr, c, r);
+      for (int i = 0; i < V; i += 2) {
+        double cd0, cd1;
+        const u64 c0 = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd0);
+        const u64 c1 = encrypt<VAR, E>(addmod(pre, X[i + 1], n), P, cd1);
+        if (oc) *reinterpret_cast<ulonglong2*>(oc + off0 + i) = make_ulonglong2(c0, c1);
+        if (orr)
+          *reinterpret_cast<double2*>(orr + off0 + i) =
+              make_double2(ratio(cd0, P.nd, P.nrcp), ratio(cd1, P.nd, P.nrcp));
+      }
     } else {
 #pragma unroll
       for (int i = 0; i < V; ++i) {
-        u64 k = laneStart + i;
-        if (k >= R.k0 && k <= last) {
-          u64 off = R.out_off + (k - R.k0);
-          if (a.out_c) a.out_c[off] = c[i];
-          if (a.out_r) a.out_r[off] = r[i];
+        const u64 k = laneStart + i;
+        double cd;
+        const u64 c = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
+        if (k >= C.k0 && k <= C.last) {
+          const u64 off = C.out_off + (k - C.k0);
+          if (oc) oc[off] = c;
+          if (orr) orr[off] = ratio(cd, P.nd, P.nrcp);
         }
       }
     }
@@ -198,11 +195,11 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
     u64 c0 = 0, c1 = 0, c2 = 0, c3 = 0, lt = 0, cnt = 0;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
-      u64 k = laneStart + i;
+      const u64 k = laneStart + i;
       double cd;
       (void)encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
-      double r = ratio(cd, P.nd);
-      if (full || (k >= R.k0 && k <= last)) {
+      const double r = ratio(cd, P.nd, P.nrcp);
+      if (full || (k >= C.k0 && k <= C.last)) {
         u64 lo, hi;
         fixed128(r, lo, hi);
         c0 += lo32(lo);
@@ -230,7 +227,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       rd[0] = c0; rd[1] = c1; rd[2] = c2; rd[3] = c3; rd[4] = lt; rd[5] = cnt;
     }
     __syncthreads();
-    rsaprng_stats* st = a.stats + R.slot;
+    rsaprng_stats* st = a.stats + C.slot;
     if (threadIdx.x == 0) {
       u64 s[4] = {0, 0, 0, 0}, tl = 0, tc = 0;
       for (int w = 0; w < WG / 64; ++w) {
@@ -263,180 +260,182 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
   }
 }
 
-template <int WG, int V, int VAR, int MODE>
-__global__ __launch_bounds__(WG) void k_tiles(LaunchArgs a) {
+// Tile body shared by both prefix modes once the message before the tile (or
+// its chain start) is known.  Returns after outputs and the chain-end state.
+template <int WG, int V, int VAR, int MODE, int PREFIX>
+__device__ __forceinline__ void tile_body(const LaunchArgs& a, TileShared<WG, MODE>& sh, u32 t,
+                                          u64 my_powv, u32 tag) {
   constexpr int T = WG * V;
   constexpr int NW = WG / 64;
-  __shared__ TileShared<WG, MODE> sh;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const u32 tag = a.ctl->epoch;
+  const u32 c = uniform(a.tile_chain[t]);
+  const Chain C = a.chain[c];
+  const rsaprng_params P = a.inst[C.inst];
+  const u64 n = P.n;
+  const u32 j = t - C.first;
+  const u64 tileStart = C.S + (u64)j * T;
 
+  // start skip of the tile: from k_sums, or from the chain start and a^(jT)
+  u64 s_tile;
+  if constexpr (PREFIX == kPrefixTwoPass) s_tile = a.s_tile[t];
+  else s_tile = mulmod_q(a.cstart[c].s_S, a.at[j]);
+
+  // walk: V skips per lane, running sums mod n
+  const u64 laneStart = tileStart + (u64)threadIdx.x * V;
+  u64 X[V];
+  const u64 s_first = mulmod_q(s_tile, my_powv);
+  u64 s = s_first;
+  u64 x = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    if (i) s = lcg_next(s);
+    x = addmod(x, skip_mod_n(s, n), n);
+    X[i] = x;
+  }
+
+  // scan: lane offsets inside the wave, wave totals through LDS
+  u64 incl = x;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    u64 y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl = addmod(incl, y, n);
+  }
+  u64 lane_excl = __shfl_up(incl, 1, 64);
+  if (lane == 0) lane_excl = 0;
+  if (lane == 63) sh.wave_tot[wave] = incl;
+  __syncthreads();
+  u64 wave_off = 0, agg = 0;
+#pragma unroll
+  for (int w = 0; w < NW; ++w) {
+    const u64 v = sh.wave_tot[w];
+    if (w < wave) wave_off = addmod(wave_off, v, n);
+    agg = addmod(agg, v, n);
+  }
+  u64 E;
+  if constexpr (PREFIX == kPrefixTwoPass) {
+    E = a.excl[t];
+  } else {
+    if (wave == 0) {
+      u64 Ew;
+      if (j == 0) {
+        Ew = a.cstart[c].m_base;
+      } else {
+        if (lane == 0) publish(a.lb + 4ull * t, tag, agg);
+        Ew = look_back(a, t, C.first, tag, n, lane);
+      }
+      if (lane == 0) {
+        publish(a.lb + 4ull * t + 2, tag, addmod(Ew, agg, n));
+        sh.pre = Ew;
+      }
+    }
+    __syncthreads();
+    E = sh.pre;
+  }
+  const u64 pre = addmod(addmod(E, wave_off, n), lane_excl, n);
+
+  // outputs (only tiles that reach the requested range)
+  if (tileStart + (T - 1) >= C.k0) {
+    const u64 off_t = C.out_off + (tileStart - C.k0);
+    const bool fast = tileStart >= C.k0 && tileStart + (T - 1) <= C.last &&
+                      (MODE == kModeConsume ||
+                       ((!a.out_c || ((uintptr_t)(a.out_c + off_t) & 15) == 0) &&
+                        (!a.out_r || ((uintptr_t)(a.out_r + off_t) & 15) == 0)));
+    if (fast) {
+      switch (P.e) {
+        case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, pre, X, laneStart); break;
+        case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, pre, X, laneStart); break;
+        case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, pre, X, laneStart); break;
+        case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, pre, X, laneStart); break;
+        case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, pre, X, laneStart); break;
+        case 257: tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, pre, X, laneStart); break;
+        case 65537:
+          tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, pre, X, laneStart);
+          break;
+        default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, pre, X, laneStart); break;
+      }
+    } else {
+      tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, pre, X, laneStart);
+    }
+  }
+  // chain-end state for a continued request: the lane holding the last index
+  if ((C.flags & kChainWriteEnd) && laneStart <= C.last && C.last - laneStart < (u64)V) {
+    u64 m_end = 0;
+    u64 ss = s_first;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (laneStart + i == C.last) m_end = addmod(pre, X[i], n);
+      if (laneStart + i < C.last) ss = lcg_next(ss);
+    }
+    ChainState cs;
+    cs.m_prev = m_end;
+    cs.s_at = lcg_next(ss);
+    a.state[C.slot] = cs;
+  }
+}
+
+template <int WG, int V, int VAR, int MODE, int PREFIX>
+__global__ __launch_bounds__(WG) void k_gen(LaunchArgs a) {
+  __shared__ TileShared<WG, MODE> sh;
+  const u64 my_powv = a.powv[threadIdx.x];
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
   }
-
-  for (;;) {
-    if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctl->counter, 1u);
-    __syncthreads();
-    const u32 t = __builtin_amdgcn_readfirstlane(sh.tile);
-    if (t >= a.ntiles) break;
-
-    // request owning tile t: the last one with tile_begin <= t
-    u32 lo = 0, hi = a.nreq - 1;
-    while (lo < hi) {
-      u32 mid = (lo + hi + 1) >> 1;
-      if (a.req[mid].tile_begin <= t) lo = mid; else hi = mid - 1;
+  if constexpr (PREFIX == kPrefixTwoPass) {
+    for (u32 t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+      tile_body<WG, V, VAR, MODE, PREFIX>(a, sh, t, my_powv, 0);
+      __syncthreads();  // LDS reuse by the next tile
     }
-    const Req R = a.req[lo];
-    const rsaprng_params P = a.inst[R.inst];
-    const u64 n = P.n;
-    const u32 j = t - R.tile_begin;
-    const u64 tileStart = R.S + (u64)j * T;
-    const u64 bs = tileStart & ~(kBlock - 1);
-    const bool cont = (R.flags & kReqContinue) != 0;
-    const bool from_state = cont && bs <= R.S;        // tile lies in the chain started from state
-    const bool chain_start = from_state ? (j == 0) : (tileStart == bs);
-    const u64 chainS = from_state ? R.S : bs;
-    const u32 first = R.tile_begin + (u32)((chainS - R.S) / T);
-
-    // 1. jump (wave 0)
-    u64 mbase = 0;
-    if (wave == 0) {
-      u64 base, K;
-      if (from_state) {
-        const ChainState cs = a.state[R.slot];
-        base = cs.s_at;
-        K = tileStart - R.S;
-        mbase = cs.m_prev;
-      } else {
-        base = P.s0;
-        K = tileStart;
-      }
-      u64 f = ((K >> lane) & 1ull) ? a.pow2[lane] : 1ull;
-#pragma unroll
-      for (int m = 1; m < 64; m <<= 1) f = mulmod_q(f, __shfl_xor(f, m, 64));
-      const u64 s_tile = mulmod_q(base, f);
-      if (chain_start && !from_state) {
-        // block seed: m_bs = m0 + G_b, G_b = s0 a (a^bs - 1)/(a - 1) mod Q; mbase = m_bs - s_bs
-        u64 G = mulmod_q(mulmod_q(P.s0, a.gc), f - 1);
-        u64 mbs = addmod(P.m0, skip_mod_n(G, n), n);
-        u64 sn = skip_mod_n(s_tile, n);
-        mbase = addmod(mbs, sn == 0 ? 0 : n - sn, n);
-      } else if (chain_start && from_state) {
-        // mbase already m_{S-1}
-      }
-      if (lane == 0) sh.s_tile = s_tile;
-    }
-    __syncthreads();
-
-    // 2. walk
-    const u64 laneStart = tileStart + (u64)threadIdx.x * V;
-    u64 X[V];
-    u64 s = mulmod_q(sh.s_tile, a.powv[threadIdx.x]);
-    u64 s_first = s;
-    u64 x = 0;
-#pragma unroll
-    for (int i = 0; i < V; ++i) {
-      if (i) s = lcg_next(s);
-      x = addmod(x, skip_mod_n(s, n), n);
-      X[i] = x;
-    }
-
-    // 3. scan
-    u64 incl = x;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      u64 y = __shfl_up(incl, d, 64);
-      if (lane >= d) incl = addmod(incl, y, n);
-    }
-    u64 lane_excl = __shfl_up(incl, 1, 64);
-    if (lane == 0) lane_excl = 0;
-    if (lane == 63) sh.wave_tot[wave] = incl;
-    __syncthreads();
-    u64 wave_off = 0, agg = 0;
-#pragma unroll
-    for (int w = 0; w < NW; ++w) {
-      u64 v = sh.wave_tot[w];
-      if (w < wave) wave_off = addmod(wave_off, v, n);
-      agg = addmod(agg, v, n);
-    }
-    if (wave == 0) {
-      u64 E;
-      if (chain_start) {
-        E = mbase;
-      } else {
-        if (lane == 0) publish(a.lb + 4ull * t, tag, agg);
-        E = look_back(a, t, first, tag, n, lane);
-      }
-      if (lane == 0) {
-        publish(a.lb + 4ull * t + 2, tag, addmod(E, agg, n));
-        sh.pre = E;
-      }
-    }
-    __syncthreads();
-    const u64 pre = addmod(addmod(sh.pre, wave_off, n), lane_excl, n);
-
-    // 4-5. outputs (only tiles that reach the requested range)
-    if (tileStart + (T - 1) >= R.k0) {
-      switch (P.e) {
-        case 1: tile_outputs<WG, V, VAR, MODE, 1>(a, sh, R, P, pre, X, laneStart); break;
-        case 3: tile_outputs<WG, V, VAR, MODE, 3>(a, sh, R, P, pre, X, laneStart); break;
-        case 5: tile_outputs<WG, V, VAR, MODE, 5>(a, sh, R, P, pre, X, laneStart); break;
-        case 7: tile_outputs<WG, V, VAR, MODE, 7>(a, sh, R, P, pre, X, laneStart); break;
-        case 17: tile_outputs<WG, V, VAR, MODE, 17>(a, sh, R, P, pre, X, laneStart); break;
-        case 257: tile_outputs<WG, V, VAR, MODE, 257>(a, sh, R, P, pre, X, laneStart); break;
-        case 65537: tile_outputs<WG, V, VAR, MODE, 65537>(a, sh, R, P, pre, X, laneStart); break;
-        default: tile_outputs<WG, V, VAR, MODE, 0>(a, sh, R, P, pre, X, laneStart); break;
-      }
-    }
-    // chain-end state (served continuation): the lane holding the last index
-    const u64 last = R.k0 + (R.count - 1);
-    if ((R.flags & kReqWriteEnd) && laneStart <= last && last - laneStart < (u64)V) {
-      u64 m_end = 0;
-      u64 ss = s_first;
-#pragma unroll
-      for (int i = 0; i < V; ++i) {
-        if (laneStart + i == last) m_end = addmod(pre, X[i], n);
-        if (laneStart + i < last) ss = lcg_next(ss);
-      }
-      ChainState cs;
-      cs.m_prev = m_end;
-      cs.s_at = lcg_next(ss);
-      a.state[R.slot] = cs;
+  } else {
+    const u32 tag = a.ctl->epoch;
+    for (;;) {
+      if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctl->counter, 1u);
+      __syncthreads();
+      const u32 t = uniform(sh.tile);
+      if (t >= a.ntiles) break;
+      tile_body<WG, V, VAR, MODE, PREFIX>(a, sh, t, my_powv, tag);
+      __syncthreads();
     }
   }
 }
 
-template <int WG, int V, int VAR, int MODE>
+template <int WG, int V, int VAR, int MODE, int PREFIX>
 static int launch_one(const LaunchArgs& a, int grid, void* stream) {
-  hipLaunchKernelGGL((k_tiles<WG, V, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL((k_gen<WG, V, VAR, MODE, PREFIX>), dim3(grid), dim3(WG), 0,
+                     (hipStream_t)stream, a);
   return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
-template <int WG, int V, int VAR, int MODE>
+template <int WG, int V, int VAR, int MODE, int PREFIX>
 static int occupancy_of() {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_tiles<WG, V, VAR, MODE>, WG, 0) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen<WG, V, VAR, MODE, PREFIX>, WG,
+                                                   0) != hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;
+}
+
+template <int WG, int V, int VAR, int MODE>
+static int launch_shape(const KernelShape& s, const LaunchArgs& a, void* stream, int* occ) {
+  if (s.prefix == kPrefixTwoPass) {
+    if (occ) {
+      *occ = occupancy_of<WG, V, VAR, MODE, kPrefixTwoPass>();
+      return RSAPRNG_OK;
+    }
+    return launch_one<WG, V, VAR, MODE, kPrefixTwoPass>(a, s.grid, stream);
+  }
+  if (occ) {
+    *occ = occupancy_of<WG, V, VAR, MODE, kPrefixLookback>();
+    return RSAPRNG_OK;
+  }
+  return launch_one<WG, V, VAR, MODE, kPrefixLookback>(a, s.grid, stream);
 }
 
 // Launcher and occupancy query for every tile shape of one (variant, mode).
 template <int VAR, int MODE>
 int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* occ) {
-  if (s.wg == 256 && s.v == 16) {
-    if (occ) { *occ = occupancy_of<256, 16, VAR, MODE>(); return RSAPRNG_OK; }
-    return launch_one<256, 16, VAR, MODE>(a, s.grid, stream);
-  }
-  if (s.wg == 256 && s.v == 8) {
-    if (occ) { *occ = occupancy_of<256, 8, VAR, MODE>(); return RSAPRNG_OK; }
-    return launch_one<256, 8, VAR, MODE>(a, s.grid, stream);
-  }
-  if (s.wg == 128 && s.v == 16) {
-    if (occ) { *occ = occupancy_of<128, 16, VAR, MODE>(); return RSAPRNG_OK; }
-    return launch_one<128, 16, VAR, MODE>(a, s.grid, stream);
-  }
+  if (s.wg == 256 && s.v == 16) return launch_shape<256, 16, VAR, MODE>(s, a, stream, occ);
+  if (s.wg == 256 && s.v == 8) return launch_shape<256, 8, VAR, MODE>(s, a, stream, occ);
+  if (s.wg == 128 && s.v == 16) return launch_shape<128, 16, VAR, MODE>(s, a, stream, occ);
   return RSAPRNG_E_ARG;
 }
 

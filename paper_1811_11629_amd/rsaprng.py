@@ -44,7 +44,8 @@ class rsaprng_params(C.Structure):
                 ("ninv", C.c_uint32), ("e", C.c_uint32), ("p", C.c_uint32), ("q", C.c_uint32),
                 ("nd", C.c_double), ("pd", C.c_double), ("qd", C.c_double),
                 ("pinv", C.c_double), ("qinv", C.c_double), ("qinvp", C.c_double),
-                ("kp", C.c_double), ("kq", C.c_double), ("reserved", C.c_uint64 * 2)]
+                ("kp", C.c_double), ("kq", C.c_double), ("nrcp", C.c_double),
+                ("reserved", C.c_uint64)]
 
 
 class rsaprng_req(C.Structure):
@@ -59,7 +60,8 @@ class rsaprng_pool_req(C.Structure):
 
 class rsaprng_config(C.Structure):
     _fields_ = [("variant", C.c_int), ("lanes_per_tile", C.c_int), ("per_lane", C.c_int),
-                ("persistent", C.c_int), ("wg_per_cu", C.c_int), ("order", C.c_int)]
+                ("persistent", C.c_int), ("wg_per_cu", C.c_int), ("order", C.c_int),
+                ("prefix", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -174,8 +176,8 @@ def _u64arr(vals: Sequence[int]):
     return arr
 
 
-def config(variant=0, lanes_per_tile=0, per_lane=0, persistent=0, wg_per_cu=0, order=0):
-    return rsaprng_config(variant, lanes_per_tile, per_lane, persistent, wg_per_cu, order)
+def config(variant=0, lanes_per_tile=0, per_lane=0, persistent=0, wg_per_cu=0, order=0, prefix=0):
+    return rsaprng_config(variant, lanes_per_tile, per_lane, persistent, wg_per_cu, order, prefix)
 
 
 # --------------------------------------------------------------------------

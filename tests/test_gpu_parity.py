@@ -75,10 +75,12 @@ def test_ragged_ranges_both_variants(R, k0, count):
     cref, rref = oracle_gen(inst, k0, count)
     for var, name in _variants(R):
         for shape in ((256, 16), (256, 8), (128, 16)):
-            log("ragged", name, shape, k0, count)
-            cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1])
-            c, r, _ = _gen_pool(R, [inst], [(0, k0, count)], cfg)
-            assert_same(c, r, cref, rref, "%s %s k0=%d" % (name, shape, k0))
+            for prefix in (0, 1):
+                log("ragged", name, shape, "prefix", prefix, k0, count)
+                cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                               prefix=prefix)
+                c, r, _ = _gen_pool(R, [inst], [(0, k0, count)], cfg)
+                assert_same(c, r, cref, rref, "%s %s %d k0=%d" % (name, shape, prefix, k0))
 
 
 def test_edge_moduli_and_cribs(R):
@@ -155,11 +157,12 @@ def test_substreams_config2_subset_all_shapes(R):
     for var in (R.VARIANT_MONT, R.VARIANT_CRT):
         for shape in ((256, 16), (256, 8), (128, 16)):
             for pers in (0, 1):
-                log("config2 subset", var, shape, pers)
-                cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
-                               persistent=pers, order=pers)
-                c, r, _ = _gen_pool(R, insts, ranges, cfg)
-                assert_same(c, r, cref, rref, "config2 %s %s %s" % (var, shape, pers))
+                for prefix in (0, 1):
+                    log("config2 subset", var, shape, pers, prefix)
+                    cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                                   persistent=pers, order=pers, prefix=prefix)
+                    c, r, _ = _gen_pool(R, insts, ranges, cfg)
+                    assert_same(c, r, cref, rref, "config2 %s %s %s %s" % (var, shape, pers, prefix))
 
 
 def test_consume_matches_oracle(R):
@@ -172,11 +175,13 @@ def test_consume_matches_oracle(R):
     ranges = [(j, k0, cnt) for j in range(len(cases))
               for k0, cnt in ((0, 1 << 18), (B - 3000, 9000), ((1 << 40) + 5, 4097))]
     pool = R.Pool.from_instances(cases)
-    for var, name in _variants(R):
-        log("consume", name)
+    for (var, name), (shape, prefix) in [(v, sp) for v in _variants(R)
+                                         for sp in (((256, 16), 0), ((256, 8), 1), ((128, 16), 0))]:
+        log("consume", name, shape, prefix)
         st = R.stats_tensor(len(ranges))
         R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx) for idx, (j, k0, cnt) in enumerate(ranges)],
-                               st, cfg=R.config(variant=var))
+                               st, cfg=R.config(variant=var, lanes_per_tile=shape[0],
+                                                per_lane=shape[1], prefix=prefix))
         R.rsaprng_check_device_error()
         got = R.stats_decode(st)
         for idx, (j, k0, cnt) in enumerate(ranges):
@@ -214,9 +219,10 @@ def test_graph_batch_replays(R):
         reqs.append((i, k0, c, off))
         off += c
     oc, orr = dev_u64(total), dev_f64(total)
-    for var in (R.VARIANT_MONT, R.VARIANT_CRT):
-        log("graph batch", var)
-        b = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr, cfg=R.config(variant=var, persistent=1))
+    for var, prefix in ((R.VARIANT_MONT, 0), (R.VARIANT_CRT, 1), (R.VARIANT_CRT, 0)):
+        log("graph batch", var, prefix)
+        b = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr,
+                    cfg=R.config(variant=var, persistent=1, prefix=prefix))
         for rep in range(3):
             oc.fill_(-1)
             orr.fill_(-1.0)
