@@ -238,8 +238,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only copy BYTES device-to-device five times (counter calibration)")
     ap.add_argument("--config", default="",
-                    help="fixed kernel configuration 'variant,lanes,per_lane,persistent[,prefix]' "
+                    help="fixed kernel configuration 'variant,lanes,per_lane,persistent[,prefix[,r]]' "
                          "instead of the autotuner (variant 1 = Montgomery-64, 2 = CRT; prefix 0 "
                          "= two passes, 1 = single pass with look-back)")
     args = ap.parse_args()
@@ -255,6 +257,16 @@ def main():
     import inputs
     from paper_1811_11629_amd import rsaprng as R
 
+    if args.copy_probe:
+        n = args.copy_probe // 8
+        src = torch.ones(n, dtype=torch.int64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": n * 8, "copies": 5}))
+        return
+
     R.lib()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
@@ -266,10 +278,10 @@ def main():
     orr = torch.empty(N, dtype=torch.float64, device="cuda")
 
     if args.config:
-        f = [int(x) for x in args.config.split(",")] + [0]
-        v, lanes, per, pers, prefix = f[:5]
+        f = [int(x) for x in args.config.split(",")] + [0, 0]
+        v, lanes, per, pers, prefix, r = f[:6]
         best = R.config(variant=v, lanes_per_tile=lanes, per_lane=per, persistent=pers, order=pers,
-                        prefix=prefix)
+                        prefix=prefix, chunks_per_wave=r)
         log("fixed config", best.as_dict())
     else:
         cache = os.environ.get("RSAPRNG_TUNE_CACHE")

@@ -175,13 +175,14 @@ typedef struct {
 /* Kernel configuration.  Outputs never depend on it. */
 typedef struct {
   int variant;          /* 0 auto, 1 Montgomery-64 integer path, 2 CRT with binary64 residues */
-  int lanes_per_tile;   /* work-group size: 0 default, else 128 or 256 */
-  int per_lane;         /* outputs per lane: 0 default, else 8 or 16 */
+  int lanes_per_tile;   /* work-group size: 0 default, else 256 or 512 */
+  int per_lane;         /* consecutive indices per lane: 0 default, else 8 or 16 */
   int persistent;       /* 1: grid of resident work-groups looping over the tiles */
   int wg_per_cu;        /* persistent grid size per compute unit (0 = default) */
   int order;            /* 0 request order, 1 longest-first by exponent cost */
   int prefix;           /* 0 two passes (tile sums, scan, generate); 1 one pass with a
                            decoupled look-back over the preceding tiles */
+  int chunks_per_wave;  /* two passes: consecutive 64*per_lane chunks each wave processes */
 } rsaprng_config;
 
 /* One-shot batched launches over a pool (reqs is a host array). */

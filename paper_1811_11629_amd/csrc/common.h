@@ -85,12 +85,14 @@ struct LaunchArgs {
   uint32_t nchain;
   uint32_t ntiles;
   uint32_t tile_log2;      // T = 2^tile_log2 indices per tile
+  uint32_t chunk_log2;     // a wave's share of a tile: 64 V = 2^chunk_log2 indices
   uint32_t spin_limit;
+  uint32_t pad0;
   uint32_t* tile_chain;    // per tile: owning chain (k_chain_setup)
   ChainStart* cstart;      // per chain (k_chain_setup)
   uint64_t* s_tile;        // per tile: skip at the tile start (k_sums)
-  uint64_t* agg;           // per tile: sum of its skips mod n (k_sums)
-  uint64_t* excl;          // per tile: message before the tile (k_scan)
+  uint64_t* agg;           // per wave chunk: sum of its skips mod n (k_sums)
+  uint64_t* excl;          // per wave chunk: message before the chunk (k_scan)
   uint64_t* lb;            // single pass: 4 tagged words per tile
   uint64_t* out_c;
   double* out_r;
@@ -111,6 +113,7 @@ struct KernelShape {
   int v;         // 8 or 16
   int mode;      // kModeGenerate or kModeConsume
   int prefix;    // kPrefixTwoPass or kPrefixLookback
+  int r;         // two passes: consecutive wave chunks per wave (tile = wg v r)
   int grid;      // number of work-groups (they loop if fewer than tiles)
 };
 int launch_begin(DevCtl* ctl, void* stream);

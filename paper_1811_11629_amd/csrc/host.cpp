@@ -148,12 +148,10 @@ struct Device {
   int id = -1;
   int ncu = 0;
   uint64_t* pow2 = nullptr;    // a^(2^i) mod Q, i < 64
-  uint64_t* powv8 = nullptr;   // a^(8 l) mod Q, l < 256
+  uint64_t* powv8 = nullptr;   // a^(8 l) mod Q, l < 1024
   uint64_t* powv16 = nullptr;  // a^(16 l) mod Q, l < 256
-  uint64_t* at2048 = nullptr;  // a^(2048 j) mod Q, j < 512
-  uint64_t* at4096 = nullptr;  // a^(4096 j) mod Q, j < 256
-  uint64_t* pl2048 = nullptr;  // a^(32 l) mod Q, l < 64
-  uint64_t* pl4096 = nullptr;  // a^(64 l) mod Q, l < 64
+  uint64_t* at[3] = {};        // a^(T j) mod Q, j < 2^20 / T, for T = 2048, 4096, 8192
+  uint64_t* pl[3] = {};        // a^((T/64) l) mod Q, l < 64
   u64h gc = 0;
 };
 
@@ -202,12 +200,13 @@ int device_get(Device** out) {
   }
   int rc = RSAPRNG_OK;
   if (!rc) rc = upload_table(&d->pow2, t2);
-  if (!rc) rc = upload_table(&d->powv8, power_table(8, 256));
+  if (!rc) rc = upload_table(&d->powv8, power_table(8, 1024));
   if (!rc) rc = upload_table(&d->powv16, power_table(16, 256));
-  if (!rc) rc = upload_table(&d->at2048, power_table(2048, kBlock / 2048));
-  if (!rc) rc = upload_table(&d->at4096, power_table(4096, kBlock / 4096));
-  if (!rc) rc = upload_table(&d->pl2048, power_table(2048 / 64, 64));
-  if (!rc) rc = upload_table(&d->pl4096, power_table(4096 / 64, 64));
+  for (int i = 0; i < 3 && !rc; ++i) {
+    const u64h T = 2048ull << i;
+    rc = upload_table(&d->at[i], power_table(T, kBlock / T));
+    if (!rc) rc = upload_table(&d->pl[i], power_table(T / 64, 64));
+  }
   if (rc) {
     delete d;
     return rc;
@@ -238,23 +237,25 @@ int Scratch::init() {
   return RSAPRNG_OK;
 }
 
-// Per-tile arrays (tile -> chain, start skip, sum, prefix, look-back words)
-// and per-chain starts.  Growing them synchronises the stream first.
-int Scratch::ensure_tiles(u64h ntiles, u64h nchains, void* stream) {
-  if (ntiles <= tiles_cap && nchains <= chains_cap) return RSAPRNG_OK;
+// Per-tile arrays (tile -> chain, start skip, look-back words), per-chunk
+// arrays (sum, prefix) and per-chain starts.  Growing them synchronises the
+// stream first.
+int Scratch::ensure_tiles(u64h ntiles, u64h nchunks, u64h nchains, void* stream) {
+  if (ntiles <= tiles_cap && nchunks <= chunks_cap && nchains <= chains_cap) return RSAPRNG_OK;
   if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSAPRNG_E_HIP;
-  if (ntiles > tiles_cap) {
-    u64h want = std::max<u64h>(std::max<u64h>(ntiles, tiles_cap * 2), 4096);
+  if (ntiles > tiles_cap || nchunks > chunks_cap) {
+    const u64h tw = std::max<u64h>(std::max<u64h>(ntiles, tiles_cap * 2), 4096);
+    const u64h cw = std::max<u64h>(std::max<u64h>(nchunks, chunks_cap * 2), 4096);
     if (tiles) (void)hipFree(tiles);
     if (lb) (void)hipFree(lb);
     tiles = nullptr;
     lb = nullptr;
-    tiles_cap = 0;
-    // tile_chain (4 B, padded to 8) + s_tile + agg + excl
-    if (hipMalloc(&tiles, want * 32) != hipSuccess) return RSAPRNG_E_OOM;
-    if (hipMalloc(&lb, want * 32) != hipSuccess) return RSAPRNG_E_OOM;
-    if (hipMemset(lb, 0, want * 32) != hipSuccess) return RSAPRNG_E_HIP;
-    tiles_cap = want;
+    tiles_cap = chunks_cap = 0;
+    if (hipMalloc(&tiles, tile_words(tw, cw) * 8) != hipSuccess) return RSAPRNG_E_OOM;
+    if (hipMalloc(&lb, tw * 32) != hipSuccess) return RSAPRNG_E_OOM;
+    if (hipMemset(lb, 0, tw * 32) != hipSuccess) return RSAPRNG_E_HIP;
+    tiles_cap = tw;
+    chunks_cap = cw;
   }
   if (nchains > chains_cap) {
     u64h want = std::max<u64h>(std::max<u64h>(nchains, chains_cap * 2), 1024);
@@ -337,15 +338,27 @@ rsaprng_config resolve_config(const rsaprng_config* cfg) {
   if (cfg) c = *cfg;
   if (c.variant == kVariantAuto) c.variant = env_int("RSAPRNG_VARIANT", kVariantCrt);
   if (c.variant != kVariantMont && c.variant != kVariantCrt) c.variant = kVariantCrt;
-  if (c.lanes_per_tile != 128 && c.lanes_per_tile != 256) c.lanes_per_tile = 256;
-  if (c.per_lane != 8 && c.per_lane != 16) c.per_lane = 16;
-  if (c.lanes_per_tile == 128) c.per_lane = 16;
   if (c.prefix != kPrefixTwoPass && c.prefix != kPrefixLookback)
     c.prefix = env_int("RSAPRNG_PREFIX", kPrefixTwoPass);
+  if (c.prefix == kPrefixTwoPass) {
+    // shapes built for two passes: (256, 8, r) for r = 1, 2, 4 and (512, 8, 2)
+    c.per_lane = 8;
+    if (c.lanes_per_tile != 512) c.lanes_per_tile = 256;
+    if (c.lanes_per_tile == 512) c.chunks_per_wave = 2;
+    else if (c.chunks_per_wave != 1 && c.chunks_per_wave != 4) c.chunks_per_wave = 2;
+  } else {
+    // one pass: (256, 8), (512, 8), (256, 16)
+    c.chunks_per_wave = 1;
+    if (c.lanes_per_tile != 256 && c.lanes_per_tile != 512) c.lanes_per_tile = 256;
+    if (c.per_lane != 8 && c.per_lane != 16) c.per_lane = 8;
+    if (c.lanes_per_tile == 512) c.per_lane = 8;
+  }
   return c;
 }
 
-u64h tile_size(const rsaprng_config& c) { return (u64h)c.lanes_per_tile * c.per_lane; }
+u64h tile_size(const rsaprng_config& c) {
+  return (u64h)c.lanes_per_tile * c.per_lane * c.chunks_per_wave;
+}
 
 // Relative cost of one output for exponent e (multiplications of the ladder),
 // used for longest-first ordering.
@@ -486,14 +499,16 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
     if (mode == kModeConsume && nstats) return launch_stats_finalize(stats, nstats, stream);
     return RSAPRNG_OK;
   }
-  if ((rc = sc->ensure_tiles(ntiles, nchain, stream))) return rc;
   const u64h T = tile_size(c);
+  const u64h chunks_per_tile = T / (64ull * c.per_lane);
+  if ((rc = sc->ensure_tiles(ntiles, ntiles * chunks_per_tile, nchain, stream))) return rc;
   KernelShape shape;
   shape.variant = c.variant;
   shape.wg = c.lanes_per_tile;
   shape.v = c.per_lane;
   shape.mode = mode;
   shape.prefix = c.prefix;
+  shape.r = c.chunks_per_wave;
   shape.grid = grid_for(d, shape, c, ntiles);
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -502,12 +517,14 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   a.nchain = nchain;
   a.ntiles = (uint32_t)ntiles;
   a.tile_log2 = (uint32_t)__builtin_ctzll(T);
+  a.chunk_log2 = (uint32_t)__builtin_ctzll(64ull * c.per_lane);
   a.spin_limit = (uint32_t)env_int("RSAPRNG_SPIN_LIMIT", 1 << 22);
-  const u64h cap = sc->tiles_cap;
+  const u64h cap = sc->tiles_cap, ccap = sc->chunks_cap;
+  const u64h half = (cap + 1) / 2;
   a.tile_chain = reinterpret_cast<uint32_t*>(sc->tiles);
-  a.s_tile = sc->tiles + cap / 2;
-  a.agg = sc->tiles + cap / 2 + cap;
-  a.excl = sc->tiles + cap / 2 + 2 * cap;
+  a.s_tile = sc->tiles + half;
+  a.agg = sc->tiles + half + cap;
+  a.excl = sc->tiles + half + cap + ccap;
   a.cstart = sc->cstart;
   a.lb = sc->lb;
   a.out_c = out_c;
@@ -516,8 +533,10 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   a.state = state;
   a.ctl = sc->ctl;
   a.pow2 = d->pow2;
-  a.at = T == 2048 ? d->at2048 : d->at4096;
-  a.pl = T == 2048 ? d->pl2048 : d->pl4096;
+  const int ti = T == 2048 ? 0 : (T == 4096 ? 1 : 2);
+  if (T != (2048ull << ti)) return RSAPRNG_E_ARG;
+  a.at = d->at[ti];
+  a.pl = d->pl[ti];
   a.powv = c.per_lane == 8 ? d->powv8 : d->powv16;
   a.gc = d->gc;
   if ((rc = launch_chain_setup(a, stream))) return rc;
@@ -893,7 +912,10 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   auto b = std::make_unique<rsaprng_batch_s>();
   b->pool = pool;
   if ((rc = b->sc.init())) return rc;
-  if ((rc = b->sc.ensure_tiles(ntiles, plan.size(), stream))) return rc;
+  // sized before the capture so that the captured launch allocates nothing
+  if ((rc = b->sc.ensure_tiles(ntiles, ntiles * (tile_size(c) / (64ull * c.per_lane)), plan.size(),
+                               stream)))
+    return rc;
   if (!plan.empty()) {
     if (hipMalloc(&b->dreq, plan.size() * sizeof(Chain)) != hipSuccess) return RSAPRNG_E_OOM;
     if (hipMemcpy(b->dreq, plan.data(), plan.size() * sizeof(Chain), hipMemcpyHostToDevice) !=
@@ -974,21 +996,26 @@ static int device_fingerprint(const void* dev, size_t words, void* stream, uint6
 }
 
 std::vector<rsaprng_config> tune_space() {
+  // (prefix, lanes, per_lane, chunks_per_wave)
+  static const int shapes[][4] = {{kPrefixTwoPass, 256, 8, 1}, {kPrefixTwoPass, 256, 8, 2},
+                                  {kPrefixTwoPass, 256, 8, 4}, {kPrefixTwoPass, 512, 8, 2},
+                                  {kPrefixLookback, 256, 8, 1}, {kPrefixLookback, 512, 8, 1},
+                                  {kPrefixLookback, 256, 16, 1}};
   std::vector<rsaprng_config> out;
   for (int var : {kVariantCrt, kVariantMont})
-    for (int shape = 0; shape < 3; ++shape)
-      for (int pers : {0, 1})
-        for (int prefix : {kPrefixTwoPass, kPrefixLookback}) {
-          rsaprng_config c;
-          std::memset(&c, 0, sizeof(c));
-          c.variant = var;
-          c.lanes_per_tile = shape == 2 ? 128 : 256;
-          c.per_lane = shape == 1 ? 8 : 16;
-          c.persistent = pers;
-          c.order = pers;
-          c.prefix = prefix;
-          out.push_back(c);
-        }
+    for (const auto& s : shapes)
+      for (int pers : {0, 1}) {
+        rsaprng_config c;
+        std::memset(&c, 0, sizeof(c));
+        c.variant = var;
+        c.prefix = s[0];
+        c.lanes_per_tile = s[1];
+        c.per_lane = s[2];
+        c.chunks_per_wave = s[3];
+        c.persistent = pers;
+        c.order = pers;
+        out.push_back(c);
+      }
   return out;
 }
 
@@ -1012,9 +1039,9 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
       if (std::sscanf(line.c_str(),
                       "{\"sig\": \"%1023[^\"]\", \"variant\": %d, \"lanes_per_tile\": %d, "
                       "\"per_lane\": %d, \"persistent\": %d, \"wg_per_cu\": %d, \"order\": %d, "
-                      "\"prefix\": %d, \"ms\": %lf}",
+                      "\"prefix\": %d, \"chunks_per_wave\": %d, \"ms\": %lf}",
                       sbuf, &c.variant, &c.lanes_per_tile, &c.per_lane, &c.persistent,
-                      &c.wg_per_cu, &c.order, &c.prefix, &ms) == 9 &&
+                      &c.wg_per_cu, &c.order, &c.prefix, &c.chunks_per_wave, &ms) == 10 &&
           sig == sbuf) {
         *best = c;
         if (best_ms) *best_ms = ms;
@@ -1071,9 +1098,10 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
     double ms = ms_tot / reps;
     if (std::getenv("RSAPRNG_TUNE_LOG"))
       std::fprintf(stderr,
-                   "[autotune] variant=%d lanes=%d per_lane=%d persistent=%d order=%d prefix=%d: "
-                   "%.3f ms\n",
-                   c.variant, c.lanes_per_tile, c.per_lane, c.persistent, c.order, c.prefix, ms);
+                   "[autotune] variant=%d lanes=%d per_lane=%d r=%d persistent=%d order=%d "
+                   "prefix=%d: %.3f ms\n",
+                   c.variant, c.lanes_per_tile, c.per_lane, c.chunks_per_wave, c.persistent,
+                   c.order, c.prefix, ms);
     if (ms < best_t) {
       best_t = ms;
       *best = c;
@@ -1090,7 +1118,7 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
       << ", \"lanes_per_tile\": " << best->lanes_per_tile << ", \"per_lane\": " << best->per_lane
       << ", \"persistent\": " << best->persistent << ", \"wg_per_cu\": " << best->wg_per_cu
       << ", \"order\": " << best->order << ", \"prefix\": " << best->prefix
-      << ", \"ms\": " << best_t << "}\n";
+      << ", \"chunks_per_wave\": " << best->chunks_per_wave << ", \"ms\": " << best_t << "}\n";
   }
   return RSAPRNG_OK;
 }

@@ -21,6 +21,12 @@ int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng
 struct Device;
 int device_get(Device** out);
 
+// Scratch layout in 64-bit words for `cap` tiles and `ccap` wave chunks:
+//   tile_chain  uint32 per tile         [0, ceil(cap/2))
+//   s_tile      one word per tile       next cap words
+//   agg, excl   one word per chunk each next 2 ccap words
+inline u64h tile_words(u64h cap, u64h ccap) { return (cap + 1) / 2 + cap + 2 * ccap; }
+
 // Launch scratch (see host.cpp).
 struct Scratch {
   struct Slot {
@@ -33,12 +39,12 @@ struct Scratch {
   uint64_t* lb = nullptr;        // look-back words, 32 B per tile
   uint64_t* tiles = nullptr;     // tile_chain | s_tile | agg | excl, 32 B per tile
   ChainStart* cstart = nullptr;
-  u64h tiles_cap = 0, chains_cap = 0;
+  u64h tiles_cap = 0, chunks_cap = 0, chains_cap = 0;
   std::vector<Slot> slots = std::vector<Slot>(4);
   int next_slot = 0;
   ~Scratch();
   int init();
-  int ensure_tiles(u64h ntiles, u64h nchains, void* stream);
+  int ensure_tiles(u64h ntiles, u64h nchunks, u64h nchains, void* stream);
   int upload(const void* data, size_t bytes, void* stream, void** dev_out, int* slot_out);
   int mark(int slot, void* stream);
 };

@@ -44,7 +44,8 @@ __global__ __launch_bounds__(256) void k_chain_setup(LaunchArgs a) {
   for (u32 i = lane; i < C.ntiles; i += 64) a.tile_chain[C.first + i] = c;
 }
 
-// One wave per tile: T/64 consecutive skips per lane.
+// One wave per tile: T/64 consecutive skips per lane; the sums of the tile's
+// wave chunks (64 V indices each, 64/NW consecutive lanes here) mod n.
 __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   const int lane = threadIdx.x & 63;
   const u32 t = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -61,32 +62,34 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
     s = lcg_next(s);
     x = addmod(x, skip_mod_n(s, n), n);
   }
-  x = wave_sum_mod(x, n);
-  if (lane == 0) {
-    a.agg[t] = x;
-    a.s_tile[t] = s_tile;
-  }
+  const int nw_log2 = a.tile_log2 - a.chunk_log2;     // wave chunks per tile
+  const int group = 64 >> nw_log2;                     // lanes per chunk
+  // chunk sums as differences of the inclusive scan at the chunk boundaries
+  const u64 incl = wave_scan_mod(x, n);
+  const u64 before = __shfl(incl, (lane & ~(group - 1)) - 1 + (lane < group ? 64 : 0), 64);
+  if ((lane & (group - 1)) == group - 1)
+    a.agg[((u64)t << nw_log2) + (lane >> (6 - nw_log2))] =
+        lane < group ? incl : submod(incl, before, n);
+  if (lane == 0) a.s_tile[t] = s_tile;
 }
 
-// One wave per chain: excl[tile] = message before the tile.
+// One wave per chain: excl[chunk] = message before the wave chunk.
 __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const int lane = threadIdx.x & 63;
   const u32 c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.nchain) return;
   const Chain C = a.chain[c];
   const u64 n = a.inst[C.inst].n;
+  const int nw_log2 = a.tile_log2 - a.chunk_log2;
+  const u64 first = (u64)C.first << nw_log2;
+  const u64 cnt = (u64)C.ntiles << nw_log2;
   u64 E = a.cstart[c].m_base;
-  for (u32 base = 0; base < C.ntiles; base += 64) {
-    const u32 i = base + lane;
-    const u64 v = i < C.ntiles ? a.agg[C.first + i] : 0;
-    u64 incl = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      u64 y = __shfl_up(incl, d, 64);
-      if (lane >= d) incl = addmod(incl, y, n);
-    }
-    if (i < C.ntiles) a.excl[C.first + i] = addmod(E, submod(incl, v, n), n);
-    E = addmod(E, __shfl(incl, 63, 64), n);
+  for (u64 base = 0; base < cnt; base += 64) {
+    const u64 i = base + lane;
+    const u64 v = i < cnt ? a.agg[first + i] : 0;
+    const u64 incl = wave_scan_mod(v, n);
+    if (i < cnt) a.excl[first + i] = addmod(E, submod(incl, v, n), n);
+    E = addmod(E, lane_value(incl, 63), n);
   }
 }
 

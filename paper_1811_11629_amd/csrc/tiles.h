@@ -40,6 +40,54 @@ __device__ __forceinline__ u64 submod(u64 x, u64 y, u64 n) {
 
 __device__ __forceinline__ u32 uniform(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// Read-only launch data (chains, instance records, per-tile and per-chunk
+// prefixes) seen through the constant address space: with wave-uniform
+// indices these become scalar loads, which do not wait on the wave's earlier
+// vector stores the way vector loads do.
+template <class T>
+__device__ __forceinline__ const __attribute__((address_space(4))) T* cst(const T* p) {
+  return (const __attribute__((address_space(4))) T*)p;
+}
+
+// Copy of a record through the constant address space, word by word.
+template <class T>
+__device__ __forceinline__ T load_cst(const T* p) {
+  static_assert(sizeof(T) % 8 == 0, "record of 64-bit words");
+  T out;
+  const __attribute__((address_space(4))) u64* src = cst(reinterpret_cast<const u64*>(p));
+  u64* dst = reinterpret_cast<u64*>(&out);
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 8); ++i) dst[i] = src[i];
+  return out;
+}
+
+// 64-bit DPP move: lanes whose source is outside the row pattern (or whose row
+// is masked off) receive 0.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ u64 dpp64(u64 v) {
+  const u32 lo = (u32)__builtin_amdgcn_update_dpp(0, (int)lo32(v), CTRL, ROW_MASK, 0xf, false);
+  const u32 hi = (u32)__builtin_amdgcn_update_dpp(0, (int)hi32(v), CTRL, ROW_MASK, 0xf, false);
+  return ((u64)hi << 32) | lo;
+}
+
+// Inclusive scan mod n over the 64 lanes: row shifts by 1, 2, 4, 8 inside
+// rows of 16, then the row-15 and row-31 broadcasts (full-rate VALU moves).
+__device__ __forceinline__ u64 wave_scan_mod(u64 x, u64 n) {
+  x = addmod(x, dpp64<0x111, 0xf>(x), n);  // row_shr:1
+  x = addmod(x, dpp64<0x112, 0xf>(x), n);  // row_shr:2
+  x = addmod(x, dpp64<0x114, 0xf>(x), n);  // row_shr:4
+  x = addmod(x, dpp64<0x118, 0xf>(x), n);  // row_shr:8
+  x = addmod(x, dpp64<0x142, 0xa>(x), n);  // row_bcast:15 into rows 1 and 3
+  x = addmod(x, dpp64<0x143, 0xc>(x), n);  // row_bcast:31 into rows 2 and 3
+  return x;
+}
+
+__device__ __forceinline__ u64 lane_value(u64 v, int lane) {
+  const u32 lo = (u32)__builtin_amdgcn_readlane((int)lo32(v), lane);
+  const u32 hi = (u32)__builtin_amdgcn_readlane((int)hi32(v), lane);
+  return ((u64)hi << 32) | lo;
+}
+
 // ---------------------------------------------------------------------------
 // look-back words: (tag << 32) | half, two words per 64-bit value
 // ---------------------------------------------------------------------------
@@ -87,7 +135,7 @@ __device__ u64 look_back(const LaunchArgs& a, u32 t, u32 first, u32 tag, u64 n, 
     int stop = imask ? __ffsll((unsigned long long)imask) - 1 : 64;
     u64 contrib = 0;
     if (valid) contrib = lane < stop ? va : (lane == stop ? vi : 0);
-    acc = addmod(acc, wave_sum_mod(contrib, n), n);
+    acc = addmod(acc, lane_value(wave_scan_mod(contrib, n), 63), n);
     if (imask) return acc;
     pos -= 64;
   }
@@ -145,6 +193,10 @@ __device__ __forceinline__ void fixed128(double r, u64& lo, u64& hi) {
   }
 }
 
+// Row stride (64-bit words) of a wave's transpose buffer: 8 values per lane
+// plus one word of padding against LDS bank conflicts.
+constexpr int kXRow = 9;
+
 template <int WG, int MODE>
 struct TileShared {
   u32 tile;
@@ -152,6 +204,8 @@ struct TileShared {
   u64 wave_tot[WG / 64];
   u64 red[MODE == kModeConsume ? (WG / 64) * 6 : 1];
   u32 hist[MODE == kModeConsume ? 1024 : 1];
+  // generate: per wave, c and r of its 64 x 8 outputs for the coalescing transpose
+  u64 xbuf[MODE == kModeGenerate ? (WG / 64) * 2 * 64 * kXRow : 1];
 };
 
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
@@ -166,7 +220,35 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
   if constexpr (MODE == kModeGenerate) {
     u64* const oc = a.out_c;
     double* const orr = a.out_r;
-    if constexpr (FAST) {
+    if constexpr (FAST && V == 8) {
+      // Each lane's 8 results go to its row of the wave's LDS buffer as they are
+      // produced; then store j writes elements 64 j + lane of the chunk, so every
+      // store instruction covers 512 contiguous bytes (full cache lines).
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      u64* xc = sh.xbuf + wave * (2 * 64 * kXRow);
+      u64* xr = xc + 64 * kXRow;
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        double cd;
+        const u64 c = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
+        xc[lane * kXRow + i] = c;
+        xr[lane * kXRow + i] = (u64)__double_as_longlong(ratio(cd, P.nd, P.nrcp));
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const u64 chunk0 = C.out_off + (laneStart - (u64)lane * V - C.k0);
+      const int src = (lane >> 3) * kXRow + (lane & 7);
+#pragma unroll
+      for (int j = 0; j < V; ++j) {
+        const u64 off = chunk0 + (u64)j * 64 + lane;
+        if (oc) oc[off] = xc[j * 8 * kXRow + src];
+        if (orr) reinterpret_cast<u64*>(orr)[off] = xr[j * 8 * kXRow + src];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else if constexpr (FAST) {
       const u64 off0 = C.out_off + (laneStart - C.k0);
 #pragma unroll
       for (int i = 0; i < V; i += 2) {
@@ -260,30 +342,10 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
   }
 }
 
-// Tile body shared by both prefix modes once the message before the tile (or
-// its chain start) is known.  Returns after outputs and the chain-end state.
-template <int WG, int V, int VAR, int MODE, int PREFIX>
-__device__ __forceinline__ void tile_body(const LaunchArgs& a, TileShared<WG, MODE>& sh, u32 t,
-                                          u64 my_powv, u32 tag) {
-  constexpr int T = WG * V;
-  constexpr int NW = WG / 64;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const u32 c = uniform(a.tile_chain[t]);
-  const Chain C = a.chain[c];
-  const rsaprng_params P = a.inst[C.inst];
-  const u64 n = P.n;
-  const u32 j = t - C.first;
-  const u64 tileStart = C.S + (u64)j * T;
-
-  // start skip of the tile: from k_sums, or from the chain start and a^(jT)
-  u64 s_tile;
-  if constexpr (PREFIX == kPrefixTwoPass) s_tile = a.s_tile[t];
-  else s_tile = mulmod_q(a.cstart[c].s_S, a.at[j]);
-
-  // walk: V skips per lane, running sums mod n
-  const u64 laneStart = tileStart + (u64)threadIdx.x * V;
-  u64 X[V];
-  const u64 s_first = mulmod_q(s_tile, my_powv);
+// Walk of one lane: V skips from s_first (eq. congruentialgenerator1), running
+// sums mod n in X.  Returns the lane total.
+template <int V>
+__device__ __forceinline__ u64 walk(u64 s_first, u64 n, u64 (&X)[V]) {
   u64 s = s_first;
   u64 x = 0;
 #pragma unroll
@@ -292,72 +354,53 @@ __device__ __forceinline__ void tile_body(const LaunchArgs& a, TileShared<WG, MO
     x = addmod(x, skip_mod_n(s, n), n);
     X[i] = x;
   }
+  return x;
+}
 
-  // scan: lane offsets inside the wave, wave totals through LDS
-  u64 incl = x;
+// Inclusive scan mod n over the wave (lane offsets of the messages).
+__device__ __forceinline__ u64 wave_scan_shfl(u64 x, u64 n, int lane) {
 #pragma unroll
   for (int d = 1; d < 64; d <<= 1) {
-    u64 y = __shfl_up(incl, d, 64);
-    if (lane >= d) incl = addmod(incl, y, n);
+    const u64 y = __shfl_up(x, d, 64);
+    if (lane >= d) x = addmod(x, y, n);
   }
-  u64 lane_excl = __shfl_up(incl, 1, 64);
-  if (lane == 0) lane_excl = 0;
-  if (lane == 63) sh.wave_tot[wave] = incl;
-  __syncthreads();
-  u64 wave_off = 0, agg = 0;
-#pragma unroll
-  for (int w = 0; w < NW; ++w) {
-    const u64 v = sh.wave_tot[w];
-    if (w < wave) wave_off = addmod(wave_off, v, n);
-    agg = addmod(agg, v, n);
-  }
-  u64 E;
-  if constexpr (PREFIX == kPrefixTwoPass) {
-    E = a.excl[t];
-  } else {
-    if (wave == 0) {
-      u64 Ew;
-      if (j == 0) {
-        Ew = a.cstart[c].m_base;
-      } else {
-        if (lane == 0) publish(a.lb + 4ull * t, tag, agg);
-        Ew = look_back(a, t, C.first, tag, n, lane);
-      }
-      if (lane == 0) {
-        publish(a.lb + 4ull * t + 2, tag, addmod(Ew, agg, n));
-        sh.pre = Ew;
-      }
-    }
-    __syncthreads();
-    E = sh.pre;
-  }
-  const u64 pre = addmod(addmod(E, wave_off, n), lane_excl, n);
+  return x;
+}
 
-  // outputs (only tiles that reach the requested range)
-  if (tileStart + (T - 1) >= C.k0) {
-    const u64 off_t = C.out_off + (tileStart - C.k0);
-    const bool fast = tileStart >= C.k0 && tileStart + (T - 1) <= C.last &&
-                      (MODE == kModeConsume ||
-                       ((!a.out_c || ((uintptr_t)(a.out_c + off_t) & 15) == 0) &&
-                        (!a.out_r || ((uintptr_t)(a.out_r + off_t) & 15) == 0)));
-    if (fast) {
-      switch (P.e) {
-        case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, pre, X, laneStart); break;
-        case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, pre, X, laneStart); break;
-        case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, pre, X, laneStart); break;
-        case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, pre, X, laneStart); break;
-        case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, pre, X, laneStart); break;
-        case 257: tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, pre, X, laneStart); break;
-        case 65537:
-          tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, pre, X, laneStart);
-          break;
-        default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, pre, X, laneStart); break;
-      }
-    } else {
-      tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, pre, X, laneStart);
+// Outputs of one wave chunk (64 V indices starting at chunkStart) whose lanes
+// hold the running sums X and the message before their first index `pre`.
+template <int WG, int V, int VAR, int MODE>
+__device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
+                                              const Chain& C, const rsaprng_params& P, u64 pre,
+                                              const u64 (&X)[V], u64 chunkStart, u64 laneStart) {
+  constexpr u64 CHUNK = 64ull * V;
+  const u64 off_c = C.out_off + (chunkStart - C.k0);
+  const bool fast = chunkStart >= C.k0 && chunkStart + (CHUNK - 1) <= C.last &&
+                    (MODE == kModeConsume ||
+                     ((!a.out_c || ((uintptr_t)(a.out_c + off_c) & 15) == 0) &&
+                      (!a.out_r || ((uintptr_t)(a.out_r + off_c) & 15) == 0)));
+  if (fast) {
+    switch (P.e) {
+      case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, pre, X, laneStart); break;
+      case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, pre, X, laneStart); break;
+      case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, pre, X, laneStart); break;
+      case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, pre, X, laneStart); break;
+      case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, pre, X, laneStart); break;
+      case 257: tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, pre, X, laneStart); break;
+      case 65537:
+        tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, pre, X, laneStart);
+        break;
+      default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, pre, X, laneStart); break;
     }
+  } else {
+    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, pre, X, laneStart);
   }
-  // chain-end state for a continued request: the lane holding the last index
+}
+
+// Chain-end state for a continued request: the lane holding the last index.
+template <int V>
+__device__ __forceinline__ void chain_end(const LaunchArgs& a, const Chain& C, u64 n, u64 pre,
+                                          const u64 (&X)[V], u64 s_first, u64 laneStart) {
   if ((C.flags & kChainWriteEnd) && laneStart <= C.last && C.last - laneStart < (u64)V) {
     u64 m_end = 0;
     u64 ss = s_first;
@@ -373,69 +416,185 @@ __device__ __forceinline__ void tile_body(const LaunchArgs& a, TileShared<WG, MO
   }
 }
 
-template <int WG, int V, int VAR, int MODE, int PREFIX>
-__global__ __launch_bounds__(WG) void k_gen(LaunchArgs a) {
+// Two passes: each wave owns R consecutive chunks of 64 V indices of the tile
+// (T = WG V R) and processes them one after the other; the message before a
+// chunk comes from k_scan and its start skip from the tile's skip and a^(64 V q
+// + V lane), so waves never wait on each other.  The next chunk's prefix and
+// offset power are loaded while the current chunk computes.
+template <int WG, int V, int R, int VAR, int MODE>
+__global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
+  constexpr int NW = WG / 64;
+  constexpr int CH = NW * R;  // chunks per tile
+  constexpr u64 T = (u64)WG * V * R;
+  constexpr u64 CHUNK = 64ull * V;
   __shared__ TileShared<WG, MODE> sh;
+  const int lane = threadIdx.x & 63;
+  const u32 wave = uniform(threadIdx.x >> 6);
+  // per-lane offset powers of the wave's chunks, loaded before any store
+  u64 pv[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) pv[r] = a.powv[((u64)wave * R + r) * 64 + lane];
+  if constexpr (MODE == kModeConsume) {
+    for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
+    __syncthreads();
+  }
+  for (u32 t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    const u32 c = cst(a.tile_chain)[t];
+    const Chain C = load_cst(a.chain + c);
+    const rsaprng_params P = load_cst(a.inst + C.inst);
+    const u64 n = P.n;
+    const u64 tileStart = C.S + (u64)(t - C.first) * T;
+    const u64 s_tile = cst(a.s_tile)[t];
+    const u64 q0 = (u64)wave * R;  // first chunk of this wave
+    u64 E[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) E[r] = cst(a.excl)[(u64)t * CH + q0 + r];
+    const bool any_out = tileStart + (T - 1) >= C.k0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const u64 chunkStart = tileStart + (q0 + r) * CHUNK;
+      const u64 laneStart = chunkStart + (u64)lane * V;
+      const bool outs = MODE == kModeConsume ? any_out : chunkStart + (CHUNK - 1) >= C.k0;
+      if (!outs && !(C.flags & kChainWriteEnd)) continue;
+      u64 X[V];
+      const u64 s_first = mulmod_q(s_tile, pv[r]);
+      const u64 x = walk<V>(s_first, n, X);
+      const u64 incl = wave_scan_shfl(x, n, lane);
+      const u64 pre = addmod(E[r], submod(incl, x, n), n);
+      if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, pre, X, chunkStart, laneStart);
+      chain_end<V>(a, C, n, pre, X, s_first, laneStart);
+    }
+  }
+}
+
+// One pass: tiles of T = WG V claimed from an atomic queue; the wave totals go
+// through LDS and the message before the tile comes from the look-back.
+template <int WG, int V, int VAR, int MODE>
+__global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
+  constexpr int NW = WG / 64;
+  constexpr u64 T = (u64)WG * V;
+  __shared__ TileShared<WG, MODE> sh;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const u64 my_powv = a.powv[threadIdx.x];
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
   }
-  if constexpr (PREFIX == kPrefixTwoPass) {
-    for (u32 t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-      tile_body<WG, V, VAR, MODE, PREFIX>(a, sh, t, my_powv, 0);
-      __syncthreads();  // LDS reuse by the next tile
+  const u32 tag = a.ctl->epoch;
+  for (;;) {
+    if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctl->counter, 1u);
+    __syncthreads();
+    const u32 t = uniform(sh.tile);
+    if (t >= a.ntiles) break;
+    const u32 c = uniform(a.tile_chain[t]);
+    const Chain C = a.chain[c];
+    const rsaprng_params P = a.inst[C.inst];
+    const u64 n = P.n;
+    const u32 j = t - C.first;
+    const u64 tileStart = C.S + (u64)j * T;
+    const u64 s_tile = mulmod_q(a.cstart[c].s_S, a.at[j]);
+    const u64 laneStart = tileStart + (u64)threadIdx.x * V;
+    u64 X[V];
+    const u64 s_first = mulmod_q(s_tile, my_powv);
+    const u64 x = walk<V>(s_first, n, X);
+    const u64 incl = wave_scan_shfl(x, n, lane);
+    if (lane == 63) sh.wave_tot[wave] = incl;
+    __syncthreads();
+    u64 wave_off = 0, agg = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const u64 v = sh.wave_tot[w];
+      if (w < wave) wave_off = addmod(wave_off, v, n);
+      agg = addmod(agg, v, n);
     }
-  } else {
-    const u32 tag = a.ctl->epoch;
-    for (;;) {
-      if (threadIdx.x == 0) sh.tile = atomicAdd(&a.ctl->counter, 1u);
-      __syncthreads();
-      const u32 t = uniform(sh.tile);
-      if (t >= a.ntiles) break;
-      tile_body<WG, V, VAR, MODE, PREFIX>(a, sh, t, my_powv, tag);
-      __syncthreads();
+    if (wave == 0) {
+      u64 Ew;
+      if (j == 0) {
+        Ew = a.cstart[c].m_base;
+      } else {
+        if (lane == 0) publish(a.lb + 4ull * t, tag, agg);
+        Ew = look_back(a, t, C.first, tag, n, lane);
+      }
+      if (lane == 0) {
+        publish(a.lb + 4ull * t + 2, tag, addmod(Ew, agg, n));
+        sh.pre = Ew;
+      }
     }
+    __syncthreads();
+    const u64 pre = addmod(addmod(sh.pre, wave_off, n), submod(incl, x, n), n);
+    if (tileStart + (T - 1) >= C.k0) {
+      // the fast path is decided per tile here so every wave takes the same barriers
+      const u64 off_t = C.out_off + (tileStart - C.k0);
+      const bool fast = tileStart >= C.k0 && tileStart + (T - 1) <= C.last &&
+                        (MODE == kModeConsume ||
+                         ((!a.out_c || ((uintptr_t)(a.out_c + off_t) & 15) == 0) &&
+                          (!a.out_r || ((uintptr_t)(a.out_r + off_t) & 15) == 0)));
+      if (fast) {
+        switch (P.e) {
+          case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, pre, X, laneStart); break;
+          case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, pre, X, laneStart); break;
+          case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, pre, X, laneStart); break;
+          case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, pre, X, laneStart); break;
+          case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, pre, X, laneStart); break;
+          case 257:
+            tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, pre, X, laneStart);
+            break;
+          case 65537:
+            tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, pre, X, laneStart);
+            break;
+          default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, pre, X, laneStart); break;
+        }
+      } else {
+        tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, pre, X, laneStart);
+      }
+    }
+    chain_end<V>(a, C, n, pre, X, s_first, laneStart);
+    __syncthreads();
   }
 }
 
-template <int WG, int V, int VAR, int MODE, int PREFIX>
-static int launch_one(const LaunchArgs& a, int grid, void* stream) {
-  hipLaunchKernelGGL((k_gen<WG, V, VAR, MODE, PREFIX>), dim3(grid), dim3(WG), 0,
-                     (hipStream_t)stream, a);
+template <int WG, int V, int R, int VAR, int MODE>
+static int launch2(const LaunchArgs& a, int grid, void* stream, int* occ) {
+  if (occ) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen2<WG, V, R, VAR, MODE>, WG, 0) !=
+        hipSuccess)
+      blocks = 1;
+    *occ = blocks > 0 ? blocks : 1;
+    return RSAPRNG_OK;
+  }
+  hipLaunchKernelGGL((k_gen2<WG, V, R, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream,
+                     a);
   return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
-template <int WG, int V, int VAR, int MODE, int PREFIX>
-static int occupancy_of() {
-  int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen<WG, V, VAR, MODE, PREFIX>, WG,
-                                                   0) != hipSuccess)
-    return 1;
-  return blocks > 0 ? blocks : 1;
-}
-
 template <int WG, int V, int VAR, int MODE>
-static int launch_shape(const KernelShape& s, const LaunchArgs& a, void* stream, int* occ) {
-  if (s.prefix == kPrefixTwoPass) {
-    if (occ) {
-      *occ = occupancy_of<WG, V, VAR, MODE, kPrefixTwoPass>();
-      return RSAPRNG_OK;
-    }
-    return launch_one<WG, V, VAR, MODE, kPrefixTwoPass>(a, s.grid, stream);
-  }
+static int launch1(const LaunchArgs& a, int grid, void* stream, int* occ) {
   if (occ) {
-    *occ = occupancy_of<WG, V, VAR, MODE, kPrefixLookback>();
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen1<WG, V, VAR, MODE>, WG, 0) !=
+        hipSuccess)
+      blocks = 1;
+    *occ = blocks > 0 ? blocks : 1;
     return RSAPRNG_OK;
   }
-  return launch_one<WG, V, VAR, MODE, kPrefixLookback>(a, s.grid, stream);
+  hipLaunchKernelGGL((k_gen1<WG, V, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream, a);
+  return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
-// Launcher and occupancy query for every tile shape of one (variant, mode).
+// Launcher and occupancy query for every shape of one (variant, mode).
 template <int VAR, int MODE>
 int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* occ) {
-  if (s.wg == 256 && s.v == 16) return launch_shape<256, 16, VAR, MODE>(s, a, stream, occ);
-  if (s.wg == 256 && s.v == 8) return launch_shape<256, 8, VAR, MODE>(s, a, stream, occ);
-  if (s.wg == 128 && s.v == 16) return launch_shape<128, 16, VAR, MODE>(s, a, stream, occ);
+  if (s.prefix == kPrefixTwoPass) {
+    if (s.wg == 256 && s.v == 8 && s.r == 1) return launch2<256, 8, 1, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 256 && s.v == 8 && s.r == 2) return launch2<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 256 && s.v == 8 && s.r == 4) return launch2<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 512 && s.v == 8 && s.r == 2) return launch2<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+    return RSAPRNG_E_ARG;
+  }
+  if (s.r != 1) return RSAPRNG_E_ARG;
+  if (s.wg == 256 && s.v == 8) return launch1<256, 8, VAR, MODE>(a, s.grid, stream, occ);
+  if (s.wg == 512 && s.v == 8) return launch1<512, 8, VAR, MODE>(a, s.grid, stream, occ);
+  if (s.wg == 256 && s.v == 16) return launch1<256, 16, VAR, MODE>(a, s.grid, stream, occ);
   return RSAPRNG_E_ARG;
 }
 

@@ -15,7 +15,7 @@ import threading
 from typing import Iterable, List, Optional, Sequence
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "librsaprng.so")
+LIB_PATH = os.environ.get("RSAPRNG_LIB") or os.path.join(HERE, "librsaprng.so")
 
 BLOCK_LOG2 = 20
 Q = 9223372036854775783
@@ -61,7 +61,7 @@ class rsaprng_pool_req(C.Structure):
 class rsaprng_config(C.Structure):
     _fields_ = [("variant", C.c_int), ("lanes_per_tile", C.c_int), ("per_lane", C.c_int),
                 ("persistent", C.c_int), ("wg_per_cu", C.c_int), ("order", C.c_int),
-                ("prefix", C.c_int)]
+                ("prefix", C.c_int), ("chunks_per_wave", C.c_int)]
 
     def as_dict(self):
         return {f: getattr(self, f) for f, _ in self._fields_}
@@ -176,8 +176,10 @@ def _u64arr(vals: Sequence[int]):
     return arr
 
 
-def config(variant=0, lanes_per_tile=0, per_lane=0, persistent=0, wg_per_cu=0, order=0, prefix=0):
-    return rsaprng_config(variant, lanes_per_tile, per_lane, persistent, wg_per_cu, order, prefix)
+def config(variant=0, lanes_per_tile=0, per_lane=0, persistent=0, wg_per_cu=0, order=0, prefix=0,
+           chunks_per_wave=0):
+    return rsaprng_config(variant, lanes_per_tile, per_lane, persistent, wg_per_cu, order, prefix,
+                          chunks_per_wave)
 
 
 # --------------------------------------------------------------------------

@@ -74,11 +74,12 @@ def test_ragged_ranges_both_variants(R, k0, count):
     inst = inputs.config1()
     cref, rref = oracle_gen(inst, k0, count)
     for var, name in _variants(R):
-        for shape in ((256, 16), (256, 8), (128, 16)):
-            for prefix in (0, 1):
+        for shape in ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
+                      (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1)):
+            for prefix in (shape[3],):
                 log("ragged", name, shape, "prefix", prefix, k0, count)
                 cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
-                               prefix=prefix)
+                               chunks_per_wave=shape[2], prefix=prefix)
                 c, r, _ = _gen_pool(R, [inst], [(0, k0, count)], cfg)
                 assert_same(c, r, cref, rref, "%s %s %d k0=%d" % (name, shape, prefix, k0))
 
@@ -155,12 +156,14 @@ def test_substreams_config2_subset_all_shapes(R):
     rref = np.concatenate([x[1] for x in refs])
     from paper_1811_11629_amd import rsaprng
     for var in (R.VARIANT_MONT, R.VARIANT_CRT):
-        for shape in ((256, 16), (256, 8), (128, 16)):
+        for shape in ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
+                      (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1)):
             for pers in (0, 1):
-                for prefix in (0, 1):
+                for prefix in (shape[3],):
                     log("config2 subset", var, shape, pers, prefix)
                     cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
-                                   persistent=pers, order=pers, prefix=prefix)
+                                   chunks_per_wave=shape[2], persistent=pers, order=pers,
+                                   prefix=prefix)
                     c, r, _ = _gen_pool(R, insts, ranges, cfg)
                     assert_same(c, r, cref, rref, "config2 %s %s %s %s" % (var, shape, pers, prefix))
 
@@ -176,12 +179,14 @@ def test_consume_matches_oracle(R):
               for k0, cnt in ((0, 1 << 18), (B - 3000, 9000), ((1 << 40) + 5, 4097))]
     pool = R.Pool.from_instances(cases)
     for (var, name), (shape, prefix) in [(v, sp) for v in _variants(R)
-                                         for sp in (((256, 16), 0), ((256, 8), 1), ((128, 16), 0))]:
+                                         for sp in (((256, 8, 4), 0), ((256, 8, 1), 1),
+                                                    ((512, 8, 2), 0), ((256, 16, 1), 1))]:
         log("consume", name, shape, prefix)
         st = R.stats_tensor(len(ranges))
         R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx) for idx, (j, k0, cnt) in enumerate(ranges)],
                                st, cfg=R.config(variant=var, lanes_per_tile=shape[0],
-                                                per_lane=shape[1], prefix=prefix))
+                                                per_lane=shape[1], chunks_per_wave=shape[2],
+                                                prefix=prefix))
         R.rsaprng_check_device_error()
         got = R.stats_decode(st)
         for idx, (j, k0, cnt) in enumerate(ranges):
