@@ -57,11 +57,28 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   const u64 s_tile = mulmod_q(a.cstart[c].s_S, a.at[j]);
   u64 s = mulmod_q(s_tile, a.pl[lane]);
   const int per = 1 << (a.tile_log2 - 6);
-  u64 x = skip_mod_n(s, n);
+  // exact integer sum of the lane's skips: lo + 2^64 hi, hi < per / 2 (skips < 2^63)
+  u64 lo = s, hi = 0;
   for (int i = 1; i < per; ++i) {
     s = lcg_next(s);
-    x = addmod(x, skip_mod_n(s, n), n);
+    const u64 t2 = lo + s;
+    hi += t2 < lo;
+    lo = t2;
   }
+  // reduce mod n: lo mod n (lo < 2^64 <= 4n), plus hi (2^64 mod n) by doubling
+  u64 x = lo;
+  x = x >= n ? x - n : x;
+  x = x >= n ? x - n : x;
+  x = x >= n ? x - n : x;
+  u64 r64 = 0 - n;  // 2^64 - n < 3n
+  r64 = r64 >= n ? r64 - n : r64;
+  r64 = r64 >= n ? r64 - n : r64;
+  u64 h = 0;
+  for (int b = 31 - __builtin_clz(per); b >= 0; --b) {
+    h = addmod(h, h, n);
+    if ((hi >> b) & 1) h = addmod(h, r64, n);
+  }
+  x = addmod(x, h, n);
   const int nw_log2 = a.tile_log2 - a.chunk_log2;     // wave chunks per tile
   const int group = 64 >> nw_log2;                     // lanes per chunk
   // chunk sums as differences of the inclusive scan at the chunk boundaries

@@ -204,8 +204,8 @@ struct TileShared {
   u64 wave_tot[WG / 64];
   u64 red[MODE == kModeConsume ? (WG / 64) * 6 : 1];
   u32 hist[MODE == kModeConsume ? 1024 : 1];
-  // generate: per wave, c and r of its 64 x 8 outputs for the coalescing transpose
-  u64 xbuf[MODE == kModeGenerate ? (WG / 64) * 2 * 64 * kXRow : 1];
+  // generate: per wave, one 64 x 8 block of results for the coalescing transpose
+  u64 xbuf[MODE == kModeGenerate ? (WG / 64) * 64 * kXRow : 1];
 };
 
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
@@ -224,30 +224,37 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       // Each lane's 8 results go to its row of the wave's LDS buffer as they are
       // produced; then store j writes elements 64 j + lane of the chunk, so every
       // store instruction covers 512 contiguous bytes (full cache lines).
+      // c goes through the buffer first while r waits in registers, then r.
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      u64* xc = sh.xbuf + wave * (2 * 64 * kXRow);
-      u64* xr = xc + 64 * kXRow;
+      u64* xb = sh.xbuf + wave * (64 * kXRow);
+      u64 rb[V];
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         double cd;
         const u64 c = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
-        xc[lane * kXRow + i] = c;
-        xr[lane * kXRow + i] = (u64)__double_as_longlong(ratio(cd, P.nd, P.nrcp));
+        xb[lane * kXRow + i] = c;
+        rb[i] = (u64)__double_as_longlong(ratio(cd, P.nd, P.nrcp));
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       const u64 chunk0 = C.out_off + (laneStart - (u64)lane * V - C.k0);
       const int src = (lane >> 3) * kXRow + (lane & 7);
 #pragma unroll
-      for (int j = 0; j < V; ++j) {
-        const u64 off = chunk0 + (u64)j * 64 + lane;
-        if (oc) oc[off] = xc[j * 8 * kXRow + src];
-        if (orr) reinterpret_cast<u64*>(orr)[off] = xr[j * 8 * kXRow + src];
+      for (int half = 0; half < 2; ++half) {
+        u64* const dst = half == 0 ? oc : reinterpret_cast<u64*>(orr);
+        if (half == 1) {
+#pragma unroll
+          for (int i = 0; i < V; ++i) xb[lane * kXRow + i] = rb[i];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if (dst) {
+#pragma unroll
+          for (int j = 0; j < V; ++j) dst[chunk0 + (u64)j * 64 + lane] = xb[j * 8 * kXRow + src];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else if constexpr (FAST) {
       const u64 off0 = C.out_off + (laneStart - C.k0);
 #pragma unroll
