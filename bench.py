@@ -12,8 +12,10 @@ rsaprng_generate launches round-robin over 4 streams; the exponent sweep in
 fused-consume mode (4096 instances x 2^18 outputs per e, no HBM write); the
 batched uneven workload (10,000 instances, lengths log-uniform in [2^8, 2^22],
 start indices below 2^40) as one graph-captured persistent launch, beside its
-plain per-request launches; the roofline of the tile kernel; and the CPU
-oracle timed on the host's cores on a bounded sample.
+plain per-request launches; the served workload (100,000 device-resident
+instances, Poisson arrivals, continuous batching: p50/p99 latency and
+throughput at a fixed offered load); the roofline of the tile kernel; and the
+CPU oracle timed on the host's cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -231,6 +233,84 @@ def run_batched_uneven(R, torch, stream, steps):
     return res
 
 
+def run_served(R, torch, stream, cfg, rho_main=0.7, sweep=(0.5, 0.9)):
+    """Served workload: 100,000 device-resident instances, requests (instance
+    uniform, k0 < 2^40, length log-uniform in [2^10, 2^24)) arriving as a Poisson
+    stream; continuous batching with a 64 GiB output arena.  Offered load is a
+    fraction rho of the server's own saturated capacity (every request of a
+    trace submitted at once)."""
+    import numpy as np
+
+    import inputs
+    t0 = time.perf_counter()
+    insts, rng = inputs.config5_instances(100000)
+    log("served pool drawn in %.1f s" % (time.perf_counter() - t0))
+    pool = R.Pool.from_instances(insts)
+    mean_count = 2.0 ** 10 * (2.0 ** 14 - 1) / (14 * np.log(2.0))   # E[2^(10+14u)], u uniform
+    srv = R.Server(pool, arena_bytes=64 << 30, cfg=cfg)
+
+    def trace(n):
+        reqs = inputs.config5_requests(rng, len(insts), n)
+        return (np.array([r.inst for r in reqs], dtype=np.uint32),
+                np.array([r.k0 for r in reqs], dtype=np.uint64),
+                np.array([r.count for r in reqs], dtype=np.uint64))
+
+    res = {"workload": "100000 instances (e from {3,5,7,17,257,65537}), requests: instance "
+                       "uniform, k0 < 2^40, count = floor(2^(10+14u)); Poisson arrivals; "
+                       "64 GiB output arena; u64+f64 outputs",
+           "config": cfg.as_dict()}
+    # saturated capacity: a trace submitted at once
+    inst, k0, cnt = trace(40000)
+    t_adm, t_done = srv.replay(inst, k0, cnt, np.zeros(len(inst)))
+    cap = float(cnt.sum()) / float(t_done.max()) / 1e9
+    res["saturated_gnumbers_per_s"] = cap
+    log("served saturated: %.1f Gnum/s over %d requests" % (cap, len(inst)))
+    # the same requests as plain per-request launches on one stream
+    n_plain = 4000
+    oc = torch.empty(int(cnt[:n_plain].max()), dtype=torch.int64, device="cuda")
+    orr = torch.empty_like(oc, dtype=torch.float64)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for j in range(n_plain):
+        R.rsaprng_pool_generate(pool, [(int(inst[j]), int(k0[j]), int(cnt[j]), 0)], oc, orr,
+                                cfg=cfg, stream=stream)
+    torch.cuda.synchronize()
+    plain = float(cnt[:n_plain].sum()) / (time.perf_counter() - t1) / 1e9
+    R.rsaprng_check_device_error(stream)
+    res["plain_per_request_gnumbers_per_s"] = plain
+    res["saturated_vs_plain"] = cap / plain
+    del oc, orr
+    log("plain per-request launches: %.1f Gnum/s" % plain)
+
+    def poisson(rho, warm, steady):
+        lam = rho * cap * 1e9 / mean_count
+        n = int(lam * (warm + steady))
+        inst, k0, cnt = trace(n)
+        t_arr = inputs.poisson_arrivals(rng, lam, n)
+        t_adm, t_done = srv.replay(inst, k0, cnt, t_arr)
+        win = (t_arr >= warm) & (t_arr < warm + steady)
+        lat = (t_done - t_arr)[win]
+        span = float(t_done.max() - t_arr.min())
+        out = {"rho": rho, "arrival_rate_per_s": lam, "requests": n,
+               "window_requests": int(win.sum()), "warmup_s": warm, "steady_s": steady,
+               "offered_gnumbers_per_s": float(cnt[win].sum()) / steady / 1e9,
+               "served_gnumbers_per_s": float(cnt.sum()) / span / 1e9,
+               "p50_ms": float(np.percentile(lat, 50) * 1e3),
+               "p99_ms": float(np.percentile(lat, 99) * 1e3),
+               "mean_admit_wait_ms": float((t_adm - t_arr)[win].mean() * 1e3)}
+        log("served rho=%.2f: %.1f Gnum/s, p50 %.2f ms, p99 %.2f ms" % (
+            rho, out["served_gnumbers_per_s"], out["p50_ms"], out["p99_ms"]))
+        return out
+
+    res["headline"] = poisson(rho_main, 2.0, 10.0)
+    res["sweep"] = [poisson(r, 1.0, 4.0) for r in sweep]
+    st = srv.stats()
+    res["iterations"] = st["iterations"]
+    srv.close()
+    del pool
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -320,6 +400,7 @@ def main():
         torch.cuda.empty_cache()
         extras["exponent_sweep_consume"] = run_consume_sweep(R, torch, stream, args.steps)
         extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
+        extras["served"] = run_served(R, torch, stream, best)
 
     cpu = None if args.no_cpu else cpu_baseline(insts, 512 * B)
     if cpu:

@@ -245,11 +245,36 @@ int rsaprng_server_submit(rsaprng_server_t s, uint32_t inst, uint64_t k0, uint64
                           uint64_t tag);
 /* Returns the number of completions written (>= 0) or a status. */
 int rsaprng_server_poll(rsaprng_server_t s, rsaprng_completion* out, size_t max);
+/* Copies outputs [offset, offset + count) of a completed, unreleased request to
+ * dst_u64 / dst_f64 (host or device memory; either may be NULL) and waits for
+ * the copy on `stream`.  RSAPRNG_E_ARG if tag is not a completed request. */
+int rsaprng_server_read(rsaprng_server_t s, uint64_t tag, uint64_t offset, uint64_t count,
+                        uint64_t* dst_u64, double* dst_f64, void* stream);
+/* Frees a completed request's arena space; its completion pointers become invalid. */
 int rsaprng_server_release(rsaprng_server_t s, uint64_t tag);
 double rsaprng_server_now(rsaprng_server_t s);
 /* Iterations run, outputs produced, and requests waiting/active, for reports. */
 int rsaprng_server_stats(rsaprng_server_t s, uint64_t* iterations, uint64_t* outputs,
                          uint64_t* waiting, uint64_t* active);
+/* Open-loop load generator: submits request i (tag 2^63 + i) at t_arrival[i]
+ * seconds after the call (non-decreasing), releases each on completion, and
+ * returns when all have completed.  t_admit / t_done (may be NULL) receive the
+ * times relative to the same origin. */
+int rsaprng_server_replay(rsaprng_server_t s, size_t n, const uint32_t* inst, const uint64_t* k0,
+                          const uint64_t* count, const double* t_arrival, double* t_admit,
+                          double* t_done);
+/* Host-only dry run of the server's scheduler, for tests (no device).  Request i
+ * arrives before iteration arrive_iter[i] (non-decreasing); every iteration
+ * completes before the next; a finished request is released hold_iters
+ * iterations later.  One record of seven words per planned chunk -- request,
+ * iteration, first index, count, arena offset, flags (1 continues from saved
+ * state, 2 saves state at its end), state slot -- is written to log while
+ * fewer than max_log have been written.  Returns the number of chunks or a status. */
+int64_t rsaprng_server_simulate(const rsaprng_config* cfg, uint64_t arena_elems,
+                                uint64_t iter_outputs, uint64_t chunk_outputs, size_t n,
+                                const uint64_t* k0, const uint64_t* count,
+                                const uint64_t* arrive_iter, uint64_t hold_iters, uint64_t* log,
+                                size_t max_log);
 void rsaprng_server_destroy(rsaprng_server_t s);
 
 /* ---------------------------------------------------------------------------

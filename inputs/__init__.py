@@ -24,6 +24,10 @@ Recipes (one per workload; the draw order below is part of the definition):
 """
 from __future__ import annotations
 
+import ctypes
+import os
+import subprocess
+import threading
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
@@ -99,9 +103,60 @@ def _is_prime32_many(xs: np.ndarray) -> np.ndarray:
     return out
 
 
-def _next_prime_many(xs: np.ndarray, filt) -> np.ndarray:
-    """Smallest prime >= x passing ``filt`` for each x (0 where none <= 4294967291)."""
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SIEVE_SRC = os.path.join(_HERE, "primes.c")
+_SIEVE_LIB = os.path.join(_HERE, "libprimes.so")
+_sieve_lock = threading.Lock()
+_sieve = None
+SIEVE_MIN = 20000   # query counts from which the sieve beats trial division
+
+
+def build_sieve(force: bool = False) -> str:
+    """Compile the segmented-sieve helper (primes.c) with gcc when stale."""
+    stale = (not os.path.exists(_SIEVE_LIB) or
+             os.path.getmtime(_SIEVE_LIB) < os.path.getmtime(_SIEVE_SRC))
+    if force or stale:
+        tmp = _SIEVE_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-o", tmp,
+                               _SIEVE_SRC])
+        os.replace(tmp, _SIEVE_LIB)
+    return _SIEVE_LIB
+
+
+def _sieve_lib():
+    global _sieve
+    with _sieve_lock:
+        if _sieve is None:
+            L = ctypes.CDLL(build_sieve())
+            L.next_primes.restype = ctypes.c_int
+            L.next_primes.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p,
+                                      ctypes.c_int, ctypes.c_void_p]
+            _sieve = L
+    return _sieve
+
+
+def next_primes_sieve(xs, exps: Sequence[int] = ()) -> np.ndarray:
+    """Smallest prime >= x with p mod f != 1 for each f in exps, for x in
+    [2^31, 2^32), by a segmented sieve (0 where there is none below 2^32)."""
+    q = np.ascontiguousarray(xs, dtype=np.uint64)
+    if q.size and (int(q.min()) < (1 << 31) or int(q.max()) >= (1 << 32)):
+        raise ValueError("sieve queries must lie in [2^31, 2^32)")
+    ex = np.ascontiguousarray(list(exps) or [0], dtype=np.uint32)
+    out = np.zeros(q.size, dtype=np.uint64)
+    rc = _sieve_lib().next_primes(q.ctypes.data, q.size, ex.ctypes.data, len(exps),
+                                  out.ctypes.data)
+    if rc:
+        raise MemoryError("sieve")
+    return out.astype(np.int64)
+
+
+def _next_prime_many(xs: np.ndarray, filt, exps: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Smallest prime >= x passing ``filt`` for each x (0 where none <= 4294967291).
+    With ``exps`` given (the filter's exponents) and many queries, the segmented
+    sieve answers instead of trial division; both give the same exact result."""
     xs = np.asarray(xs, dtype=np.int64)
+    if exps is not None and xs.size >= SIEVE_MIN:
+        return next_primes_sieve(xs, exps)
     res = np.zeros(xs.shape, dtype=np.int64)
     cand = xs.copy()
     cand[cand % 2 == 0] += 1
@@ -183,7 +238,7 @@ def draw_instances_rng(rng: SplitMix64, count: int, filt_exps: Sequence[int] = (
         xs = np.array([(1 << 31) + (u >> 33) for u in us], dtype=np.int64)
         need = [i for i, x in enumerate(xs) if int(x) not in cache]
         if need:
-            ps = _next_prime_many(xs[need], filt)
+            ps = _next_prime_many(xs[need], filt, tuple(filt_exps))
             for i, pv in zip(need, ps):
                 cache[int(xs[i])] = int(pv)
 

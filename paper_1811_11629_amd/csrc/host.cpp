@@ -810,6 +810,7 @@ namespace rsaprng {
 
 const rsaprng_params* pool_dev(rsaprng_pool_t pool) { return pool->dev; }
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i) { return pool->host[i]; }
+int pool_device(rsaprng_pool_t pool) { return pool->device; }
 
 int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
               const rsaprng_config& c, std::vector<Chain>& plan, u64h* ntiles) {

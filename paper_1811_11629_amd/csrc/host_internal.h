@@ -72,5 +72,6 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    ChainState* state, void* stream);
 const rsaprng_params* pool_dev(rsaprng_pool_t pool);
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i);
+int pool_device(rsaprng_pool_t pool);
 
 }  // namespace rsaprng

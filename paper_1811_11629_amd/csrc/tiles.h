@@ -340,12 +340,15 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       if (tc) atomicAdd((unsigned long long*)&st->count, (unsigned long long)tc);
     }
     for (int b = threadIdx.x; b < 1024; b += WG) {
-      u32 h = sh.hist[b];
+      const u32 h = sh.hist[b];
       if (h) {
         atomicAdd((unsigned long long*)&st->hist[b], (unsigned long long)h);
         sh.hist[b] = 0;
       }
     }
+    // No wave may add to the histogram or the reduction slots of the next chunk
+    // (possibly another chain's record) before every bin of this one is flushed.
+    __syncthreads();
   }
 }
 

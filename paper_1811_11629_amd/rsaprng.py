@@ -29,6 +29,7 @@ STATUS = {
     -10: "RSAPRNG_E_HIP", -11: "RSAPRNG_E_BUSY", -12: "RSAPRNG_E_ARG", -13: "RSAPRNG_E_DEVICE",
     -14: "RSAPRNG_E_NO_DEVICE",
 }
+globals().update({name[len("RSAPRNG_"):]: code for code, name in STATUS.items() if code})
 VARIANT_AUTO, VARIANT_MONT, VARIANT_CRT = 0, 1, 2
 MODE_GENERATE, MODE_CONSUME = 0, 1
 
@@ -117,7 +118,11 @@ _SIGS = {
     "rsaprng_server_create": (_i32, [_vp, C.POINTER(rsaprng_server_opts), C.POINTER(_vp)]),
     "rsaprng_server_submit": (_i32, [_vp, _u32, _u64, _u64, _u64]),
     "rsaprng_server_poll": (_i32, [_vp, C.POINTER(rsaprng_completion), _sz]),
+    "rsaprng_server_read": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _vp]),
     "rsaprng_server_release": (_i32, [_vp, _u64]),
+    "rsaprng_server_replay": (_i32, [_vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "rsaprng_server_simulate": (C.c_int64, [C.POINTER(rsaprng_config), _u64, _u64, _u64, _sz,
+                                            _vp, _vp, _vp, _u64, _vp, _sz]),
     "rsaprng_server_now": (_dbl, [_vp]),
     "rsaprng_server_stats": (_i32, [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
                                     C.POINTER(_u64)]),
@@ -370,6 +375,30 @@ def stats_decode(t) -> List[dict]:
     return out
 
 
+def server_simulate(k0, count, arrive_iter, arena_elems, iter_outputs=0, chunk_outputs=0,
+                    hold_iters=0, cfg=None):
+    """Host-only dry run of the server's scheduler; returns an (nchunks, 7) uint64
+    array: request, iteration, first index, count, arena offset, flags, slot."""
+    import numpy as np
+    k0 = np.ascontiguousarray(k0, dtype=np.uint64)
+    count = np.ascontiguousarray(count, dtype=np.uint64)
+    arrive_iter = np.ascontiguousarray(arrive_iter, dtype=np.uint64)
+    c = cfg if cfg is not None else rsaprng_config()
+    n = len(k0)
+    nch = lib().rsaprng_server_simulate(C.byref(c), arena_elems, iter_outputs, chunk_outputs, n,
+                                        k0.ctypes.data, count.ctypes.data,
+                                        arrive_iter.ctypes.data, hold_iters, None, 0)
+    if nch < 0:
+        raise RsaprngError(int(nch), "rsaprng_server_simulate")
+    log = np.zeros((max(nch, 1), 7), dtype=np.uint64)
+    nch2 = lib().rsaprng_server_simulate(C.byref(c), arena_elems, iter_outputs, chunk_outputs, n,
+                                         k0.ctypes.data, count.ctypes.data,
+                                         arrive_iter.ctypes.data, hold_iters, log.ctypes.data,
+                                         nch)
+    assert nch2 == nch
+    return log[:nch]
+
+
 class Server:
     """An rsaprng_server_t (continuous batching over a pool)."""
 
@@ -393,8 +422,41 @@ class Server:
             raise RsaprngError(n, "rsaprng_server_poll")
         return [buf[i] for i in range(n)]
 
+    def read(self, tag: int, out_u64=None, out_f64=None, offset: int = 0, count=None,
+             stream=None) -> None:
+        """Copy a completed request's outputs into out_u64 / out_f64 (torch tensors
+        or numpy arrays, host or device)."""
+        def addr(x):
+            if x is None:
+                return None
+            if hasattr(x, "data_ptr"):
+                return x.data_ptr()
+            return x.ctypes.data
+        if count is None:
+            count = len(out_u64 if out_u64 is not None else out_f64)
+        _check(lib().rsaprng_server_read(self.h, tag, offset, count, addr(out_u64),
+                                         addr(out_f64), _stream(stream)),
+               "rsaprng_server_read")
+
     def release(self, tag: int) -> None:
         _check(lib().rsaprng_server_release(self.h, tag), "rsaprng_server_release")
+
+    def replay(self, inst, k0, count, t_arrival):
+        """Open-loop replay of a request trace (numpy arrays); returns (t_admit, t_done)
+        in seconds from the start of the replay."""
+        import numpy as np
+        inst = np.ascontiguousarray(inst, dtype=np.uint32)
+        k0 = np.ascontiguousarray(k0, dtype=np.uint64)
+        count = np.ascontiguousarray(count, dtype=np.uint64)
+        t_arrival = np.ascontiguousarray(t_arrival, dtype=np.float64)
+        n = len(inst)
+        t_admit = np.zeros(n)
+        t_done = np.zeros(n)
+        _check(lib().rsaprng_server_replay(self.h, n, inst.ctypes.data, k0.ctypes.data,
+                                           count.ctypes.data, t_arrival.ctypes.data,
+                                           t_admit.ctypes.data, t_done.ctypes.data),
+               "rsaprng_server_replay")
+        return t_admit, t_done
 
     def now(self) -> float:
         return lib().rsaprng_server_now(self.h)

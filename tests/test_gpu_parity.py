@@ -200,6 +200,37 @@ def test_consume_matches_oracle(R):
             assert g["sum"] == float(Fraction(ref["sum_fx"], 1 << 128))
 
 
+def test_consume_persistent_many_chains(R):
+    # one work-group per compute unit walks tiles of many chains in turn: each
+    # tile's statistics must land in its own record, in every shape and variant
+    insts = inputs.config3(24)
+    ranges = []
+    for j in range(len(insts)):
+        ranges.append((j, (j * 7919) % B, 3 * 4096 + 17 * j))
+        ranges.append((j, (1 << 33) + j * 12345, 2 * B // 3))
+    refs = [oracle_stats(insts[j], k0, cnt) for j, k0, cnt in ranges]
+    pool = R.Pool.from_instances(insts)
+    for var, name in _variants(R):
+        for shape, prefix in (((256, 8, 1), 0), ((256, 8, 2), 0), ((256, 8, 4), 0),
+                              ((512, 8, 2), 0), ((256, 8, 1), 1), ((512, 8, 1), 1),
+                              ((256, 16, 1), 1)):
+            log("consume persistent", name, shape, prefix)
+            st = R.stats_tensor(len(ranges))
+            cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                           chunks_per_wave=shape[2], prefix=prefix, persistent=1, wg_per_cu=1,
+                           order=1)
+            R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx)
+                                          for idx, (j, k0, cnt) in enumerate(ranges)], st, cfg=cfg)
+            R.rsaprng_check_device_error()
+            got = R.stats_decode(st)
+            for idx, ref in enumerate(refs):
+                g = got[idx]
+                assert g["count"] == ranges[idx][2], (name, shape, idx)
+                assert g["sum_fx"] == ref["sum_fx"], (name, shape, idx)
+                assert g["lt_half"] == ref["lt_half"], (name, shape, idx)
+                assert np.array_equal(g["hist"], ref["hist"]), (name, shape, idx)
+
+
 def test_consume_single_handle(R):
     inst = inputs.config1()
     g = R.rsaprng_create(inst.p, inst.q, inst.e, inst.m0)
