@@ -38,11 +38,15 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
+DEVICE_SOURCES = ("common.h", "devmath.h", "tiles.h")
+
+
 def kernel_source_hash() -> str:
+    """Hash of the device-code sources (the kernels' text, not the host library)."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1811_11629_amd", "csrc")
     for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".h")):
+        if f.endswith(".hip") or f in DEVICE_SOURCES:
             with open(os.path.join(d, f), "rb") as fh:
                 h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
@@ -63,6 +67,22 @@ def traffic_from_profiles(workload: str):
     return ent.get("hbm_bytes_per_launch")
 
 
+def time_timed(batch, stream, steps, warmup, torch):
+    """The timed region of the headline: `steps` launches of the prepared batch,
+    each with HIP events between its kernels on `stream`; returns wall seconds
+    and the per-kernel averages of those same launches."""
+    for _ in range(warmup):
+        batch.run_timed(stream)
+    batch.kernel_ms()  # discard the warm-up runs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        batch.run_timed(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, batch.kernel_ms()
+
+
 def time_graph(batch, stream, steps, warmup, torch):
     for _ in range(warmup):
         batch.run(stream)
@@ -79,6 +99,16 @@ def time_graph(batch, stream, steps, warmup, torch):
     wall = time.perf_counter() - t0
     kms = [a.elapsed_time(b) for a, b in evs]
     return wall, kms
+
+
+def tile_kernel_name(cfg) -> str:
+    """The tile kernel's symbol stem for a configuration (as rocprofv3 lists it)."""
+    two = cfg.prefix == 0
+    return "%s<%d, %d%s, %d, 0> (%s, %s)" % (
+        "k_gen2" if two else "k_gen1", cfg.lanes_per_tile, cfg.per_lane,
+        (", %d" % cfg.chunks_per_wave) if two else "", cfg.variant,
+        "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64",
+        "generate")
 
 
 def config2_requests():
@@ -370,12 +400,16 @@ def main():
                                            stream=stream)
         log("best config", best.as_dict(), "%.3f ms" % best_ms)
     batch = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr, cfg=best, stream=stream)
-    wall, kms = time_graph(batch, stream, args.steps, args.warmup, torch)
+    wall, kt = time_timed(batch, stream, args.steps, args.warmup, torch)
     batch.check()
     ms_step = wall / args.steps * 1e3
     value = N / (wall / args.steps) / 1e9
-    k_ms = sum(kms) / len(kms)
-    log("multi-instance: %.3f ms/step, %.1f Gnum/s; kernel avg %.3f ms" % (ms_step, value, k_ms))
+    k_ms = kt["tiles"]
+    log("multi-instance: %.3f ms/step, %.1f Gnum/s; kernels (ms): setup %.3f prefix %.3f "
+        "tiles %.3f" % (ms_step, value, kt["setup"], kt["prefix"], k_ms))
+    gwall, gkms = time_graph(batch, stream, args.steps, 1, torch)
+    batch.check()
+    log("graph replay: %.3f ms/step" % (gwall / args.steps * 1e3))
     verified = verify_config2(insts, oc, orr)
     log("verified against oracle:", verified)
 
@@ -384,8 +418,10 @@ def main():
     traffic = traffic_from_profiles("multi_instance_e3")
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "k_tiles (generate, variant %d)" % best.variant,
-                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": k_ms}
+                "kernel": tile_kernel_name(best),
+                "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": k_ms,
+                "other_kernels_ms": {"setup": kt["setup"], "prefix": kt["prefix"]},
+                "graph_replay_ms_per_step": gwall / args.steps * 1e3}
 
     extras = {}
     if not args.no_extras:

@@ -181,7 +181,9 @@ typedef struct {
   int wg_per_cu;        /* persistent grid size per compute unit (0 = default) */
   int order;            /* 0 request order, 1 longest-first by exponent cost */
   int prefix;           /* 0 two passes (tile sums, scan, generate); 1 one pass with a
-                           decoupled look-back over the preceding tiles */
+                           decoupled look-back over the preceding tiles; 2 chain-serial:
+                           one work-group walks each chain (a request's indices inside
+                           one 2^20 block) in order, carrying the message prefix */
   int chunks_per_wave;  /* two passes: consecutive 64*per_lane chunks each wave processes */
 } rsaprng_config;
 
@@ -204,6 +206,14 @@ int rsaprng_batch_run(rsaprng_batch_t b, void* stream);
 /* RSAPRNG_E_DEVICE if a replay flagged an error since the last call (the caller
  * must have synchronised the stream of the replays), else RSAPRNG_OK. */
 int rsaprng_batch_check(rsaprng_batch_t b);
+/* The same launch enqueued without its graph, with HIP events recorded on
+ * `stream` between its kernels: per-kernel durations without a profiler. */
+int rsaprng_batch_run_timed(rsaprng_batch_t b, void* stream);
+/* Average durations in ms over the timed runs since the previous call: ms[0]
+ * chain setup (with statistics zeroing), ms[1] prefix pass(es), ms[2] tile
+ * kernel, ms[3] statistics finalisation; *runs (may be NULL) receives their
+ * number.  Waits for those runs, then forgets them. */
+int rsaprng_batch_kernel_ms(rsaprng_batch_t b, double* ms, int* runs);
 void rsaprng_batch_destroy(rsaprng_batch_t b);
 
 /* Autotuner: times every kernel configuration in its search space on this

@@ -77,7 +77,10 @@ struct DevCtl {
 
 enum Variant : int { kVariantAuto = 0, kVariantMont = 1, kVariantCrt = 2 };
 enum Mode : int { kModeGenerate = 0, kModeConsume = 1 };
-enum Prefix : int { kPrefixTwoPass = 0, kPrefixLookback = 1 };
+// How a tile learns the message before it: two passes (tile sums, scan, then
+// generate), one pass with a decoupled look-back, or chain-serial (one
+// work-group walks a whole chain and carries the prefix from step to step).
+enum Prefix : int { kPrefixTwoPass = 0, kPrefixLookback = 1, kPrefixSerial = 2 };
 
 struct LaunchArgs {
   const rsaprng_params* inst;
@@ -109,10 +112,10 @@ struct LaunchArgs {
 // Host-callable launchers (kernels.hip).
 struct KernelShape {
   int variant;   // kVariantMont or kVariantCrt
-  int wg;        // 128 or 256
+  int wg;        // 256 or 512
   int v;         // 8 or 16
   int mode;      // kModeGenerate or kModeConsume
-  int prefix;    // kPrefixTwoPass or kPrefixLookback
+  int prefix;    // kPrefixTwoPass, kPrefixLookback or kPrefixSerial
   int r;         // two passes: consecutive wave chunks per wave (tile = wg v r)
   int grid;      // number of work-groups (they loop if fewer than tiles)
 };

@@ -190,14 +190,21 @@ __device__ __forceinline__ double fp_pow_rt(double x, double P, double Pinv, u32
   return y;
 }
 
+// x in (-P, P) (an integer) moved to [0, P): floor(x / P) is -1 or 0, and
+// RN(x RN(1/P)) stays inside (-1, 1) on the right side of 0 for P < 2^52, so
+// its floor decides; the fma then adds P exactly.  Arithmetic instead of a
+// compare and select keeps the condition out of VCC.
+__device__ __forceinline__ double to_unsigned_residue(double x, double P, double Pinv) {
+  return __fma_rn(-__builtin_floor(x * Pinv), P, x);
+}
+
 // Garner's recombination c = ((c_p - c_q) q^-1 mod p) q + c_q.  Returns the
 // integer c and RN(c) (one rounding of t q + c_q by the fma).
 __device__ __forceinline__ u64 garner(double cp, double cq, double pd, double qd, double pinv,
-                                      double qinvp, u32 q, double& cd) {
-  double cqn = cq < 0.0 ? cq + qd : cq;            // [0, q)
-  double d = cp - cqn;                             // exact, |d| < 2^33
-  double t = fmm(d, qinvp, pd, pinv);              // (-p, p)
-  t = t < 0.0 ? t + pd : t;                        // [0, p)
+                                      double qinv, double qinvp, u32 q, double& cd) {
+  const double cqn = to_unsigned_residue(cq, qd, qinv);   // [0, q)
+  const double d = cp - cqn;                              // exact, |d| < 2^33
+  const double t = to_unsigned_residue(fmm(d, qinvp, pd, pinv), pd, pinv);  // [0, p)
   cd = __fma_rn(t, qd, cqn);
   return mad32((u32)t, q, (u64)(u32)cqn);
 }
@@ -220,7 +227,8 @@ __device__ __forceinline__ double ratio(double cd, double nd, double y) {
   const double q0 = cd * y;
   const double q1 = __fma_rn(__fma_rn(-q0, nd, cd), y, q0);
   const double r = __fma_rn(__fma_rn(-q1, nd, cd), y, q1);
-  return r == 1.0 ? 0x1.fffffffffffffp-1 : r;
+  // r <= 1; the guard replaces exactly 1.0 by the largest double below it
+  return __builtin_fmin(r, 0x1.fffffffffffffp-1);
 }
 
 }  // namespace rsaprng

@@ -5,6 +5,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -338,9 +339,14 @@ rsaprng_config resolve_config(const rsaprng_config* cfg) {
   if (cfg) c = *cfg;
   if (c.variant == kVariantAuto) c.variant = env_int("RSAPRNG_VARIANT", kVariantCrt);
   if (c.variant != kVariantMont && c.variant != kVariantCrt) c.variant = kVariantCrt;
-  if (c.prefix != kPrefixTwoPass && c.prefix != kPrefixLookback)
+  if (c.prefix != kPrefixTwoPass && c.prefix != kPrefixLookback && c.prefix != kPrefixSerial)
     c.prefix = env_int("RSAPRNG_PREFIX", kPrefixTwoPass);
-  if (c.prefix == kPrefixTwoPass) {
+  if (c.prefix == kPrefixSerial) {
+    // chain-serial: (256, 8) or (512, 8), one step of WG V indices at a time
+    c.per_lane = 8;
+    c.chunks_per_wave = 1;
+    if (c.lanes_per_tile != 512) c.lanes_per_tile = 256;
+  } else if (c.prefix == kPrefixTwoPass) {
     // shapes built for two passes: (256, 8, r) for r = 1, 2, 4 and (512, 8, 2)
     c.per_lane = 8;
     if (c.lanes_per_tile != 512) c.lanes_per_tile = 256;
@@ -478,7 +484,7 @@ int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode
 
 static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c, u64h ntiles) {
   // The dispatch packet counts work-items in 32 bits; work-groups loop over the
-  // tile queue, so any grid covers every tile.
+  // tile queue (chains, for the chain-serial form), so any grid covers all work.
   if (!c.persistent) return (int)std::min<u64h>(ntiles, (1ull << 24));
   int occ = 1;
   if (kernel_max_grid(shape, &occ)) occ = 1;
@@ -492,11 +498,19 @@ static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
-                   ChainState* state, void* stream) {
+                   ChainState* state, void* stream, hipEvent_t* marks) {
   int rc;
+  auto mark = [&](int i) {
+    return !marks || hipEventRecord(marks[i], (hipStream_t)stream) == hipSuccess ? RSAPRNG_OK
+                                                                                : RSAPRNG_E_HIP;
+  };
+  if ((rc = mark(0))) return rc;
   if (mode == kModeConsume && nstats && (rc = launch_stats_zero(stats, nstats, stream))) return rc;
   if (ntiles == 0) {
-    if (mode == kModeConsume && nstats) return launch_stats_finalize(stats, nstats, stream);
+    if (mode == kModeConsume && nstats && (rc = launch_stats_finalize(stats, nstats, stream)))
+      return rc;
+    for (int i = 1; i < 5; ++i)
+      if ((rc = mark(i))) return rc;
     return RSAPRNG_OK;
   }
   const u64h T = tile_size(c);
@@ -509,7 +523,7 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   shape.mode = mode;
   shape.prefix = c.prefix;
   shape.r = c.chunks_per_wave;
-  shape.grid = grid_for(d, shape, c, ntiles);
+  shape.grid = grid_for(d, shape, c, c.prefix == kPrefixSerial ? (u64h)nchain : ntiles);
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
   a.inst = inst;
@@ -539,16 +553,17 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   a.pl = d->pl[ti];
   a.powv = c.per_lane == 8 ? d->powv8 : d->powv16;
   a.gc = d->gc;
-  if ((rc = launch_chain_setup(a, stream))) return rc;
+  if ((rc = launch_chain_setup(a, stream)) || (rc = mark(1))) return rc;
   if (c.prefix == kPrefixTwoPass) {
     if ((rc = launch_sums(a, stream))) return rc;
     if ((rc = launch_scan(a, stream))) return rc;
-  } else {
+  } else if (c.prefix == kPrefixLookback) {
     if ((rc = launch_begin(sc->ctl, stream))) return rc;
   }
-  if ((rc = launch_tiles(shape, a, stream))) return rc;
+  if ((rc = mark(2))) return rc;
+  if ((rc = launch_tiles(shape, a, stream)) || (rc = mark(3))) return rc;
   if (mode == kModeConsume && (rc = launch_stats_finalize(stats, nstats, stream))) return rc;
-  return RSAPRNG_OK;
+  return mark(4);
 }
 
 }  // namespace rsaprng
@@ -886,7 +901,22 @@ struct rsaprng_batch_s {
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // what the eager (timed) form needs to enqueue the same launch again
+  rsaprng::Device* dev = nullptr;
+  rsaprng_config cfg;
+  int mode = 0;
+  u64h ntiles = 0;
+  uint32_t nchain = 0;
+  uint64_t* out_c = nullptr;
+  double* out_r = nullptr;
+  rsaprng_stats* stats = nullptr;
+  size_t nst = 0;
+  std::vector<std::array<hipEvent_t, 5>> ev;  // per timed run
+  size_t ev_used = 0;
   ~rsaprng_batch_s() {
+    for (auto& e : ev)
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
     if (exec) (void)hipGraphExecDestroy(exec);
     if (graph) (void)hipGraphDestroy(graph);
     if (cap_stream) (void)hipStreamDestroy(cap_stream);
@@ -939,6 +969,15 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   if (e1 != hipSuccess || !g) return RSAPRNG_E_HIP;
   b->graph = g;
   if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) return RSAPRNG_E_HIP;
+  b->dev = d;
+  b->cfg = c;
+  b->mode = mode;
+  b->ntiles = ntiles;
+  b->nchain = (uint32_t)plan.size();
+  b->out_c = out_u64;
+  b->out_r = out_f64;
+  b->stats = stats_dev;
+  b->nst = nst;
   (void)stream;
   *out = b.release();
   return RSAPRNG_OK;
@@ -947,6 +986,45 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
 int rsaprng_batch_run(rsaprng_batch_t b, void* stream) {
   if (!b) return RSAPRNG_E_NULL;
   return hipGraphLaunch(b->exec, (hipStream_t)stream) == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
+}
+
+int rsaprng_batch_run_timed(rsaprng_batch_t b, void* stream) {
+  if (!b) return RSAPRNG_E_NULL;
+  if (b->ev_used == b->ev.size()) {
+    std::array<hipEvent_t, 5> e{};
+    for (auto& x : e) {
+      if (hipEventCreate(&x) != hipSuccess) {
+        for (auto& y : e)
+          if (y) (void)hipEventDestroy(y);
+        return RSAPRNG_E_HIP;
+      }
+    }
+    b->ev.push_back(e);
+  }
+  hipEvent_t* marks = b->ev[b->ev_used].data();
+  const int rc = enqueue_launch(b->dev, &b->sc, b->cfg, b->mode, b->pool->dev,
+                                (const Chain*)b->dreq, b->nchain, b->ntiles, b->out_c, b->out_r,
+                                b->stats, b->nst, nullptr, stream, marks);
+  if (!rc) ++b->ev_used;
+  return rc;
+}
+
+int rsaprng_batch_kernel_ms(rsaprng_batch_t b, double* ms, int* runs) {
+  if (!b || !ms) return RSAPRNG_E_NULL;
+  for (int j = 0; j < 4; ++j) ms[j] = 0;
+  const size_t n = b->ev_used;
+  for (size_t i = 0; i < n; ++i) {
+    if (hipEventSynchronize(b->ev[i][4]) != hipSuccess) return RSAPRNG_E_HIP;
+    for (int j = 0; j < 4; ++j) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, b->ev[i][j], b->ev[i][j + 1]) != hipSuccess) return RSAPRNG_E_HIP;
+      ms[j] += t;
+    }
+  }
+  for (int j = 0; j < 4 && n; ++j) ms[j] /= (double)n;
+  if (runs) *runs = (int)n;
+  b->ev_used = 0;
+  return RSAPRNG_OK;
 }
 
 int rsaprng_batch_check(rsaprng_batch_t b) {
@@ -1001,7 +1079,8 @@ std::vector<rsaprng_config> tune_space() {
   static const int shapes[][4] = {{kPrefixTwoPass, 256, 8, 1}, {kPrefixTwoPass, 256, 8, 2},
                                   {kPrefixTwoPass, 256, 8, 4}, {kPrefixTwoPass, 512, 8, 2},
                                   {kPrefixLookback, 256, 8, 1}, {kPrefixLookback, 512, 8, 1},
-                                  {kPrefixLookback, 256, 16, 1}};
+                                  {kPrefixLookback, 256, 16, 1}, {kPrefixSerial, 256, 8, 1},
+                                  {kPrefixSerial, 512, 8, 1}};
   std::vector<rsaprng_config> out;
   for (int var : {kVariantCrt, kVariantMont})
     for (const auto& s : shapes)

@@ -66,10 +66,12 @@ int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mo
                   std::vector<Req>& out, u64h* ntiles_out);
 int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode,
                 std::vector<Chain>& chains, u64h* ntiles_out);
+// marks (optional, 5 timing events): recorded before the launch, after chain
+// setup, after the prefix pass(es), after the tile kernel and at the end.
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
-                   ChainState* state, void* stream);
+                   ChainState* state, void* stream, hipEvent_t* marks = nullptr);
 const rsaprng_params* pool_dev(rsaprng_pool_t pool);
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i);
 int pool_device(rsaprng_pool_t pool);

@@ -144,6 +144,23 @@ __device__ u64 look_back(const LaunchArgs& a, u32 t, u32 first, u32 tag, u64 n, 
 // ---------------------------------------------------------------------------
 // encryption of one message
 // ---------------------------------------------------------------------------
+// CRT form from the residues of m: m^E mod p and mod q, then Garner.  For
+// E >= 2 the residues may be unreduced (|x| < 2^42: the ladder opens with a
+// squaring), otherwise they must lie in (-P, P).
+template <u32 E>
+__device__ __forceinline__ u64 encrypt_res(double mp, double mq, const rsaprng_params& P,
+                                           double& cd) {
+  double cp, cq;
+  if constexpr (E != 0) {
+    cp = fp_pow<E>(mp, P.pd, P.pinv);
+    cq = fp_pow<E>(mq, P.qd, P.qinv);
+  } else {
+    cp = fp_pow_rt(mp, P.pd, P.pinv, P.e);
+    cq = fp_pow_rt(mq, P.qd, P.qinv, P.e);
+  }
+  return garner(cp, cq, P.pd, P.qd, P.pinv, P.qinv, P.qinvp, P.q, cd);
+}
+
 template <int VAR, u32 E>
 __device__ __forceinline__ u64 encrypt(u64 m, const rsaprng_params& P, double& cd) {
   if constexpr (VAR == kVariantMont) {
@@ -163,15 +180,7 @@ __device__ __forceinline__ u64 encrypt(u64 m, const rsaprng_params& P, double& c
       mp = residue(m, P.pd, P.pinv, P.kp);
       mq = residue(m, P.qd, P.qinv, P.kq);
     }
-    double cp, cq;
-    if constexpr (E != 0) {
-      cp = fp_pow<E>(mp, P.pd, P.pinv);
-      cq = fp_pow<E>(mq, P.qd, P.qinv);
-    } else {
-      cp = fp_pow_rt(mp, P.pd, P.pinv, P.e);
-      cq = fp_pow_rt(mq, P.qd, P.qinv, P.e);
-    }
-    return garner(cp, cq, P.pd, P.qd, P.pinv, P.qinvp, P.q, cd);
+    return encrypt_res<E>(mp, mq, P, cd);
   }
 }
 
@@ -193,6 +202,60 @@ __device__ __forceinline__ void fixed128(double r, u64& lo, u64& hi) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Message sources of one lane's V consecutive indices.  enc<VAR, E>(i, ...)
+// encrypts the i-th message; callers take i = 0, 1, ..., V-1 in order.
+// ---------------------------------------------------------------------------
+// Exact messages: m_i = (pre + X_i) mod n, X_i the running skip sums mod n.
+template <int V>
+struct MsgExact {
+  u64 pre, n;
+  const u64 (&X)[V];
+  template <int VAR, u32 E>
+  __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
+    return encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
+  }
+};
+
+// x (an integer-valued double, |x| < 2^52) reduced into (-P, P).
+__device__ __forceinline__ double reduce_res(double x, double P, double Pinv) {
+  return __fma_rn(-__builtin_rint(x * Pinv), P, x);
+}
+
+// H 2^32 + L modulo P up to a multiple of P, for integer-valued H < 2^35 and
+// 0 <= L < 2^36: h + l = H (2^32 mod P) exactly, h - rint(h/P) P is exact and
+// below P in magnitude, so the result lies in (-P - 2^14, P + 2^14 + L).
+__device__ __forceinline__ double fold_hl(double H, double L, double P, double Pinv, double K) {
+  const double h = H * K;
+  const double l = __fma_rn(H, K, -h);
+  return (__fma_rn(-__builtin_rint(h * Pinv), P, h) + l) + L;
+}
+
+// Residue messages (CRT variant).  With the lane's skips s_0..s_{V-1} and the
+// residues bp, bq of the message before its first index, m_i is congruent to
+// b + S_i where S_i = s_0 + ... + s_i = H_i 2^32 + L_i, H_i and L_i the exact
+// sums of the skips' upper and lower halves (below 2^34 and 2^35 for V = 8).
+// Only m mod p and m mod q enter the encryption, so no 64-bit modular
+// addition is done; the residues handed to the ladder stay below 2^37.
+template <int V>
+struct MsgRes {
+  const u64 (&S)[V];
+  double bp, bq;
+  double H = 0.0, L = 0.0;
+  template <int VAR, u32 E>
+  __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
+    H += (double)hi32(S[i]);
+    L += (double)lo32(S[i]);
+    double mp = bp + fold_hl(H, L, P.pd, P.pinv, P.kp);
+    double mq = bq + fold_hl(H, L, P.qd, P.qinv, P.kq);
+    if constexpr (E < 2) {  // no opening squaring: Garner needs reduced residues
+      mp = reduce_res(mp, P.pd, P.pinv);
+      mq = reduce_res(mq, P.qd, P.qinv);
+    }
+    return encrypt_res<E>(mp, mq, P, cd);
+  }
+};
+
 // Row stride (64-bit words) of a wave's transpose buffer: 8 values per lane
 // plus one word of padding against LDS bank conflicts.
 constexpr int kXRow = 9;
@@ -204,64 +267,60 @@ struct TileShared {
   u64 wave_tot[WG / 64];
   u64 red[MODE == kModeConsume ? (WG / 64) * 6 : 1];
   u32 hist[MODE == kModeConsume ? 1024 : 1];
-  // generate: per wave, one 64 x 8 block of results for the coalescing transpose
-  u64 xbuf[MODE == kModeGenerate ? (WG / 64) * 64 * kXRow : 1];
+  // generate: per wave, two 64 x 8 blocks (c, then r) for the coalescing transpose
+  u64 xbuf[MODE == kModeGenerate ? 2 * (WG / 64) * 64 * kXRow : 1];
 };
 
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
 // every index of the tile is requested and both outputs are 16-byte aligned at
 // every lane's first index, so pairs are stored without predicates.
-template <int WG, int V, int VAR, int MODE, u32 E, bool FAST>
+template <int WG, int V, int VAR, int MODE, u32 E, bool FAST, class Msg>
 __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
-                                             const Chain& C, const rsaprng_params& P, u64 pre,
-                                             const u64 (&X)[V], u64 laneStart) {
-  const u64 n = P.n;
+                                             const Chain& C, const rsaprng_params& P, Msg msg,
+                                             u64 laneStart) {
   const bool full = FAST || (laneStart >= C.k0 && laneStart + (V - 1) <= C.last);
   if constexpr (MODE == kModeGenerate) {
     u64* const oc = a.out_c;
     double* const orr = a.out_r;
     if constexpr (FAST && V == 8) {
-      // Each lane's 8 results go to its row of the wave's LDS buffer as they are
-      // produced; then store j writes elements 64 j + lane of the chunk, so every
-      // store instruction covers 512 contiguous bytes (full cache lines).
-      // c goes through the buffer first while r waits in registers, then r.
+      // Each lane's 8 results go to its row of the wave's LDS buffers (c and r)
+      // as they are produced; then store j writes elements 64 j + lane of the
+      // chunk, so every store instruction covers 512 contiguous bytes (full
+      // cache lines).  No result waits in registers.
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-      u64* xb = sh.xbuf + wave * (64 * kXRow);
-      u64 rb[V];
+      u64* xc = sh.xbuf + wave * (2 * 64 * kXRow);
+      u64* xr = xc + 64 * kXRow;
 #pragma unroll
       for (int i = 0; i < V; ++i) {
         double cd;
-        const u64 c = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
-        xb[lane * kXRow + i] = c;
-        rb[i] = (u64)__double_as_longlong(ratio(cd, P.nd, P.nrcp));
+        const u64 c = msg.template enc<VAR, E>(i, P, cd);
+        xc[lane * kXRow + i] = c;
+        xr[lane * kXRow + i] = (u64)__double_as_longlong(ratio(cd, P.nd, P.nrcp));
       }
       const u64 chunk0 = C.out_off + (laneStart - (u64)lane * V - C.k0);
       const int src = (lane >> 3) * kXRow + (lane & 7);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      if (oc) {
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        u64* const dst = half == 0 ? oc : reinterpret_cast<u64*>(orr);
-        if (half == 1) {
-#pragma unroll
-          for (int i = 0; i < V; ++i) xb[lane * kXRow + i] = rb[i];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if (dst) {
-#pragma unroll
-          for (int j = 0; j < V; ++j) dst[chunk0 + (u64)j * 64 + lane] = xb[j * 8 * kXRow + src];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int j = 0; j < V; ++j) oc[chunk0 + (u64)j * 64 + lane] = xc[j * 8 * kXRow + src];
       }
+      if (orr) {
+        u64* const dr = reinterpret_cast<u64*>(orr);
+#pragma unroll
+        for (int j = 0; j < V; ++j) dr[chunk0 + (u64)j * 64 + lane] = xr[j * 8 * kXRow + src];
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     } else if constexpr (FAST) {
       const u64 off0 = C.out_off + (laneStart - C.k0);
 #pragma unroll
       for (int i = 0; i < V; i += 2) {
         double cd0, cd1;
-        const u64 c0 = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd0);
-        const u64 c1 = encrypt<VAR, E>(addmod(pre, X[i + 1], n), P, cd1);
+        const u64 c0 = msg.template enc<VAR, E>(i, P, cd0);
+        const u64 c1 = msg.template enc<VAR, E>(i + 1, P, cd1);
         if (oc) *reinterpret_cast<ulonglong2*>(oc + off0 + i) = make_ulonglong2(c0, c1);
         if (orr)
           *reinterpret_cast<double2*>(orr + off0 + i) =
@@ -272,7 +331,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       for (int i = 0; i < V; ++i) {
         const u64 k = laneStart + i;
         double cd;
-        const u64 c = encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
+        const u64 c = msg.template enc<VAR, E>(i, P, cd);
         if (k >= C.k0 && k <= C.last) {
           const u64 off = C.out_off + (k - C.k0);
           if (oc) oc[off] = c;
@@ -286,7 +345,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
     for (int i = 0; i < V; ++i) {
       const u64 k = laneStart + i;
       double cd;
-      (void)encrypt<VAR, E>(addmod(pre, X[i], n), P, cd);
+      (void)msg.template enc<VAR, E>(i, P, cd);
       const double r = ratio(cd, P.nd, P.nrcp);
       if (full || (k >= C.k0 && k <= C.last)) {
         u64 lo, hi;
@@ -367,6 +426,52 @@ __device__ __forceinline__ u64 walk(u64 s_first, u64 n, u64 (&X)[V]) {
   return x;
 }
 
+// Walk of one lane keeping the skips, and the sums of their upper and lower
+// 32-bit halves (below 2^35 and 2^36 for V <= 16) as exact doubles.  The sums
+// are formed in integers so that the per-index conversions of the output pass
+// are not shared with this one (sharing would keep 2 V doubles live).
+template <int V>
+__device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H, double& L) {
+  static_assert(V <= 16, "half sums must stay exact and below the residue bounds");
+  u64 s = s_first;
+  u64 h = 0, l = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    if (i) s = lcg_next(s);
+    S[i] = s;
+    h += hi32(s);
+    l += lo32(s);
+  }
+  H = __fma_rn((double)hi32(h), 4294967296.0, (double)lo32(h));
+  L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
+}
+
+// The same sums without keeping the skips (steps that only walk).
+template <int V>
+__device__ __forceinline__ void walk_totals(u64 s_first, double& H, double& L) {
+  u64 s = s_first;
+  u64 h = 0, l = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    if (i) s = lcg_next(s);
+    h += hi32(s);
+    l += lo32(s);
+  }
+  H = __fma_rn((double)hi32(h), 4294967296.0, (double)lo32(h));
+  L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
+}
+
+// Inclusive scan over the wave of integer-valued doubles whose partial sums
+// stay below 2^53 (exact).
+__device__ __forceinline__ double wave_scan_f64(double x, int lane) {
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const double y = __shfl_up(x, d, 64);
+    x += lane >= d ? y : 0.0;
+  }
+  return x;
+}
+
 // Inclusive scan mod n over the wave (lane offsets of the messages).
 __device__ __forceinline__ u64 wave_scan_shfl(u64 x, u64 n, int lane) {
 #pragma unroll
@@ -377,33 +482,67 @@ __device__ __forceinline__ u64 wave_scan_shfl(u64 x, u64 n, int lane) {
   return x;
 }
 
-// Outputs of one wave chunk (64 V indices starting at chunkStart) whose lanes
-// hold the running sums X and the message before their first index `pre`.
-template <int WG, int V, int VAR, int MODE>
+// Dispatch of one lane's outputs on the exponent: ladders unrolled for the
+// common exponents when every index of the span is requested and the stores
+// are 16-byte aligned, a generic ladder with predicated stores otherwise.
+template <int WG, int V, int VAR, int MODE, class Msg>
+__device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG, MODE>& sh,
+                                              const Chain& C, const rsaprng_params& P,
+                                              const Msg& msg, bool fast, u64 laneStart) {
+  if (fast) {
+    switch (P.e) {
+      case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, msg, laneStart); break;
+      case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, msg, laneStart); break;
+      case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, msg, laneStart); break;
+      case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, msg, laneStart); break;
+      case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, msg, laneStart); break;
+      case 257: tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, msg, laneStart); break;
+      case 65537: tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, msg, laneStart); break;
+      default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, msg, laneStart); break;
+    }
+  } else {
+    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, msg, laneStart);
+  }
+}
+
+// Outputs of one wave chunk (64 V indices starting at chunkStart).
+template <int WG, int V, int VAR, int MODE, class Msg>
 __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
-                                              const Chain& C, const rsaprng_params& P, u64 pre,
-                                              const u64 (&X)[V], u64 chunkStart, u64 laneStart) {
+                                              const Chain& C, const rsaprng_params& P,
+                                              const Msg& msg, u64 chunkStart, u64 laneStart) {
   constexpr u64 CHUNK = 64ull * V;
   const u64 off_c = C.out_off + (chunkStart - C.k0);
   const bool fast = chunkStart >= C.k0 && chunkStart + (CHUNK - 1) <= C.last &&
                     (MODE == kModeConsume ||
                      ((!a.out_c || ((uintptr_t)(a.out_c + off_c) & 15) == 0) &&
                       (!a.out_r || ((uintptr_t)(a.out_r + off_c) & 15) == 0)));
-  if (fast) {
-    switch (P.e) {
-      case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, pre, X, laneStart); break;
-      case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, pre, X, laneStart); break;
-      case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, pre, X, laneStart); break;
-      case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, pre, X, laneStart); break;
-      case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, pre, X, laneStart); break;
-      case 257: tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, pre, X, laneStart); break;
-      case 65537:
-        tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, pre, X, laneStart);
-        break;
-      default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, pre, X, laneStart); break;
+  outputs_for_e<WG, V, VAR, MODE>(a, sh, C, P, msg, fast, laneStart);
+}
+
+// The same state from residue messages: m at the last index recombined by
+// Garner (encryption with e = 1) and the skip after it.
+template <int V>
+__device__ __forceinline__ void chain_end_res(const LaunchArgs& a, const Chain& C,
+                                              const rsaprng_params& P, const MsgRes<V>& msg,
+                                              u64 laneStart) {
+  if ((C.flags & kChainWriteEnd) && laneStart <= C.last && C.last - laneStart < (u64)V) {
+    double H = 0.0, L = 0.0;
+    u64 s_last = 0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (laneStart + i <= C.last) {
+        H += (double)hi32(msg.S[i]);
+        L += (double)lo32(msg.S[i]);
+        s_last = msg.S[i];
+      }
     }
-  } else {
-    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, pre, X, laneStart);
+    const double mp = reduce_res(msg.bp + fold_hl(H, L, P.pd, P.pinv, P.kp), P.pd, P.pinv);
+    const double mq = reduce_res(msg.bq + fold_hl(H, L, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+    double cd;
+    ChainState cs;
+    cs.m_prev = garner(mp, mq, P.pd, P.qd, P.pinv, P.qinv, P.qinvp, P.q, cd);
+    cs.s_at = lcg_next(s_last);
+    a.state[C.slot] = cs;
   }
 }
 
@@ -466,13 +605,32 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
       const u64 laneStart = chunkStart + (u64)lane * V;
       const bool outs = MODE == kModeConsume ? any_out : chunkStart + (CHUNK - 1) >= C.k0;
       if (!outs && !(C.flags & kChainWriteEnd)) continue;
-      u64 X[V];
       const u64 s_first = mulmod_q(s_tile, pv[r]);
-      const u64 x = walk<V>(s_first, n, X);
-      const u64 incl = wave_scan_shfl(x, n, lane);
-      const u64 pre = addmod(E[r], submod(incl, x, n), n);
-      if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, pre, X, chunkStart, laneStart);
-      chain_end<V>(a, C, n, pre, X, s_first, laneStart);
+      if constexpr (VAR == kVariantCrt) {
+        // lane totals as residues, scanned in exact binary64 arithmetic
+        u64 S[V];
+        double Ht, Lt;
+        walk_halves<V>(s_first, S, Ht, Lt);
+        const double tp = reduce_res(fold_hl(Ht, Lt, P.pd, P.pinv, P.kp), P.pd, P.pinv);
+        const double tq = reduce_res(fold_hl(Ht, Lt, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+        const double ip = wave_scan_f64(tp, lane);
+        const double iq = wave_scan_f64(tq, lane);
+        const double bp =
+            reduce_res(residue(E[r], P.pd, P.pinv, P.kp) + (ip - tp), P.pd, P.pinv);
+        const double bq =
+            reduce_res(residue(E[r], P.qd, P.qinv, P.kq) + (iq - tq), P.qd, P.qinv);
+        const MsgRes<V> msg{S, bp, bq};
+        if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+        chain_end_res<V>(a, C, P, msg, laneStart);
+      } else {
+        u64 X[V];
+        const u64 x = walk<V>(s_first, n, X);
+        const u64 incl = wave_scan_shfl(x, n, lane);
+        const u64 pre = addmod(E[r], submod(incl, x, n), n);
+        const MsgExact<V> msg{pre, n, X};
+        if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+        chain_end<V>(a, C, n, pre, X, s_first, laneStart);
+      }
     }
   }
 }
@@ -538,28 +696,133 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
                         (MODE == kModeConsume ||
                          ((!a.out_c || ((uintptr_t)(a.out_c + off_t) & 15) == 0) &&
                           (!a.out_r || ((uintptr_t)(a.out_r + off_t) & 15) == 0)));
-      if (fast) {
-        switch (P.e) {
-          case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, pre, X, laneStart); break;
-          case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, pre, X, laneStart); break;
-          case 5: tile_outputs<WG, V, VAR, MODE, 5, true>(a, sh, C, P, pre, X, laneStart); break;
-          case 7: tile_outputs<WG, V, VAR, MODE, 7, true>(a, sh, C, P, pre, X, laneStart); break;
-          case 17: tile_outputs<WG, V, VAR, MODE, 17, true>(a, sh, C, P, pre, X, laneStart); break;
-          case 257:
-            tile_outputs<WG, V, VAR, MODE, 257, true>(a, sh, C, P, pre, X, laneStart);
-            break;
-          case 65537:
-            tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, pre, X, laneStart);
-            break;
-          default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, pre, X, laneStart); break;
-        }
-      } else {
-        tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, pre, X, laneStart);
-      }
+      outputs_for_e<WG, V, VAR, MODE>(a, sh, C, P, MsgExact<V>{pre, n, X}, fast, laneStart);
     }
     chain_end<V>(a, C, n, pre, X, s_first, laneStart);
     __syncthreads();
   }
+}
+
+// Chain-serial: one work-group per chain walks it in steps of T = WG V
+// indices (wave w takes the w-th chunk of 64 V), carrying the message before
+// the step from one step to the next -- as residues mod p and q for the CRT
+// variant, exactly mod n for the Montgomery variant.  The waves exchange
+// their totals through LDS once per step (double-buffered by step parity, so
+// one barrier per step suffices).  Steps before the chain's first requested
+// index only walk.  No prefix pass is needed, so every skip is computed once.
+template <int WG, int V, int VAR, int MODE>
+__global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
+  constexpr int NW = WG / 64;
+  constexpr u64 T = (u64)WG * V;
+  constexpr u64 CHUNK = 64ull * V;
+  __shared__ TileShared<WG, MODE> sh;
+  __shared__ double2 xch[2][NW];  // wave totals: residues (CRT) or the u64 bits in .x
+  const int lane = threadIdx.x & 63;
+  const u32 wave = uniform(threadIdx.x >> 6);
+  const u64 pvl = a.powv[threadIdx.x];  // a^(V thread): the lane's offset inside a step
+  const u64 aT = load_cst(a.at + 1);    // a^T mod Q
+  if constexpr (MODE == kModeConsume) {
+    for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
+    __syncthreads();
+  }
+  for (u32 c = blockIdx.x; c < a.nchain; c += gridDim.x) {
+    const Chain C = load_cst(a.chain + c);
+    const rsaprng_params P = load_cst(a.inst + C.inst);
+    const ChainStart cs0 = load_cst(a.cstart + c);
+    const u64 n = P.n;
+    // the chain ends at the request's last index or at the end of its 2^20 block
+    const u64 clast = C.last < (C.S | (kBlock - 1)) ? C.last : (C.S | (kBlock - 1));
+    u64 s_lane = mulmod_q(cs0.s_S, pvl);
+    double cp = 0.0, cq = 0.0;  // CRT carry: residues of the message before the step
+    u64 cm = 0;                 // Montgomery carry: the message before the step
+    if constexpr (VAR == kVariantCrt) {
+      cp = residue(cs0.m_base, P.pd, P.pinv, P.kp);
+      cq = residue(cs0.m_base, P.qd, P.qinv, P.kq);
+    } else {
+      cm = cs0.m_base;
+    }
+    for (u32 step = 0;; ++step) {
+      const u64 base = C.S + (u64)step * T;
+      const u64 chunkStart = base + wave * CHUNK;
+      const u64 laneStart = chunkStart + (u64)lane * V;
+      const bool step_out = base + (T - 1) >= C.k0;  // uniform over the work-group
+      const bool chunk_out = MODE == kModeConsume
+                                 ? step_out
+                                 : chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast;
+      const int par = step & 1;
+      if constexpr (VAR == kVariantCrt) {
+        u64 S[V];
+        double Ht, Lt;
+        if (step_out) {
+          walk_halves<V>(s_lane, S, Ht, Lt);
+        } else {
+          walk_totals<V>(s_lane, Ht, Lt);
+        }
+        const double tp = reduce_res(fold_hl(Ht, Lt, P.pd, P.pinv, P.kp), P.pd, P.pinv);
+        const double tq = reduce_res(fold_hl(Ht, Lt, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+        const double ip = wave_scan_f64(tp, lane);
+        const double iq = wave_scan_f64(tq, lane);
+        if (lane == 63) xch[par][wave] = make_double2(ip, iq);
+        __syncthreads();
+        double op = 0.0, oq = 0.0, Tp = 0.0, Tq = 0.0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const double2 v = xch[par][w];
+          if (w < (int)wave) {
+            op += v.x;
+            oq += v.y;
+          }
+          Tp += v.x;
+          Tq += v.y;
+        }
+        if (step_out) {
+          const double bp = reduce_res(cp + op + (ip - tp), P.pd, P.pinv);
+          const double bq = reduce_res(cq + oq + (iq - tq), P.qd, P.qinv);
+          const MsgRes<V> msg{S, bp, bq};
+          if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+          chain_end_res<V>(a, C, P, msg, laneStart);
+        }
+        cp = reduce_res(cp + Tp, P.pd, P.pinv);
+        cq = reduce_res(cq + Tq, P.qd, P.qinv);
+      } else {
+        u64 X[V];
+        const u64 x = walk<V>(s_lane, n, X);
+        const u64 incl = wave_scan_shfl(x, n, lane);
+        if (lane == 63) xch[par][wave].x = __longlong_as_double((long long)incl);
+        __syncthreads();
+        u64 off = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+          const u64 v = (u64)__double_as_longlong(xch[par][w].x);
+          if (w < (int)wave) off = addmod(off, v, n);
+          tot = addmod(tot, v, n);
+        }
+        if (step_out) {
+          const u64 pre = addmod(addmod(cm, off, n), submod(incl, x, n), n);
+          const MsgExact<V> msg{pre, n, X};
+          if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+          chain_end<V>(a, C, n, pre, X, s_lane, laneStart);
+        }
+        cm = addmod(cm, tot, n);
+      }
+      if (clast - base < T) break;
+      s_lane = mulmod_q(s_lane, aT);
+    }
+  }
+}
+
+template <int WG, int V, int VAR, int MODE>
+static int launch3(const LaunchArgs& a, int grid, void* stream, int* occ) {
+  if (occ) {
+    int blocks = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen3<WG, V, VAR, MODE>, WG, 0) !=
+        hipSuccess)
+      blocks = 1;
+    *occ = blocks > 0 ? blocks : 1;
+    return RSAPRNG_OK;
+  }
+  hipLaunchKernelGGL((k_gen3<WG, V, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream, a);
+  return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
 template <int WG, int V, int R, int VAR, int MODE>
@@ -602,6 +865,11 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
     return RSAPRNG_E_ARG;
   }
   if (s.r != 1) return RSAPRNG_E_ARG;
+  if (s.prefix == kPrefixSerial) {
+    if (s.wg == 256 && s.v == 8) return launch3<256, 8, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 512 && s.v == 8) return launch3<512, 8, VAR, MODE>(a, s.grid, stream, occ);
+    return RSAPRNG_E_ARG;
+  }
   if (s.wg == 256 && s.v == 8) return launch1<256, 8, VAR, MODE>(a, s.grid, stream, occ);
   if (s.wg == 512 && s.v == 8) return launch1<512, 8, VAR, MODE>(a, s.grid, stream, occ);
   if (s.wg == 256 && s.v == 16) return launch1<256, 16, VAR, MODE>(a, s.grid, stream, occ);

@@ -112,6 +112,8 @@ _SIGS = {
                                     C.POINTER(rsaprng_config), _vp, C.POINTER(_vp)]),
     "rsaprng_batch_run": (_i32, [_vp, _vp]),
     "rsaprng_batch_check": (_i32, [_vp]),
+    "rsaprng_batch_run_timed": (_i32, [_vp, _vp]),
+    "rsaprng_batch_kernel_ms": (_i32, [_vp, C.POINTER(_dbl), C.POINTER(_i32)]),
     "rsaprng_batch_destroy": (None, [_vp]),
     "rsaprng_autotune": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _i32, _vp, _vp, _vp,
                                 C.c_char_p, _vp, C.POINTER(rsaprng_config), C.POINTER(_dbl)]),
@@ -339,6 +341,19 @@ class Batch:
 
     def check(self):
         _check(lib().rsaprng_batch_check(self.h), "rsaprng_batch_check")
+
+    def run_timed(self, stream=None):
+        """Enqueue the launch without the graph, with events between its kernels."""
+        _check(lib().rsaprng_batch_run_timed(self.h, _stream(stream)), "rsaprng_batch_run_timed")
+
+    def kernel_ms(self):
+        """Average per-kernel ms of the timed runs since the last call:
+        {setup, prefix, tiles, finalize, runs}."""
+        ms = (_dbl * 4)()
+        runs = _i32(0)
+        _check(lib().rsaprng_batch_kernel_ms(self.h, ms, C.byref(runs)), "rsaprng_batch_kernel_ms")
+        return {"setup": ms[0], "prefix": ms[1], "tiles": ms[2], "finalize": ms[3],
+                "runs": runs.value}
 
     def __del__(self):
         if getattr(self, "h", None) and _lib is not None:

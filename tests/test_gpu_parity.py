@@ -28,6 +28,12 @@ def R():
     return rsaprng
 
 
+# Every kernel shape the library builds: (lanes, per_lane, chunks_per_wave, prefix),
+# prefix 0 two passes, 1 one pass with look-back, 2 chain-serial.
+SHAPES = ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
+          (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1), (256, 8, 1, 2), (512, 8, 1, 2))
+
+
 def _variants(R):
     return [(R.VARIANT_MONT, "mont64"), (R.VARIANT_CRT, "crt-fp64")]
 
@@ -74,8 +80,7 @@ def test_ragged_ranges_both_variants(R, k0, count):
     inst = inputs.config1()
     cref, rref = oracle_gen(inst, k0, count)
     for var, name in _variants(R):
-        for shape in ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
-                      (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1)):
+        for shape in SHAPES:
             for prefix in (shape[3],):
                 log("ragged", name, shape, "prefix", prefix, k0, count)
                 cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
@@ -156,8 +161,7 @@ def test_substreams_config2_subset_all_shapes(R):
     rref = np.concatenate([x[1] for x in refs])
     from paper_1811_11629_amd import rsaprng
     for var in (R.VARIANT_MONT, R.VARIANT_CRT):
-        for shape in ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
-                      (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1)):
+        for shape in SHAPES:
             for pers in (0, 1):
                 for prefix in (shape[3],):
                     log("config2 subset", var, shape, pers, prefix)
@@ -180,7 +184,8 @@ def test_consume_matches_oracle(R):
     pool = R.Pool.from_instances(cases)
     for (var, name), (shape, prefix) in [(v, sp) for v in _variants(R)
                                          for sp in (((256, 8, 4), 0), ((256, 8, 1), 1),
-                                                    ((512, 8, 2), 0), ((256, 16, 1), 1))]:
+                                                    ((512, 8, 2), 0), ((256, 16, 1), 1),
+                                                    ((256, 8, 1), 2), ((512, 8, 1), 2))]:
         log("consume", name, shape, prefix)
         st = R.stats_tensor(len(ranges))
         R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx) for idx, (j, k0, cnt) in enumerate(ranges)],
@@ -211,9 +216,7 @@ def test_consume_persistent_many_chains(R):
     refs = [oracle_stats(insts[j], k0, cnt) for j, k0, cnt in ranges]
     pool = R.Pool.from_instances(insts)
     for var, name in _variants(R):
-        for shape, prefix in (((256, 8, 1), 0), ((256, 8, 2), 0), ((256, 8, 4), 0),
-                              ((512, 8, 2), 0), ((256, 8, 1), 1), ((512, 8, 1), 1),
-                              ((256, 16, 1), 1)):
+        for shape, prefix in [((sh[0], sh[1], sh[2]), sh[3]) for sh in SHAPES]:
             log("consume persistent", name, shape, prefix)
             st = R.stats_tensor(len(ranges))
             cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
@@ -255,7 +258,8 @@ def test_graph_batch_replays(R):
         reqs.append((i, k0, c, off))
         off += c
     oc, orr = dev_u64(total), dev_f64(total)
-    for var, prefix in ((R.VARIANT_MONT, 0), (R.VARIANT_CRT, 1), (R.VARIANT_CRT, 0)):
+    for var, prefix in ((R.VARIANT_MONT, 0), (R.VARIANT_CRT, 1), (R.VARIANT_CRT, 0),
+                        (R.VARIANT_CRT, 2), (R.VARIANT_MONT, 2)):
         log("graph batch", var, prefix)
         b = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr,
                     cfg=R.config(variant=var, persistent=1, prefix=prefix))
@@ -270,6 +274,17 @@ def test_graph_batch_replays(R):
                           "graph replay %d" % rep)
             x = torch.randn(1000, device="cuda").sum().item()  # eager work between replays
             assert math.isfinite(x)
+        # the timed (eager) form of the same launch writes the same outputs
+        oc.fill_(-1)
+        orr.fill_(-1.0)
+        torch.cuda.synchronize()
+        b.run_timed()
+        b.run_timed()
+        kt = b.kernel_ms()
+        b.check()
+        assert kt["runs"] == 2 and kt["tiles"] > 0 and kt["setup"] > 0 and kt["finalize"] >= 0
+        _check_ranges(insts, ranges, host_u64(oc, total), host_f64(orr, total), "timed run")
+        assert b.kernel_ms()["runs"] == 0
 
 
 def test_debug_encrypt_bijection(R):

@@ -75,6 +75,8 @@ CFGS = {
     "crt-twopass": dict(variant=2),
     "mont-lookback-16": dict(variant=1, lanes_per_tile=256, per_lane=16, prefix=1),
     "crt-512": dict(variant=2, lanes_per_tile=512),
+    "crt-serial": dict(variant=2, prefix=2),
+    "mont-serial-512": dict(variant=1, lanes_per_tile=512, prefix=2),
 }
 
 
