@@ -52,9 +52,9 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from_profiles(workload: str):
+def traffic_from_profiles(workload: str, kernel: str):
     """HBM bytes per launch from the committed rocprofv3 --pmc summary, if it was
-    taken on the current kernel sources (else None)."""
+    taken on the current kernel sources and on the same tile kernel (else None)."""
     path = os.path.join(ROOT, "profiles", "tile_kernel_traffic.json")
     try:
         with open(path) as f:
@@ -63,6 +63,8 @@ def traffic_from_profiles(workload: str):
         return None
     ent = rec.get(workload)
     if not ent or ent.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    if ent.get("kernel") != kernel.split(" (")[0]:
         return None
     return ent.get("hbm_bytes_per_launch")
 
@@ -102,13 +104,12 @@ def time_graph(batch, stream, steps, warmup, torch):
 
 
 def tile_kernel_name(cfg) -> str:
-    """The tile kernel's symbol stem for a configuration (as rocprofv3 lists it)."""
-    two = cfg.prefix == 0
-    return "%s<%d, %d%s, %d, 0> (%s, %s)" % (
-        "k_gen2" if two else "k_gen1", cfg.lanes_per_tile, cfg.per_lane,
-        (", %d" % cfg.chunks_per_wave) if two else "", cfg.variant,
-        "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64",
-        "generate")
+    """The tile kernel of a configuration, as rocprofv3 lists it."""
+    form = {0: "k_gen2", 1: "k_gen1", 2: "k_gen3"}[cfg.prefix]
+    r = "" if cfg.prefix == 1 else ", %d" % cfg.chunks_per_wave
+    return "%s<%d, %d%s, %d, 0> (%s, generate)" % (
+        form, cfg.lanes_per_tile, cfg.per_lane, r, cfg.variant,
+        "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64")
 
 
 def config2_requests():
@@ -147,12 +148,13 @@ def verify_config2(insts, oc, orr, n_full=3, n_samples=48):
 
 
 def cpu_baseline(insts, budget_outputs):
-    """The oracle, unmodified, over whole instances of the workload on the host's cores."""
+    """The oracle, unmodified, over whole instances of the workload on the host's
+    cores (and on one core for context)."""
     import concurrent.futures as cf
 
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    n_inst = max(threads, budget_outputs // B)
+    n_inst = min(len(insts), max(threads, budget_outputs // B))
     sample = insts[:n_inst]
     oracle.lib()
 
@@ -161,12 +163,20 @@ def cpu_baseline(insts, budget_outputs):
         return B
 
     t0 = time.perf_counter()
+    c0 = time.process_time()
     with cf.ThreadPoolExecutor(threads) as ex:
         done = sum(ex.map(one, sample))
     dt = time.perf_counter() - t0
+    cpu_s = time.process_time() - c0
+    t1 = time.perf_counter()
+    for inst in sample[:4]:
+        one(inst)
+    single = 4 * B / (time.perf_counter() - t1) / 1e9
     return {"value": done / dt / 1e9, "unit": "Gnumbers/s", "cores": threads, "kind": "oracle",
             "sample": "%d of the 1024 multi-instance workload's instances, each k in [0, 2^20) "
-                      "(c_k and r_k), %d host threads, %.1f s wall" % (len(sample), threads, dt)}
+                      "(c_k and r_k) by the plain C oracle, %d host threads: %.1f s wall, %.1f "
+                      "CPU-s" % (len(sample), threads, dt, cpu_s),
+            "single_thread_value": single}
 
 
 def run_plain_config2(R, gens, oc, orr, torch, reps=2):
@@ -263,7 +273,23 @@ def run_batched_uneven(R, torch, stream, steps):
     return res
 
 
-def run_served(R, torch, stream, cfg, rho_main=0.7, sweep=(0.5, 0.9)):
+def tune_served(R, torch, stream, pool, inst, k0, cnt, chunk):
+    """Kernel configuration for the server, tuned on an iteration-like batch: 64
+    requests of the trace, each cut to the server's per-iteration chunk."""
+    reqs, off = [], 0
+    for j in range(64):
+        c = int(min(int(cnt[j]), chunk))
+        reqs.append((int(inst[j]), int(k0[j]), c, off))
+        off += c
+    oc = torch.empty(off, dtype=torch.int64, device="cuda")
+    orr = torch.empty(off, dtype=torch.float64, device="cuda")
+    best, ms = R.rsaprng_autotune(pool, reqs, R.MODE_GENERATE, oc, orr, stream=stream)
+    del oc, orr
+    torch.cuda.empty_cache()
+    return best, ms
+
+
+def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
     """Served workload: 100,000 device-resident instances, requests (instance
     uniform, k0 < 2^40, length log-uniform in [2^10, 2^24)) arriving as a Poisson
     stream; continuous batching with a 64 GiB output arena.  Offered load is a
@@ -277,13 +303,17 @@ def run_served(R, torch, stream, cfg, rho_main=0.7, sweep=(0.5, 0.9)):
     log("served pool drawn in %.1f s" % (time.perf_counter() - t0))
     pool = R.Pool.from_instances(insts)
     mean_count = 2.0 ** 10 * (2.0 ** 14 - 1) / (14 * np.log(2.0))   # E[2^(10+14u)], u uniform
-    srv = R.Server(pool, arena_bytes=64 << 30, cfg=cfg)
 
     def trace(n):
         reqs = inputs.config5_requests(rng, len(insts), n)
         return (np.array([r.inst for r in reqs], dtype=np.uint32),
                 np.array([r.k0 for r in reqs], dtype=np.uint64),
                 np.array([r.count for r in reqs], dtype=np.uint64))
+
+    chunk = 1 << 22
+    cfg, tune_ms = tune_served(R, torch, stream, pool, *trace(64), chunk)
+    log("served config", cfg.as_dict())
+    srv = R.Server(pool, arena_bytes=64 << 30, chunk_outputs=chunk, cfg=cfg)
 
     res = {"workload": "100000 instances (e from {3,5,7,17,257,65537}), requests: instance "
                        "uniform, k0 < 2^40, count = floor(2^(10+14u)); Poisson arrivals; "
@@ -345,7 +375,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-extras", action="store_true", help="headline only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -415,7 +445,7 @@ def main():
 
     alg_bytes = 16 * N                                      # 8 B c_k + 8 B r_k per output
     achieved = alg_bytes / (k_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles("multi_instance_e3")
+    traffic = traffic_from_profiles("multi_instance_e3", tile_kernel_name(best))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                 "kernel": tile_kernel_name(best),
@@ -436,9 +466,9 @@ def main():
         torch.cuda.empty_cache()
         extras["exponent_sweep_consume"] = run_consume_sweep(R, torch, stream, args.steps)
         extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
-        extras["served"] = run_served(R, torch, stream, best)
+        extras["served"] = run_served(R, torch, stream)
 
-    cpu = None if args.no_cpu else cpu_baseline(insts, 512 * B)
+    cpu = None if args.no_cpu else cpu_baseline(insts, 1024 * B)
     if cpu:
         log("cpu oracle: %.3f Gnum/s on %d threads" % (cpu["value"], cpu["cores"]))
 

@@ -184,7 +184,7 @@ typedef struct {
                            decoupled look-back over the preceding tiles; 2 chain-serial:
                            one work-group walks each chain (a request's indices inside
                            one 2^20 block) in order, carrying the message prefix */
-  int chunks_per_wave;  /* two passes: consecutive 64*per_lane chunks each wave processes */
+  int chunks_per_wave;  /* two passes and chain-serial: 64*per_lane chunks per wave per tile */
 } rsaprng_config;
 
 /* One-shot batched launches over a pool (reqs is a host array). */

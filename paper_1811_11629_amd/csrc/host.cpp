@@ -342,10 +342,10 @@ rsaprng_config resolve_config(const rsaprng_config* cfg) {
   if (c.prefix != kPrefixTwoPass && c.prefix != kPrefixLookback && c.prefix != kPrefixSerial)
     c.prefix = env_int("RSAPRNG_PREFIX", kPrefixTwoPass);
   if (c.prefix == kPrefixSerial) {
-    // chain-serial: (256, 8) or (512, 8), one step of WG V indices at a time
+    // chain-serial: (256, 8, r) for r = 2, 4 and (512, 8, 2)
     c.per_lane = 8;
-    c.chunks_per_wave = 1;
     if (c.lanes_per_tile != 512) c.lanes_per_tile = 256;
+    if (c.lanes_per_tile == 512 || c.chunks_per_wave != 4) c.chunks_per_wave = 2;
   } else if (c.prefix == kPrefixTwoPass) {
     // shapes built for two passes: (256, 8, r) for r = 1, 2, 4 and (512, 8, 2)
     c.per_lane = 8;
@@ -1079,8 +1079,8 @@ std::vector<rsaprng_config> tune_space() {
   static const int shapes[][4] = {{kPrefixTwoPass, 256, 8, 1}, {kPrefixTwoPass, 256, 8, 2},
                                   {kPrefixTwoPass, 256, 8, 4}, {kPrefixTwoPass, 512, 8, 2},
                                   {kPrefixLookback, 256, 8, 1}, {kPrefixLookback, 512, 8, 1},
-                                  {kPrefixLookback, 256, 16, 1}, {kPrefixSerial, 256, 8, 1},
-                                  {kPrefixSerial, 512, 8, 1}};
+                                  {kPrefixLookback, 256, 16, 1}, {kPrefixSerial, 256, 8, 2},
+                                  {kPrefixSerial, 256, 8, 4}, {kPrefixSerial, 512, 8, 2}};
   std::vector<rsaprng_config> out;
   for (int var : {kVariantCrt, kVariantMont})
     for (const auto& s : shapes)
@@ -1094,7 +1094,10 @@ std::vector<rsaprng_config> tune_space() {
         c.chunks_per_wave = s[3];
         c.persistent = pers;
         c.order = pers;
-        out.push_back(c);
+        c = resolve_config(&c);
+        bool dup = false;
+        for (const auto& o : out) dup = dup || std::memcmp(&o, &c, sizeof(c)) == 0;
+        if (!dup) out.push_back(c);
       }
   return out;
 }

@@ -88,6 +88,10 @@ __device__ __forceinline__ u64 lane_value(u64 v, int lane) {
   return ((u64)hi << 32) | lo;
 }
 
+__device__ __forceinline__ double lane_value_f64(double v, int lane) {
+  return __longlong_as_double((long long)lane_value((u64)__double_as_longlong(v), lane));
+}
+
 // ---------------------------------------------------------------------------
 // look-back words: (tag << 32) | half, two words per 64-bit value
 // ---------------------------------------------------------------------------
@@ -253,6 +257,41 @@ struct MsgRes {
       mq = reduce_res(mq, P.qd, P.qinv);
     }
     return encrypt_res<E>(mp, mq, P, cd);
+  }
+};
+
+// The same, walking the lane's skips from its first one as the indices are
+// taken (nothing kept from an earlier walk).
+template <int V>
+struct MsgResWalk {
+  u64 s;
+  double bp, bq;
+  double H = 0.0, L = 0.0;
+  template <int VAR, u32 E>
+  __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
+    if (i) s = lcg_next(s);
+    H += (double)hi32(s);
+    L += (double)lo32(s);
+    double mp = bp + fold_hl(H, L, P.pd, P.pinv, P.kp);
+    double mq = bq + fold_hl(H, L, P.qd, P.qinv, P.kq);
+    if constexpr (E < 2) {
+      mp = reduce_res(mp, P.pd, P.pinv);
+      mq = reduce_res(mq, P.qd, P.qinv);
+    }
+    return encrypt_res<E>(mp, mq, P, cd);
+  }
+};
+
+// Exact messages, walking: m_i = (pre + s_0 + ... + s_i) mod n.
+template <int V>
+struct MsgExactWalk {
+  u64 pre, n, s;
+  u64 x = 0;
+  template <int VAR, u32 E>
+  __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
+    if (i) s = lcg_next(s);
+    x = addmod(x, skip_mod_n(s, n), n);
+    return encrypt<VAR, E>(addmod(pre, x, n), P, cd);
   }
 };
 
@@ -519,28 +558,51 @@ __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG
   outputs_for_e<WG, V, VAR, MODE>(a, sh, C, P, msg, fast, laneStart);
 }
 
-// The same state from residue messages: m at the last index recombined by
+// The same state from residue messages (b the residues of the message before
+// the lane's first index, s_first its skip): m at the last index recombined by
 // Garner (encryption with e = 1) and the skip after it.
 template <int V>
 __device__ __forceinline__ void chain_end_res(const LaunchArgs& a, const Chain& C,
-                                              const rsaprng_params& P, const MsgRes<V>& msg,
-                                              u64 laneStart) {
+                                              const rsaprng_params& P, u64 s_first, double bp,
+                                              double bq, u64 laneStart) {
   if ((C.flags & kChainWriteEnd) && laneStart <= C.last && C.last - laneStart < (u64)V) {
     double H = 0.0, L = 0.0;
-    u64 s_last = 0;
+    u64 s = s_first, s_last = 0;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
+      if (i) s = lcg_next(s);
       if (laneStart + i <= C.last) {
-        H += (double)hi32(msg.S[i]);
-        L += (double)lo32(msg.S[i]);
-        s_last = msg.S[i];
+        H += (double)hi32(s);
+        L += (double)lo32(s);
+        s_last = s;
       }
     }
-    const double mp = reduce_res(msg.bp + fold_hl(H, L, P.pd, P.pinv, P.kp), P.pd, P.pinv);
-    const double mq = reduce_res(msg.bq + fold_hl(H, L, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+    const double mp = reduce_res(bp + fold_hl(H, L, P.pd, P.pinv, P.kp), P.pd, P.pinv);
+    const double mq = reduce_res(bq + fold_hl(H, L, P.qd, P.qinv, P.kq), P.qd, P.qinv);
     double cd;
     ChainState cs;
     cs.m_prev = garner(mp, mq, P.pd, P.qd, P.pinv, P.qinv, P.qinvp, P.q, cd);
+    cs.s_at = lcg_next(s_last);
+    a.state[C.slot] = cs;
+  }
+}
+
+// The exact state, walking from the lane's first skip.
+template <int V>
+__device__ __forceinline__ void chain_end_walk(const LaunchArgs& a, const Chain& C, u64 n,
+                                               u64 pre, u64 s_first, u64 laneStart) {
+  if ((C.flags & kChainWriteEnd) && laneStart <= C.last && C.last - laneStart < (u64)V) {
+    u64 s = s_first, x = 0, s_last = 0;
+#pragma unroll
+    for (int i = 0; i < V; ++i) {
+      if (i) s = lcg_next(s);
+      if (laneStart + i <= C.last) {
+        x = addmod(x, skip_mod_n(s, n), n);
+        s_last = s;
+      }
+    }
+    ChainState cs;
+    cs.m_prev = addmod(pre, x, n);
     cs.s_at = lcg_next(s_last);
     a.state[C.slot] = cs;
   }
@@ -621,7 +683,7 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
             reduce_res(residue(E[r], P.qd, P.qinv, P.kq) + (iq - tq), P.qd, P.qinv);
         const MsgRes<V> msg{S, bp, bq};
         if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-        chain_end_res<V>(a, C, P, msg, laneStart);
+        chain_end_res<V>(a, C, P, s_first, bp, bq, laneStart);
       } else {
         u64 X[V];
         const u64 x = walk<V>(s_first, n, X);
@@ -703,24 +765,28 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
   }
 }
 
-// Chain-serial: one work-group per chain walks it in steps of T = WG V
-// indices (wave w takes the w-th chunk of 64 V), carrying the message before
-// the step from one step to the next -- as residues mod p and q for the CRT
-// variant, exactly mod n for the Montgomery variant.  The waves exchange
-// their totals through LDS once per step (double-buffered by step parity, so
-// one barrier per step suffices).  Steps before the chain's first requested
-// index only walk.  No prefix pass is needed, so every skip is computed once.
-template <int WG, int V, int VAR, int MODE>
+// Chain-serial: one work-group per chain walks it in steps of T = WG V R
+// indices (wave w takes chunks w R .. w R + R - 1 of 64 V indices, so its R
+// >= 2 walks are independent), carrying the message before the step from one step
+// to the next -- as residues mod p and q for the CRT variant, exactly mod n
+// for the Montgomery variant.  The waves exchange their totals through LDS
+// once per step (double-buffered by step parity: one barrier per step).  The
+// output pass walks each chunk again from its first skip instead of keeping
+// R V skips across the barrier.  Steps before the chain's first requested
+// index only walk.  No prefix pass is needed.
+template <int WG, int V, int R, int VAR, int MODE>
 __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
   constexpr int NW = WG / 64;
-  constexpr u64 T = (u64)WG * V;
+  constexpr u64 T = (u64)WG * V * R;
   constexpr u64 CHUNK = 64ull * V;
   __shared__ TileShared<WG, MODE> sh;
   __shared__ double2 xch[2][NW];  // wave totals: residues (CRT) or the u64 bits in .x
   const int lane = threadIdx.x & 63;
   const u32 wave = uniform(threadIdx.x >> 6);
-  const u64 pvl = a.powv[threadIdx.x];  // a^(V thread): the lane's offset inside a step
-  const u64 aT = load_cst(a.at + 1);    // a^T mod Q
+  u64 pv[R];  // a^(offset of the lane's first index in each of its chunks)
+#pragma unroll
+  for (int r = 0; r < R; ++r) pv[r] = a.powv[((u64)wave * R + r) * 64 + lane];
+  const u64 aT = load_cst(a.at + 1);  // a^T mod Q
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
     __syncthreads();
@@ -732,7 +798,7 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
     const u64 n = P.n;
     // the chain ends at the request's last index or at the end of its 2^20 block
     const u64 clast = C.last < (C.S | (kBlock - 1)) ? C.last : (C.S | (kBlock - 1));
-    u64 s_lane = mulmod_q(cs0.s_S, pvl);
+    u64 s_step = cs0.s_S;       // skip at the step's first index
     double cp = 0.0, cq = 0.0;  // CRT carry: residues of the message before the step
     u64 cm = 0;                 // Montgomery carry: the message before the step
     if constexpr (VAR == kVariantCrt) {
@@ -743,26 +809,30 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
     }
     for (u32 step = 0;; ++step) {
       const u64 base = C.S + (u64)step * T;
-      const u64 chunkStart = base + wave * CHUNK;
-      const u64 laneStart = chunkStart + (u64)lane * V;
       const bool step_out = base + (T - 1) >= C.k0;  // uniform over the work-group
-      const bool chunk_out = MODE == kModeConsume
-                                 ? step_out
-                                 : chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast;
       const int par = step & 1;
+      u64 sf[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) sf[r] = mulmod_q(s_step, pv[r]);
       if constexpr (VAR == kVariantCrt) {
-        u64 S[V];
-        double Ht, Lt;
-        if (step_out) {
-          walk_halves<V>(s_lane, S, Ht, Lt);
-        } else {
-          walk_totals<V>(s_lane, Ht, Lt);
+        // per chunk: lane totals as residues, exclusive lane prefix plus the
+        // totals of the wave's earlier chunks
+        double ep[R], eq[R];
+        double wp = 0.0, wq = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double Ht, Lt;
+          walk_totals<V>(sf[r], Ht, Lt);
+          const double tp = reduce_res(fold_hl(Ht, Lt, P.pd, P.pinv, P.kp), P.pd, P.pinv);
+          const double tq = reduce_res(fold_hl(Ht, Lt, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+          const double ip = wave_scan_f64(tp, lane);
+          const double iq = wave_scan_f64(tq, lane);
+          ep[r] = wp + (ip - tp);
+          eq[r] = wq + (iq - tq);
+          wp += lane_value_f64(ip, 63);
+          wq += lane_value_f64(iq, 63);
         }
-        const double tp = reduce_res(fold_hl(Ht, Lt, P.pd, P.pinv, P.kp), P.pd, P.pinv);
-        const double tq = reduce_res(fold_hl(Ht, Lt, P.qd, P.qinv, P.kq), P.qd, P.qinv);
-        const double ip = wave_scan_f64(tp, lane);
-        const double iq = wave_scan_f64(tq, lane);
-        if (lane == 63) xch[par][wave] = make_double2(ip, iq);
+        if (lane == 63) xch[par][wave] = make_double2(wp, wq);
         __syncthreads();
         double op = 0.0, oq = 0.0, Tp = 0.0, Tq = 0.0;
 #pragma unroll
@@ -776,19 +846,33 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
           Tq += v.y;
         }
         if (step_out) {
-          const double bp = reduce_res(cp + op + (ip - tp), P.pd, P.pinv);
-          const double bq = reduce_res(cq + oq + (iq - tq), P.qd, P.qinv);
-          const MsgRes<V> msg{S, bp, bq};
-          if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-          chain_end_res<V>(a, C, P, msg, laneStart);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+            const u64 laneStart = chunkStart + (u64)lane * V;
+            const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
+            const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
+            const MsgResWalk<V> msg{sf[r], bp, bq};
+            const bool chunk_out = MODE == kModeConsume ||
+                                   (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
+            if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+            chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
+          }
         }
         cp = reduce_res(cp + Tp, P.pd, P.pinv);
         cq = reduce_res(cq + Tq, P.qd, P.qinv);
       } else {
-        u64 X[V];
-        const u64 x = walk<V>(s_lane, n, X);
-        const u64 incl = wave_scan_shfl(x, n, lane);
-        if (lane == 63) xch[par][wave].x = __longlong_as_double((long long)incl);
+        u64 ex[R];
+        u64 wt = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          u64 X[V];
+          const u64 x = walk<V>(sf[r], n, X);
+          const u64 incl = wave_scan_shfl(x, n, lane);
+          ex[r] = addmod(wt, submod(incl, x, n), n);
+          wt = addmod(wt, lane_value(incl, 63), n);
+        }
+        if (lane == 63) xch[par][wave].x = __longlong_as_double((long long)wt);
         __syncthreads();
         u64 off = 0, tot = 0;
 #pragma unroll
@@ -798,30 +882,38 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
           tot = addmod(tot, v, n);
         }
         if (step_out) {
-          const u64 pre = addmod(addmod(cm, off, n), submod(incl, x, n), n);
-          const MsgExact<V> msg{pre, n, X};
-          if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-          chain_end<V>(a, C, n, pre, X, s_lane, laneStart);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+            const u64 laneStart = chunkStart + (u64)lane * V;
+            const u64 pre = addmod(addmod(cm, off, n), ex[r], n);
+            const MsgExactWalk<V> msg{pre, n, sf[r]};
+            const bool chunk_out = MODE == kModeConsume ||
+                                   (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
+            if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+            chain_end_walk<V>(a, C, n, pre, sf[r], laneStart);
+          }
         }
         cm = addmod(cm, tot, n);
       }
       if (clast - base < T) break;
-      s_lane = mulmod_q(s_lane, aT);
+      s_step = mulmod_q(s_step, aT);
     }
   }
 }
 
-template <int WG, int V, int VAR, int MODE>
+template <int WG, int V, int R, int VAR, int MODE>
 static int launch3(const LaunchArgs& a, int grid, void* stream, int* occ) {
   if (occ) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen3<WG, V, VAR, MODE>, WG, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen3<WG, V, R, VAR, MODE>, WG, 0) !=
         hipSuccess)
       blocks = 1;
     *occ = blocks > 0 ? blocks : 1;
     return RSAPRNG_OK;
   }
-  hipLaunchKernelGGL((k_gen3<WG, V, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream, a);
+  hipLaunchKernelGGL((k_gen3<WG, V, R, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream,
+                     a);
   return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
@@ -864,12 +956,13 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
     if (s.wg == 512 && s.v == 8 && s.r == 2) return launch2<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
     return RSAPRNG_E_ARG;
   }
-  if (s.r != 1) return RSAPRNG_E_ARG;
   if (s.prefix == kPrefixSerial) {
-    if (s.wg == 256 && s.v == 8) return launch3<256, 8, VAR, MODE>(a, s.grid, stream, occ);
-    if (s.wg == 512 && s.v == 8) return launch3<512, 8, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 256 && s.v == 8 && s.r == 4) return launch3<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
     return RSAPRNG_E_ARG;
   }
+  if (s.r != 1) return RSAPRNG_E_ARG;
   if (s.wg == 256 && s.v == 8) return launch1<256, 8, VAR, MODE>(a, s.grid, stream, occ);
   if (s.wg == 512 && s.v == 8) return launch1<512, 8, VAR, MODE>(a, s.grid, stream, occ);
   if (s.wg == 256 && s.v == 16) return launch1<256, 16, VAR, MODE>(a, s.grid, stream, occ);
