@@ -371,6 +371,51 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
     return res
 
 
+def run_param_gen(R, torch, stream):
+    """Parameter generation: primes and safe primes in [2^31, 2^32) counted on the
+    device (the paper's counts are the check), and the next prime at or above
+    200,000 draws with the e = 3 filter; the oracle's sieve timed on a slice."""
+    import numpy as np
+
+    import inputs
+    import oracle
+    lo, hi = 1 << 31, 1 << 32
+    res = {}
+    for safe, want in ((False, 98182656), (True, 3060794)):
+        R.rsaprng_prime_count(lo, lo + (1 << 24), safe, stream=stream)   # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        got = R.rsaprng_prime_count(lo, hi, safe, stream=stream)
+        dt = time.perf_counter() - t0
+        key = "safe_prime_count" if safe else "prime_count"
+        res[key] = {"range": "[2^31, 2^32)", "count": got, "matches_paper": got == want,
+                    "ms": dt * 1e3, "gnumbers_tested_per_s": (hi - lo) / dt / 1e9}
+        log("%s: %d (%s) in %.1f ms" % (key, got, "= paper" if got == want else "MISMATCH", dt * 1e3))
+    rng = inputs.SplitMix64(181111629 + 6)
+    x = torch.tensor([(1 << 31) + (rng.next() >> 33) for _ in range(200000)], dtype=torch.int64,
+                     device="cuda")
+    out = torch.empty_like(x)
+    R.rsaprng_next_primes(x, out, exps=(3,), stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    R.rsaprng_next_primes(x, out, exps=(3,), stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    got = out.cpu().numpy().view(np.uint64)
+    idx = np.random.default_rng(5).choice(len(got), 64, replace=False)
+    ok = all(int(got[i]) == oracle.next_prime(int(x[i].item()), False, (3,)) for i in idx)
+    res["next_primes"] = {"queries": 200000, "filter": "p mod 3 != 1", "ms": dt * 1e3,
+                          "queries_per_s": 200000 / dt, "verified_samples": ok}
+    t0 = time.perf_counter()
+    oracle.count_primes(lo, lo + (1 << 28))
+    dtc = time.perf_counter() - t0
+    res["cpu_oracle_sieve"] = {"gnumbers_tested_per_s": (1 << 28) / dtc / 1e9, "cores": 1,
+                               "sample": "primes in [2^31, 2^31 + 2^28) by the oracle's sieve"}
+    log("next_primes: %.1f ms for 200000 (%s); oracle sieve %.2f Gnum/s" % (
+        dt * 1e3, "verified" if ok else "MISMATCH", res["cpu_oracle_sieve"]["gnumbers_tested_per_s"]))
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -467,6 +512,7 @@ def main():
         extras["exponent_sweep_consume"] = run_consume_sweep(R, torch, stream, args.steps)
         extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
         extras["served"] = run_served(R, torch, stream)
+        extras["parameter_generation"] = run_param_gen(R, torch, stream)
 
     cpu = None if args.no_cpu else cpu_baseline(insts, 1024 * B)
     if cpu:

@@ -288,6 +288,24 @@ int64_t rsaprng_server_simulate(const rsaprng_config* cfg, uint64_t arena_elems,
 void rsaprng_server_destroy(rsaprng_server_t s);
 
 /* ---------------------------------------------------------------------------
+ * Parameter generation on the device (Implementation section: the primes of
+ * an instance lie in [2^31, 2^32), deterministic Miller-Rabin with the first
+ * five prime bases below 2^32, and safe primes p = 2 p' + 1 with p' prime as
+ * the recommended class).
+ * rsaprng_prime_count: number of primes (safe primes if safe != 0) in
+ *   [lo, hi), hi <= 2^32; waits for the result on `stream` (allocates 8 bytes
+ *   of device memory for the call).
+ * rsaprng_next_primes: for each of n device values x[i], out[i] = the smallest
+ *   p in [x[i], min(x[i] + 2^24, 2^32)) that is prime (safe if asked) with
+ *   p mod f != 1 for every f in the host array exps[0..nexp) (nexp <= 8, each
+ *   f >= 2: the exponent filter gcd(f, p - 1) = 1 for prime f), or 0 if there
+ *   is none.  Device arrays, 8-byte aligned; enqueued on `stream`.
+ * ------------------------------------------------------------------------ */
+int rsaprng_prime_count(uint64_t lo, uint64_t hi, int safe, uint64_t* count, void* stream);
+int rsaprng_next_primes(const uint64_t* x, uint64_t n, int safe, const uint32_t* exps, int nexp,
+                        uint64_t* out, void* stream);
+
+/* ---------------------------------------------------------------------------
  * Checks and test entry points.
  * ------------------------------------------------------------------------ */
 /* Returns RSAPRNG_E_DEVICE if a kernel on this stream's scratch flagged an

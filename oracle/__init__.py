@@ -77,6 +77,8 @@ def lib():
                 "oracle_encrypt_array": (None, [u64, u64, P64, P64, u64]),
                 "oracle_consume": (i32, [u64] * 7 + [C.POINTER(Stats)]),
                 "oracle_stats_of": (None, [PD, u64, C.POINTER(Stats)]),
+                "oracle_count_primes": (u64, [u64, u64, i32]),
+                "oracle_next_prime": (u64, [u64, i32, C.c_void_p, i32]),
             }
             for name, (res, args) in sig.items():
                 f = getattr(L, name)
@@ -164,3 +166,14 @@ def stats_of(r):
 def generate_instance(inst, k0, count, want_c=True, want_r=True):
     """Convenience: an object with p, q, e, m0, s0 attributes."""
     return generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, count, want_c, want_r)
+
+
+def count_primes(lo, hi, safe=False):
+    """Primes (or safe primes) in [lo, hi), hi <= 2^32, by a segmented sieve."""
+    return lib().oracle_count_primes(lo, hi, 1 if safe else 0)
+
+
+def next_prime(x, safe=False, exps=()):
+    """Smallest p >= x below 2^32, prime (safe if asked), p mod f != 1 for f in exps; 0 if none."""
+    arr = (C.c_uint32 * max(1, len(exps)))(*exps)
+    return lib().oracle_next_prime(x, 1 if safe else 0, arr, len(exps))

@@ -8,6 +8,7 @@
 
 #include <math.h>
 #include <stddef.h>
+#include <stdlib.h>
 #include <string.h>
 
 typedef unsigned __int128 u128;
@@ -288,4 +289,81 @@ int oracle_consume(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
   memset(st, 0, sizeof(*st));
   struct gen_ctx g = {p * q, e, k0, NULL, NULL, NULL, st};
   return walk(p, q, m0, s0, k0, count, emit_stats, &g);
+}
+
+/* ------------------------------------------------------------------------
+ * Parameter generation (Implementation section: 32-bit primes, and the safe
+ * primes p = 2 p' + 1 with p' prime that the paper recommends).
+ * ---------------------------------------------------------------------- */
+
+/* Number of primes (safe primes when safe != 0) in [lo, hi), hi <= 2^32, by a
+ * sieve of Eratosthenes over segments: every composite below 2^32 has a prime
+ * factor below 2^16.  For safe primes both p and (p - 1)/2 are looked up in
+ * sieved segments. */
+static void sieve_segment(uint64_t lo, uint64_t len, const uint32_t* small, int ns,
+                          unsigned char* isp) {
+  memset(isp, 1, len);
+  for (uint64_t i = 0; i < len; ++i)
+    if (lo + i < 2) isp[i] = 0;
+  for (int k = 0; k < ns; ++k) {
+    const uint64_t p = small[k];
+    if (p * p >= lo + len) break;
+    uint64_t m = (lo + p - 1) / p * p;
+    if (m < p * p) m = p * p;
+    for (; m < lo + len; m += p) isp[m - lo] = 0;
+  }
+}
+
+static int small_primes(uint32_t* out) {
+  static unsigned char comp[1 << 16];
+  int ns = 0;
+  memset(comp, 0, sizeof(comp));
+  for (uint32_t i = 2; i < (1u << 16); ++i) {
+    if (comp[i]) continue;
+    out[ns++] = i;
+    for (uint32_t j = i * i; j < (1u << 16); j += i) comp[j] = 1;
+  }
+  return ns;
+}
+
+uint64_t oracle_count_primes(uint64_t lo, uint64_t hi, int safe) {
+  if (hi > (1ULL << 32)) hi = 1ULL << 32;
+  if (lo >= hi) return 0;
+  static uint32_t small[6542];
+  const int ns = small_primes(small);
+  const uint64_t SEG = 1ULL << 22;
+  unsigned char* a = (unsigned char*)malloc(SEG);
+  unsigned char* b = (unsigned char*)malloc(SEG / 2 + 2);
+  uint64_t count = 0;
+  for (uint64_t s = lo; s < hi; s += SEG) {
+    const uint64_t len = hi - s < SEG ? hi - s : SEG;
+    sieve_segment(s, len, small, ns, a);
+    if (!safe) {
+      for (uint64_t i = 0; i < len; ++i) count += a[i];
+      continue;
+    }
+    /* halves (p - 1)/2 of the candidates p in [s, s + len) lie in [h0, h0 + hl) */
+    const uint64_t h0 = s / 2 > 0 ? (s - 1) / 2 : 0;
+    const uint64_t hl = (s + len - 1) / 2 - h0 + 1;
+    sieve_segment(h0, hl, small, ns, b);
+    for (uint64_t i = 0; i < len; ++i) {
+      const uint64_t p = s + i;
+      if (a[i] && p >= 5 && b[(p - 1) / 2 - h0]) ++count;
+    }
+  }
+  free(a);
+  free(b);
+  return count;
+}
+
+/* Smallest p >= x, p < 2^32, prime (safe if asked) with p mod f != 1 for each
+ * f in exps[0..nexp); 0 if there is none. */
+uint64_t oracle_next_prime(uint64_t x, int safe, const uint32_t* exps, int nexp) {
+  for (uint64_t p = x; p < (1ULL << 32); ++p) {
+    int ok = oracle_is_prime(p) && (!safe || (p >= 5 && oracle_is_prime((p - 1) / 2)));
+    for (int f = 0; ok && f < nexp; ++f)
+      if (p % exps[f] == 1) ok = 0;
+    if (ok) return p;
+  }
+  return 0;
 }

@@ -99,6 +99,13 @@ int oracle_consume(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
 /* Same statistics over a given array of r values. */
 void oracle_stats_of(const double* r, uint64_t count, oracle_stats* st);
 
+/* Parameter generation (Implementation section).  Number of primes, or safe
+ * primes p = 2 p' + 1 with p' prime, in [lo, hi) for hi <= 2^32, by a segmented
+ * sieve; and the smallest p >= x below 2^32 that is prime (safe if asked) with
+ * p mod f != 1 for every listed f, or 0. */
+uint64_t oracle_count_primes(uint64_t lo, uint64_t hi, int safe);
+uint64_t oracle_next_prime(uint64_t x, int safe, const uint32_t* exps, int nexp);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1206,6 +1206,38 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
   return RSAPRNG_OK;
 }
 
+int rsaprng_prime_count(uint64_t lo, uint64_t hi, int safe, uint64_t* count, void* stream) {
+  if (!count) return RSAPRNG_E_NULL;
+  if (hi > (1ull << 32) || lo > hi) return RSAPRNG_E_RANGE;
+  Device* d;
+  int rc;
+  if ((rc = device_get(&d))) return rc;
+  unsigned long long* dev = nullptr;
+  if (hipMalloc(&dev, sizeof(*dev)) != hipSuccess) return RSAPRNG_E_OOM;
+  rc = launch_count_primes(lo, hi, safe, dev, stream);
+  unsigned long long h = 0;
+  if (!rc && hipMemcpyAsync(&h, dev, sizeof(h), hipMemcpyDeviceToHost, (hipStream_t)stream) !=
+                 hipSuccess)
+    rc = RSAPRNG_E_HIP;
+  if (!rc && hipStreamSynchronize((hipStream_t)stream) != hipSuccess) rc = RSAPRNG_E_HIP;
+  (void)hipFree(dev);
+  if (!rc) *count = h;
+  return rc;
+}
+
+int rsaprng_next_primes(const uint64_t* x, uint64_t n, int safe, const uint32_t* exps, int nexp,
+                        uint64_t* out, void* stream) {
+  if (n && (!x || !out)) return RSAPRNG_E_NULL;
+  if (nexp < 0 || nexp > 8 || (nexp && !exps)) return RSAPRNG_E_ARG;
+  for (int i = 0; i < nexp; ++i)
+    if (exps[i] < 2) return RSAPRNG_E_ARG;
+  if (misaligned(x) || misaligned(out)) return RSAPRNG_E_ALIGN;
+  Device* d;
+  int rc;
+  if ((rc = device_get(&d))) return rc;
+  return launch_next_primes(x, n, safe, exps, nexp, 1ull << 24, out, stream);
+}
+
 int rsaprng_check_device_error(void* stream) {
   Scratch* sc;
   int rc;

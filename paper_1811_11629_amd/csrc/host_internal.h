@@ -72,6 +72,12 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks = nullptr);
+// Parameter generation kernels (k_primes.hip).
+int launch_count_primes(uint64_t lo, uint64_t hi, int safe, unsigned long long* count_dev,
+                        void* stream);
+int launch_next_primes(const uint64_t* x, uint64_t n, int safe, const uint32_t* exps, int nexp,
+                       uint64_t span, uint64_t* out, void* stream);
+
 const rsaprng_params* pool_dev(rsaprng_pool_t pool);
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i);
 int pool_device(rsaprng_pool_t pool);

@@ -120,6 +120,8 @@ _SIGS = {
     "rsaprng_server_create": (_i32, [_vp, C.POINTER(rsaprng_server_opts), C.POINTER(_vp)]),
     "rsaprng_server_submit": (_i32, [_vp, _u32, _u64, _u64, _u64]),
     "rsaprng_server_poll": (_i32, [_vp, C.POINTER(rsaprng_completion), _sz]),
+    "rsaprng_prime_count": (_i32, [_u64, _u64, _i32, C.POINTER(_u64), _vp]),
+    "rsaprng_next_primes": (_i32, [_vp, _u64, _i32, _vp, _i32, _vp, _vp]),
     "rsaprng_server_read": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _vp]),
     "rsaprng_server_release": (_i32, [_vp, _u64]),
     "rsaprng_server_replay": (_i32, [_vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
@@ -412,6 +414,22 @@ def server_simulate(k0, count, arrive_iter, arena_elems, iter_outputs=0, chunk_o
                                          nch)
     assert nch2 == nch
     return log[:nch]
+
+
+def rsaprng_prime_count(lo: int, hi: int, safe: bool = False, stream=None) -> int:
+    """Number of primes (safe primes) in [lo, hi), hi <= 2^32, counted on the device."""
+    out = C.c_uint64(0)
+    _check(lib().rsaprng_prime_count(lo, hi, 1 if safe else 0, C.byref(out), _stream(stream)),
+           "rsaprng_prime_count")
+    return out.value
+
+
+def rsaprng_next_primes(x, out, safe: bool = False, exps=(), stream=None) -> None:
+    """out[i] = smallest qualifying prime >= x[i] (device tensors of int64), or 0."""
+    n = len(x)
+    arr = (C.c_uint32 * max(1, len(exps)))(*exps)
+    _check(lib().rsaprng_next_primes(_ptr(x), n, 1 if safe else 0, arr, len(exps), _ptr(out),
+                                     _stream(stream)), "rsaprng_next_primes")
 
 
 class Server:
