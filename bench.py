@@ -371,6 +371,42 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
     return res
 
 
+def run_battery(R, torch, stream, steps):
+    """The statistical battery as a fused consumer over 2^30 outputs (the
+    exponent-sweep instances at e = 3, 2^18 indices each) into one record."""
+    import inputs
+    base = inputs.config3()
+    insts = [inputs.Instance(i.p, i.q, 3, i.m0) for i in base]
+    pool = R.Pool.from_instances(insts)
+    reqs = [(i, 0, 1 << 18, 0) for i in range(len(insts))]
+    rec = R.battery_tensor()
+    best = None
+    t_best = 1e30
+    for cfg in (R.config(variant=2, prefix=2, lanes_per_tile=256, chunks_per_wave=4),
+                R.config(variant=2, prefix=0, lanes_per_tile=256, chunks_per_wave=4)):
+        R.rsaprng_pool_battery(pool, reqs, rec, cfg=cfg, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(max(2, steps // 4)):
+            R.rsaprng_pool_battery(pool, reqs, rec, cfg=cfg, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / max(2, steps // 4)
+        if dt < t_best:
+            t_best, best = dt, cfg
+    R.rsaprng_check_device_error(stream)
+    rep = R.battery_report(rec)
+    n = len(insts) << 18
+    res = {"workload": "4096 instances, e = 3, k in [0, 2^18): 2^30 outputs into one record",
+           "gnumbers_per_s": n / t_best / 1e9, "ms": t_best * 1e3, "config": best.as_dict(),
+           "tests": rep,
+           "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep.values())}
+    log("battery: %.1f Gnum/s (%.2f ms); p-values %s" % (
+        res["gnumbers_per_s"], t_best * 1e3, " ".join("%s=%.3f" % (k, v["p"]) for k, v in rep.items())))
+    del rec, pool
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_param_gen(R, torch, stream):
     """Parameter generation: primes and safe primes in [2^31, 2^32) counted on the
     device (the paper's counts are the check), and the next prime at or above
@@ -513,6 +549,7 @@ def main():
         extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
         extras["served"] = run_served(R, torch, stream)
         extras["parameter_generation"] = run_param_gen(R, torch, stream)
+        extras["battery"] = run_battery(R, torch, stream, args.steps)
 
     cpu = None if args.no_cpu else cpu_baseline(insts, 1024 * B)
     if cpu:

@@ -288,6 +288,60 @@ int64_t rsaprng_server_simulate(const rsaprng_config* cfg, uint64_t arena_elems,
 void rsaprng_server_destroy(rsaprng_server_t s);
 
 /* ---------------------------------------------------------------------------
+ * Statistical battery as a fused consumer (Tests section: one-dimensional
+ * frequency with 2^20 bins; serial tests in D = 2..6 dimensions with 2^20 or
+ * 10^6 bins; the poker test with five cards of sixteen denominations; the
+ * maximum of t = 32).  The counts of every output r_k, k in [k0, k0+count), of
+ * every request are accumulated into ONE device record; no output is stored.
+ * Grouping (this library's reading; the tuples must not depend on how the work
+ * is tiled): tuples are taken inside aligned blocks of 8 indices (k = 8j ..
+ * 8j+7, absolute index): D-tuples at offsets 0, D, 2D, ... that fit in the
+ * block (floor(8/D) per block), the poker hand is offsets 0..4, and the
+ * maximum of 32 uses aligned blocks of 32 indices; a block counts only when
+ * all its indices are requested.  Bins: floor(b r) for b bins per coordinate
+ * (a serial cell is the mixed-radix number of its coordinates, first index
+ * most significant), the poker class is the number of distinct floor(16 r),
+ * and the maximum M of 32 goes to bin floor(1024 M^32) (M^32 by five exact
+ * squarings; it is uniform when the r are).  Counts are unsigned 32-bit (per
+ * bin; wraps after 2^32).
+ * ------------------------------------------------------------------------ */
+#define RSAPRNG_BAT_TESTS 8   /* frequency, serial D = 2..6, poker, max-of-32 */
+typedef struct {
+  uint64_t outputs;           /* number of r_k consumed */
+  uint64_t reserved;
+  uint32_t freq[1 << 20];     /* bin floor(2^20 r) */
+  uint32_t serial2[1 << 20];  /* 1024 bins per coordinate */
+  uint32_t serial3[1000000];  /* 100 */
+  uint32_t serial4[1 << 20];  /* 32 */
+  uint32_t serial5[1 << 20];  /* 16 */
+  uint32_t serial6[1000000];  /* 10 */
+  uint32_t poker[8];          /* [d] = hands with d distinct values, d = 1..5 */
+  uint32_t maxt[1024];        /* bin floor(1024 M^32) */
+} rsaprng_battery;
+
+/* Zeroes *rec_dev, then accumulates every request into it (reqs[i].out_off is
+ * ignored).  The CRT variant is used whatever cfg->variant says. */
+int rsaprng_pool_battery(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
+                         rsaprng_battery* rec_dev, const rsaprng_config* cfg, void* stream);
+
+/* Chi-squared statistic, degrees of freedom and p-value (the upper tail
+ * P(X >= chi2) of the chi-squared distribution) of each test, in the order of
+ * RSAPRNG_BAT_TESTS, from a HOST copy of a record: uniform expectations for the
+ * frequency, serial and max tests, and for poker the exact probabilities
+ * S(5, d) 16 15 ... (16 - d + 1) / 16^5 (S: Stirling numbers of the second
+ * kind), with the classes d = 1, 2 merged.  Host only. */
+typedef struct {
+  double chi2[RSAPRNG_BAT_TESTS];
+  double dof[RSAPRNG_BAT_TESTS];
+  double p[RSAPRNG_BAT_TESTS];
+  uint64_t samples[RSAPRNG_BAT_TESTS];  /* tuples, hands or maxima counted */
+} rsaprng_battery_result;
+int rsaprng_battery_report(const rsaprng_battery* rec_host, rsaprng_battery_result* out);
+
+/* Upper tail of the chi-squared distribution with dof degrees of freedom. */
+double rsaprng_chi2_sf(double chi2, double dof);
+
+/* ---------------------------------------------------------------------------
  * Parameter generation on the device (Implementation section: the primes of
  * an instance lie in [2^31, 2^32), deterministic Miller-Rabin with the first
  * five prime bases below 2^32, and safe primes p = 2 p' + 1 with p' prime as

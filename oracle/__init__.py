@@ -78,6 +78,7 @@ def lib():
                 "oracle_consume": (i32, [u64] * 7 + [C.POINTER(Stats)]),
                 "oracle_stats_of": (None, [PD, u64, C.POINTER(Stats)]),
                 "oracle_count_primes": (u64, [u64, u64, i32]),
+                "oracle_battery_add": (i32, [u64] * 7 + [C.c_void_p]),
                 "oracle_next_prime": (u64, [u64, i32, C.c_void_p, i32]),
             }
             for name, (res, args) in sig.items():
@@ -177,3 +178,33 @@ def next_prime(x, safe=False, exps=()):
     """Smallest p >= x below 2^32, prime (safe if asked), p mod f != 1 for f in exps; 0 if none."""
     arr = (C.c_uint32 * max(1, len(exps)))(*exps)
     return lib().oracle_next_prime(x, 1 if safe else 0, arr, len(exps))
+
+
+BATTERY_FIELDS = [("outputs", 1, np.uint64), ("reserved", 1, np.uint64),
+                  ("freq", 1 << 20, np.uint32), ("serial2", 1 << 20, np.uint32),
+                  ("serial3", 1000000, np.uint32), ("serial4", 1 << 20, np.uint32),
+                  ("serial5", 1 << 20, np.uint32), ("serial6", 1000000, np.uint32),
+                  ("poker", 8, np.uint32), ("maxt", 1024, np.uint32)]
+BATTERY_BYTES = sum(n * np.dtype(t).itemsize for _, n, t in BATTERY_FIELDS)
+
+
+def battery_decode(buf):
+    """bytes of a battery record -> dict of numpy arrays (shared layout with C)."""
+    out, off = {}, 0
+    raw = np.frombuffer(buf, dtype=np.uint8)
+    for name, n, t in BATTERY_FIELDS:
+        size = n * np.dtype(t).itemsize
+        out[name] = raw[off:off + size].view(t).copy()
+        off += size
+    return out
+
+
+def battery(ranges):
+    """Battery counts over [(instance, k0, count), ...], accumulated into one record."""
+    buf = np.zeros(BATTERY_BYTES, dtype=np.uint8)
+    for inst, k0, count in ranges:
+        rc = lib().oracle_battery_add(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, count,
+                                      buf.ctypes.data)
+        if rc:
+            raise ValueError("oracle_battery_add: %d" % rc)
+    return battery_decode(buf.tobytes())

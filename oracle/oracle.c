@@ -367,3 +367,71 @@ uint64_t oracle_next_prime(uint64_t x, int safe, const uint32_t* exps, int nexp)
   }
   return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Statistical battery (Tests section), counted from the oracle's own
+ * outputs by the definitions stated in oracle.h.
+ * ---------------------------------------------------------------------- */
+static uint32_t bin_of(double r, double b, uint32_t nb) {
+  uint32_t x = (uint32_t)(r * b);
+  return x < nb ? x : nb - 1;
+}
+
+int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
+                       uint64_t count, oracle_battery* B) {
+  if (count == 0) return 0;
+  double* r = (double*)malloc(count * sizeof(double));
+  if (!r) return -9;
+  int rc = oracle_generate(p, q, e, m0, s0, k0, count, NULL, r);
+  if (rc) {
+    free(r);
+    return rc;
+  }
+  const uint64_t last = k0 + (count - 1);
+  for (uint64_t i = 0; i < count; ++i) B->freq[bin_of(r[i], 1048576.0, 1u << 20)]++;
+  B->outputs += count;
+  /* aligned blocks of 8 indices inside [k0, last] */
+  for (uint64_t k8 = (k0 + 7) / 8 * 8; k8 >= k0 && k8 <= last && last - k8 >= 7; k8 += 8) {
+    const double* x = r + (k8 - k0);
+    for (int t = 0; t < 4; ++t)
+      B->serial2[bin_of(x[2 * t], 1024.0, 1024) * 1024 + bin_of(x[2 * t + 1], 1024.0, 1024)]++;
+    for (int t = 0; t < 2; ++t)
+      B->serial3[(bin_of(x[3 * t], 100.0, 100) * 100 + bin_of(x[3 * t + 1], 100.0, 100)) * 100 +
+                 bin_of(x[3 * t + 2], 100.0, 100)]++;
+    for (int t = 0; t < 2; ++t) {
+      uint32_t c = 0;
+      for (int j = 0; j < 4; ++j) c = c * 32 + bin_of(x[4 * t + j], 32.0, 32);
+      B->serial4[c]++;
+    }
+    uint32_t c5 = 0, c6 = 0, seen = 0;
+    for (int j = 0; j < 5; ++j) c5 = c5 * 16 + bin_of(x[j], 16.0, 16);
+    for (int j = 0; j < 6; ++j) c6 = c6 * 10 + bin_of(x[j], 10.0, 10);
+    B->serial5[c5]++;
+    B->serial6[c6]++;
+    /* number of distinct card values among the first five */
+    int distinct = 0;
+    for (int j = 0; j < 5; ++j) {
+      uint32_t v = bin_of(x[j], 16.0, 16);
+      if (!(seen & (1u << v))) {
+        seen |= 1u << v;
+        ++distinct;
+      }
+    }
+    B->poker[distinct]++;
+    if (k8 > UINT64_MAX - 8) break;
+  }
+  /* aligned blocks of 32: the maximum M, binned by floor(1024 M^32) */
+  for (uint64_t k32 = (k0 + 31) / 32 * 32; k32 >= k0 && k32 <= last && last - k32 >= 31; k32 += 32) {
+    double mx = 0.0;
+    for (int j = 0; j < 32; ++j) {
+      double v = r[k32 - k0 + j];
+      if (v > mx) mx = v;
+    }
+    double t = mx;
+    for (int j = 0; j < 5; ++j) t = t * t;
+    B->maxt[bin_of(t, 1024.0, 1024)]++;
+    if (k32 > UINT64_MAX - 32) break;
+  }
+  free(r);
+  return 0;
+}

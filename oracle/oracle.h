@@ -106,6 +106,31 @@ void oracle_stats_of(const double* r, uint64_t count, oracle_stats* st);
 uint64_t oracle_count_primes(uint64_t lo, uint64_t hi, int safe);
 uint64_t oracle_next_prime(uint64_t x, int safe, const uint32_t* exps, int nexp);
 
+/* Statistical battery (Tests section: frequency with 2^20 bins, serial tests
+ * in D = 2..6 dimensions, poker with five cards of sixteen denominations,
+ * maximum of t = 32).  Groups: inside aligned blocks of 8 absolute indices
+ * (8j .. 8j+7) the D-tuples at offsets 0, D, 2D, ... that fit, and the poker
+ * hand at offsets 0..4; aligned blocks of 32 for the maximum; only blocks whose
+ * indices all lie in [k0, k0+count) count.  Bin of r with b bins per
+ * coordinate: min(floor(b r), b - 1); a serial cell is the mixed-radix number
+ * of its coordinates, first index most significant; the poker class is the
+ * number of distinct floor(16 r); the maximum M goes to floor(1024 M^32) with
+ * M^32 by five squarings.  oracle_battery_add ACCUMULATES into *b. */
+typedef struct {
+  uint64_t outputs;
+  uint64_t reserved;
+  uint32_t freq[1 << 20];
+  uint32_t serial2[1 << 20];
+  uint32_t serial3[1000000];
+  uint32_t serial4[1 << 20];
+  uint32_t serial5[1 << 20];
+  uint32_t serial6[1000000];
+  uint32_t poker[8];
+  uint32_t maxt[1024];
+} oracle_battery;
+int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
+                       uint64_t count, oracle_battery* b);
+
 #ifdef __cplusplus
 }
 #endif

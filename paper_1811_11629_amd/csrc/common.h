@@ -76,7 +76,7 @@ struct DevCtl {
 };
 
 enum Variant : int { kVariantAuto = 0, kVariantMont = 1, kVariantCrt = 2 };
-enum Mode : int { kModeGenerate = 0, kModeConsume = 1 };
+enum Mode : int { kModeGenerate = 0, kModeConsume = 1, kModeBattery = 2 };
 // How a tile learns the message before it: two passes (tile sums, scan, then
 // generate), one pass with a decoupled look-back, or chain-serial (one
 // work-group walks a whole chain and carries the prefix from step to step).
@@ -100,6 +100,7 @@ struct LaunchArgs {
   uint64_t* out_c;
   double* out_r;
   rsaprng_stats* stats;
+  rsaprng_battery* battery;
   ChainState* state;
   DevCtl* ctl;
   const uint64_t* pow2;    // a^(2^i) mod Q, i < 64
@@ -124,6 +125,7 @@ int launch_chain_setup(const LaunchArgs& args, void* stream);
 int launch_sums(const LaunchArgs& args, void* stream);
 int launch_scan(const LaunchArgs& args, void* stream);
 int launch_tiles(const KernelShape& shape, const LaunchArgs& args, void* stream);
+int launch_battery_zero(rsaprng_battery* rec, void* stream);
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_stats_finalize(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t* m, uint64_t* c,

@@ -390,7 +390,7 @@ int plan_requests(const PlanIn* in_raw, size_t nreq_raw, const rsaprng_config& c
       PlanIn& m = merged.back();
       const bool plain = !(m.flags | r.flags);
       const bool adj_k = m.count && r.k0 == m.k0 + m.count && r.k0 > m.k0;
-      const bool adj_o = mode == kModeConsume ? r.slot == m.slot : r.out_off == m.out_off + m.count;
+      const bool adj_o = mode != kModeGenerate ? r.slot == m.slot : r.out_off == m.out_off + m.count;
       if (plain && r.inst == m.inst && adj_k && adj_o && r.count) {
         m.count += r.count;
         continue;
@@ -498,7 +498,8 @@ static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
-                   ChainState* state, void* stream, hipEvent_t* marks) {
+                   ChainState* state, void* stream, hipEvent_t* marks,
+                   rsaprng_battery* battery) {
   int rc;
   auto mark = [&](int i) {
     return !marks || hipEventRecord(marks[i], (hipStream_t)stream) == hipSuccess ? RSAPRNG_OK
@@ -506,6 +507,7 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   };
   if ((rc = mark(0))) return rc;
   if (mode == kModeConsume && nstats && (rc = launch_stats_zero(stats, nstats, stream))) return rc;
+  if (mode == kModeBattery && (rc = launch_battery_zero(battery, stream))) return rc;
   if (ntiles == 0) {
     if (mode == kModeConsume && nstats && (rc = launch_stats_finalize(stats, nstats, stream)))
       return rc;
@@ -544,6 +546,7 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   a.out_c = out_c;
   a.out_r = out_r;
   a.stats = stats;
+  a.battery = battery;
   a.state = state;
   a.ctl = sc->ctl;
   a.pow2 = d->pow2;
@@ -849,28 +852,35 @@ static size_t stats_records(const rsaprng_pool_req* reqs, size_t nreq) {
 
 int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
                 uint64_t* out_u64, double* out_f64, rsaprng_stats* stats,
-                const rsaprng_config* cfg, void* stream) {
+                const rsaprng_config* cfg, void* stream, rsaprng_battery* battery = nullptr) {
   if (!pool || (nreq && !reqs)) return RSAPRNG_E_NULL;
-  if (misaligned(out_u64) || misaligned(out_f64) || misaligned(stats)) return RSAPRNG_E_ALIGN;
+  if (misaligned(out_u64) || misaligned(out_f64) || misaligned(stats) || misaligned(battery))
+    return RSAPRNG_E_ALIGN;
   if (mode == kModeConsume && !stats) return RSAPRNG_E_NULL;
+  if (mode == kModeBattery && !battery) return RSAPRNG_E_NULL;
   if (mode == kModeGenerate && !out_u64 && !out_f64) return RSAPRNG_OK;
   Device* d;
   Scratch* sc;
   int rc;
   if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
   rsaprng_config c = resolve_config(cfg);
+  if (mode == kModeBattery && c.variant != kVariantCrt) {
+    rsaprng_config c2 = c;
+    c2.variant = kVariantCrt;
+    c = resolve_config(&c2);
+  }
   std::vector<Chain> plan;
   u64h ntiles;
   if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
   const size_t nst = mode == kModeConsume ? stats_records(reqs, nreq) : 0;
   if (plan.empty())
     return enqueue_launch(d, sc, c, mode, pool->dev, nullptr, 0, 0, out_u64, out_f64, stats, nst,
-                          nullptr, stream);
+                          nullptr, stream, nullptr, battery);
   void* dreq;
   int slot;
   if ((rc = sc->upload(plan.data(), plan.size() * sizeof(Chain), stream, &dreq, &slot))) return rc;
   rc = enqueue_launch(d, sc, c, mode, pool->dev, (const Chain*)dreq, (uint32_t)plan.size(), ntiles,
-                      out_u64, out_f64, stats, nst, nullptr, stream);
+                      out_u64, out_f64, stats, nst, nullptr, stream, nullptr, battery);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -888,6 +898,85 @@ int rsaprng_pool_generate(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, siz
 int rsaprng_pool_consume(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
                          rsaprng_stats* stats_dev, const rsaprng_config* cfg, void* stream) {
   return pool_launch(pool, reqs, nreq, kModeConsume, nullptr, nullptr, stats_dev, cfg, stream);
+}
+
+int rsaprng_pool_battery(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
+                         rsaprng_battery* rec_dev, const rsaprng_config* cfg, void* stream) {
+  return pool_launch(pool, reqs, nreq, kModeBattery, nullptr, nullptr, nullptr, cfg, stream,
+                     rec_dev);
+}
+
+// Upper tail of the chi-squared distribution: the regularised upper incomplete
+// gamma function Q(k/2, x/2), by its power series for P below a + 1 and by the
+// continued fraction for Q above (evaluated with the modified Lentz method).
+double rsaprng_chi2_sf(double chi2, double dof) {
+  if (!(dof > 0.0)) return 0.0 / 0.0;
+  if (!(chi2 > 0.0)) return 1.0;
+  const double a = 0.5 * dof, x = 0.5 * chi2;
+  const double lpre = a * std::log(x) - x - std::lgamma(a);  // log(x^a e^-x / Gamma(a))
+  if (x < a + 1.0) {
+    double term = 1.0 / a, sum = term;
+    for (int k = 1; k < 100000; ++k) {
+      term *= x / (a + k);
+      sum += term;
+      if (term < sum * 1e-16) break;
+    }
+    return 1.0 - std::exp(lpre) * sum;
+  }
+  const double tiny = 1e-300;
+  double b = x + 1.0 - a, c = 1.0 / tiny, d = 1.0 / b, h = d;
+  for (int i = 1; i < 100000; ++i) {
+    const double an = -i * (i - a);
+    b += 2.0;
+    d = an * d + b;
+    if (std::fabs(d) < tiny) d = tiny;
+    c = b + an / c;
+    if (std::fabs(c) < tiny) c = tiny;
+    d = 1.0 / d;
+    const double del = d * c;
+    h *= del;
+    if (std::fabs(del - 1.0) < 1e-16) break;
+  }
+  return std::exp(lpre) * h;
+}
+
+int rsaprng_battery_report(const rsaprng_battery* r, rsaprng_battery_result* out) {
+  if (!r || !out) return RSAPRNG_E_NULL;
+  std::memset(out, 0, sizeof(*out));
+  auto uniform = [&](int t, const uint32_t* cnt, size_t nb) {
+    double n = 0;
+    for (size_t i = 0; i < nb; ++i) n += cnt[i];
+    const double e = n / (double)nb;
+    double x = 0;
+    for (size_t i = 0; i < nb; ++i) x += ((double)cnt[i] - e) * ((double)cnt[i] - e);
+    out->samples[t] = (uint64_t)n;
+    out->chi2[t] = e > 0 ? x / e : 0.0;
+    out->dof[t] = (double)(nb - 1);
+    out->p[t] = e > 0 ? rsaprng_chi2_sf(out->chi2[t], out->dof[t]) : 0.0 / 0.0;
+  };
+  uniform(0, r->freq, 1u << 20);
+  uniform(1, r->serial2, 1u << 20);
+  uniform(2, r->serial3, 1000000);
+  uniform(3, r->serial4, 1u << 20);
+  uniform(4, r->serial5, 1u << 20);
+  uniform(5, r->serial6, 1000000);
+  {
+    // classes {1, 2}, 3, 4, 5 distinct values of five cards of 16 denominations:
+    // S(5, d) 16!/(16 - d)! / 16^5 with S(5, .) = 1, 15, 25, 10, 1
+    const double tot = 1048576.0;
+    const double pr[4] = {(16.0 + 3600.0) / tot, 84000.0 / tot, 436800.0 / tot, 524160.0 / tot};
+    const double o[4] = {(double)r->poker[1] + r->poker[2], (double)r->poker[3],
+                         (double)r->poker[4], (double)r->poker[5]};
+    const double n = o[0] + o[1] + o[2] + o[3];
+    double x = 0;
+    for (int i = 0; i < 4; ++i) x += (o[i] - n * pr[i]) * (o[i] - n * pr[i]) / (n * pr[i]);
+    out->samples[6] = (uint64_t)n;
+    out->chi2[6] = n > 0 ? x : 0.0;
+    out->dof[6] = 3.0;
+    out->p[6] = n > 0 ? rsaprng_chi2_sf(x, 3.0) : 0.0 / 0.0;
+  }
+  uniform(7, r->maxt, 1024);
+  return RSAPRNG_OK;
 }
 
 // ---- prepared batches (hipGraph) ---------------------------------------------

@@ -71,7 +71,8 @@ int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
-                   ChainState* state, void* stream, hipEvent_t* marks = nullptr);
+                   ChainState* state, void* stream, hipEvent_t* marks = nullptr,
+                   rsaprng_battery* battery = nullptr);
 // Parameter generation kernels (k_primes.hip).
 int launch_count_primes(uint64_t lo, uint64_t hi, int safe, unsigned long long* count_dev,
                         void* stream);

@@ -235,6 +235,7 @@ int launch_mont_gen(const KernelShape&, const LaunchArgs&, void*, int*);
 int launch_crt_gen(const KernelShape&, const LaunchArgs&, void*, int*);
 int launch_mont_con(const KernelShape&, const LaunchArgs&, void*, int*);
 int launch_crt_con(const KernelShape&, const LaunchArgs&, void*, int*);
+int launch_crt_bat(const KernelShape&, const LaunchArgs&, void*, int*);
 
 static int dispatch(const KernelShape& s, const LaunchArgs* a, void* stream, int* occ) {
   static const LaunchArgs dummy{};
@@ -243,6 +244,7 @@ static int dispatch(const KernelShape& s, const LaunchArgs* a, void* stream, int
   if (s.variant == kVariantCrt && s.mode == kModeGenerate) return launch_crt_gen(s, aa, stream, occ);
   if (s.variant == kVariantMont && s.mode == kModeConsume) return launch_mont_con(s, aa, stream, occ);
   if (s.variant == kVariantCrt && s.mode == kModeConsume) return launch_crt_con(s, aa, stream, occ);
+  if (s.variant == kVariantCrt && s.mode == kModeBattery) return launch_crt_bat(s, aa, stream, occ);
   return RSAPRNG_E_ARG;
 }
 
@@ -251,6 +253,21 @@ int launch_tiles(const KernelShape& s, const LaunchArgs& a, void* stream) {
 }
 
 int kernel_max_grid(const KernelShape& s, int* wg_per_cu) { return dispatch(s, nullptr, nullptr, wg_per_cu); }
+
+// Clears a battery record word by word (a kernel, so that graph capture
+// records no memset node).
+__global__ __launch_bounds__(256) void k_battery_zero(uint64_t* w, size_t nwords) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
+       i += (size_t)gridDim.x * blockDim.x)
+    w[i] = 0;
+}
+
+int launch_battery_zero(rsaprng_battery* rec, void* stream) {
+  const size_t nwords = sizeof(rsaprng_battery) / 8;
+  hipLaunchKernelGGL(k_battery_zero, dim3(2048), dim3(256), 0, (hipStream_t)stream,
+                     reinterpret_cast<uint64_t*>(rec), nwords);
+  return hip_rc(hipGetLastError());
+}
 
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream) {
   size_t words = nrec * (sizeof(rsaprng_stats) / 8);

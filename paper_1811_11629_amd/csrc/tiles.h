@@ -299,6 +299,97 @@ struct MsgExactWalk {
 // plus one word of padding against LDS bank conflicts.
 constexpr int kXRow = 9;
 
+// ---------------------------------------------------------------------------
+// Statistical battery (fused consumer): counts of one lane's V indices into
+// the device record.  Tuples live inside aligned blocks of 8 indices and the
+// maximum of 32 in aligned blocks of 32 (a block counts when all its indices
+// are requested), so the counts do not depend on the tiling.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ u32 bin_of(double r, double b, u32 nb) {
+  const u32 x = (u32)(r * b);
+  return x < nb ? x : nb - 1;
+}
+
+__device__ __forceinline__ void bat_add(u32* p) {
+  __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int V, int VAR, u32 E, class Msg>
+__device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain& C,
+                                                const rsaprng_params& P, Msg msg, u64 laneStart) {
+  static_assert(V % 8 == 0, "blocks of 8 indices");
+  rsaprng_battery* const B = a.battery;
+  const int lane = threadIdx.x & 63;
+  double rv[V];
+  u32 nout = 0;
+#pragma unroll
+  for (int i = 0; i < V; ++i) {
+    double cd;
+    (void)msg.template enc<VAR, E>(i, P, cd);
+    rv[i] = ratio(cd, P.nd, P.nrcp);
+    const u64 k = laneStart + i;
+    if (k >= C.k0 && k <= C.last) {
+      bat_add(&B->freq[bin_of(rv[i], 1048576.0, 1u << 20)]);
+      ++nout;
+    }
+  }
+  double mx = 0.0;
+  bool all = true;
+#pragma unroll
+  for (int b = 0; b < V / 8; ++b) {
+    const double* r = rv + 8 * b;
+    const u64 k8 = laneStart + 8 * b;
+    const bool full = k8 >= C.k0 && k8 <= C.last && C.last - k8 >= 7;
+    all = all && full;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) mx = r[i] > mx ? r[i] : mx;
+    if (!full) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t)
+      bat_add(&B->serial2[bin_of(r[2 * t], 1024.0, 1024) * 1024 + bin_of(r[2 * t + 1], 1024.0, 1024)]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t)
+      bat_add(&B->serial3[(bin_of(r[3 * t], 100.0, 100) * 100 + bin_of(r[3 * t + 1], 100.0, 100)) * 100 +
+                          bin_of(r[3 * t + 2], 100.0, 100)]);
+#pragma unroll
+    for (int t = 0; t < 2; ++t) {
+      u32 c = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) c = c * 32 + bin_of(r[4 * t + j], 32.0, 32);
+      bat_add(&B->serial4[c]);
+    }
+    u32 c5 = 0, c6 = 0, hand = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      c5 = c5 * 16 + bin_of(r[j], 16.0, 16);
+      hand |= 1u << bin_of(r[j], 16.0, 16);
+    }
+#pragma unroll
+    for (int j = 0; j < 6; ++j) c6 = c6 * 10 + bin_of(r[j], 10.0, 10);
+    bat_add(&B->serial5[c5]);
+    bat_add(&B->serial6[c6]);
+    bat_add(&B->poker[__builtin_popcount(hand)]);
+  }
+  // maximum of 32: the lanes holding one aligned block of 32 indices
+  constexpr int LPG = 32 / V;  // lanes per block of 32
+#pragma unroll
+  for (int m = 1; m < LPG; m <<= 1) {
+    const double o = __shfl_xor(mx, m, 64);
+    mx = o > mx ? o : mx;
+    all = (__shfl_xor((int)all, m, 64) != 0) && all;
+  }
+  if (all && (lane % LPG) == 0) {
+    double x = mx;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) x = x * x;  // M^32
+    bat_add(&B->maxt[bin_of(x, 1024.0, 1024)]);
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) nout += __shfl_xor(nout, m, 64);
+  if (lane == 0 && nout)
+    __hip_atomic_fetch_add(&B->outputs, (u64)nout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 template <int WG, int MODE>
 struct TileShared {
   u32 tile;
@@ -378,6 +469,8 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
         }
       }
     }
+  } else if constexpr (MODE == kModeBattery) {
+    battery_outputs<V, VAR, E>(a, C, P, msg, laneStart);
   } else {
     u64 c0 = 0, c1 = 0, c2 = 0, c3 = 0, lt = 0, cnt = 0;
 #pragma unroll

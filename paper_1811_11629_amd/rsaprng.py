@@ -86,6 +86,15 @@ _lock = threading.Lock()
 _lib = None
 
 _u64, _u32, _i32, _dbl, _sz, _vp = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_size_t, C.c_void_p
+BAT_TESTS = ("frequency", "serial2", "serial3", "serial4", "serial5", "serial6", "poker",
+             "max_of_32")
+BATTERY_BYTES = 16 + 4 * (4 * (1 << 20) + 2 * 1000000 + 8 + 1024)
+
+
+class rsaprng_battery_result(C.Structure):
+    _fields_ = [("chi2", _dbl * 8), ("dof", _dbl * 8), ("p", _dbl * 8), ("samples", _u64 * 8)]
+
+
 _SIGS = {
     "rsaprng_params_init": (_i32, [_u64, _u64, _u64, _u64, _u64, C.POINTER(rsaprng_params)]),
     "rsaprng_is_prime": (_i32, [_u64]),
@@ -120,6 +129,10 @@ _SIGS = {
     "rsaprng_server_create": (_i32, [_vp, C.POINTER(rsaprng_server_opts), C.POINTER(_vp)]),
     "rsaprng_server_submit": (_i32, [_vp, _u32, _u64, _u64, _u64]),
     "rsaprng_server_poll": (_i32, [_vp, C.POINTER(rsaprng_completion), _sz]),
+    "rsaprng_pool_battery": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp,
+                                     C.POINTER(rsaprng_config), _vp]),
+    "rsaprng_battery_report": (_i32, [_vp, C.POINTER(rsaprng_battery_result)]),
+    "rsaprng_chi2_sf": (_dbl, [_dbl, _dbl]),
     "rsaprng_prime_count": (_i32, [_u64, _u64, _i32, C.POINTER(_u64), _vp]),
     "rsaprng_next_primes": (_i32, [_vp, _u64, _i32, _vp, _i32, _vp, _vp]),
     "rsaprng_server_read": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _vp]),
@@ -145,6 +158,12 @@ def lib():
             if not os.path.exists(LIB_PATH):
                 raise ImportError("librsaprng.so not built: run __graft_entry__.build() "
                                   "or python paper_1811_11629_amd/build.py")
+            # torch ships its own HIP runtime; load it first so that the library
+            # binds to the same one (the process can then use both)
+            try:
+                import torch  # noqa: F401
+            except ImportError:
+                pass
             L = C.CDLL(LIB_PATH)
             for name, (res, args) in _SIGS.items():
                 f = getattr(L, name)
@@ -414,6 +433,40 @@ def server_simulate(k0, count, arrive_iter, arena_elems, iter_outputs=0, chunk_o
                                          nch)
     assert nch2 == nch
     return log[:nch]
+
+
+def battery_tensor(device="cuda"):
+    """A device buffer holding one rsaprng_battery record."""
+    import torch
+    return torch.empty(BATTERY_BYTES, dtype=torch.uint8, device=device)
+
+
+def rsaprng_pool_battery(pool: "Pool", reqs, rec, cfg=None, stream=None) -> None:
+    arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
+    _check(lib().rsaprng_pool_battery(pool.h, arr, len(arr), _ptr(rec),
+                                      C.byref(cfg) if cfg is not None else None, _stream(stream)),
+           "rsaprng_pool_battery")
+
+
+def battery_report(rec) -> dict:
+    """Chi-squared, dof, p-value and sample count per test from a battery record
+    (device tensor or host bytes)."""
+    import numpy as np
+    if hasattr(rec, "cpu"):
+        import torch
+        torch.cuda.synchronize()
+        host = rec.cpu().numpy().tobytes()
+    else:
+        host = bytes(rec)
+    buf = np.frombuffer(host, dtype=np.uint8).copy()
+    out = rsaprng_battery_result()
+    _check(lib().rsaprng_battery_report(buf.ctypes.data, C.byref(out)), "rsaprng_battery_report")
+    return {name: {"chi2": out.chi2[i], "dof": out.dof[i], "p": out.p[i],
+                   "samples": out.samples[i]} for i, name in enumerate(BAT_TESTS)}
+
+
+def rsaprng_chi2_sf(chi2: float, dof: float) -> float:
+    return lib().rsaprng_chi2_sf(chi2, dof)
 
 
 def rsaprng_prime_count(lo: int, hi: int, safe: bool = False, stream=None) -> int:

@@ -1,0 +1,78 @@
+"""The statistical battery on the host: the chi-squared tail against scipy,
+the report on constructed records, and the oracle's counts against a direct
+restatement of the grouping rules on a short ragged range."""
+import numpy as np
+import pytest
+import scipy.stats as st
+
+import inputs
+import oracle
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1811_11629_amd import rsaprng
+    rsaprng.lib()
+    return rsaprng
+
+
+def test_chi2_tail_matches_scipy(R):
+    for x, k in [(3.0, 3), (10.0, 3), (0.5, 1), (1000.0, 1023), (1100.0, 1023),
+                 (1048575.0, 1048575), (1050000.0, 1048575), (999000.0, 999999), (200.0, 50)]:
+        assert abs(R.rsaprng_chi2_sf(x, k) - st.chi2.sf(x, k)) < 1e-9 * max(1.0, st.chi2.sf(x, k))
+
+
+def test_report_on_constructed_records(R):
+    rec = np.zeros(R.BATTERY_BYTES, dtype=np.uint8)
+    fields = oracle.BATTERY_FIELDS
+    offs, off = {}, 0
+    for name, n, t in fields:
+        offs[name] = (off, n, t)
+        off += n * np.dtype(t).itemsize
+    view = {name: rec[o:o + n * np.dtype(t).itemsize].view(t) for name, (o, n, t) in offs.items()}
+    view["freq"][:] = 7                      # perfectly uniform: chi2 = 0, p = 1
+    view["maxt"][:512] = 3                   # half the bins empty
+    view["maxt"][512:] = 1
+    view["poker"][2:6] = [40, 1000, 5000, 6000]
+    out = R.battery_report(rec.tobytes())
+    assert out["frequency"]["chi2"] == 0.0 and out["frequency"]["p"] == 1.0
+    m = view["maxt"].astype(float)
+    e = m.mean()
+    assert abs(out["max_of_32"]["chi2"] - ((m - e) ** 2 / e).sum()) < 1e-9
+    pr = np.array([16 + 3600, 84000, 436800, 524160]) / 16.0 ** 5
+    o = np.array([40, 1000, 5000, 6000], dtype=float)
+    x = ((o - o.sum() * pr) ** 2 / (o.sum() * pr)).sum()
+    assert abs(out["poker"]["chi2"] - x) < 1e-9 and out["poker"]["dof"] == 3
+    assert abs(out["poker"]["p"] - st.chi2.sf(x, 3)) < 1e-12
+
+
+def _bin(r, b):
+    return min(int(r * b), b - 1)
+
+
+def test_oracle_battery_matches_definition():
+    inst = inputs.config1()
+    k0, count = (1 << 20) - 1000 + 3, 3000      # unaligned, crosses a block re-seeding
+    _, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, count)
+    got = oracle.battery([(inst, k0, count)])
+    freq = np.zeros(1 << 20, dtype=np.uint64)
+    for v in r:
+        freq[_bin(v, 1 << 20)] += 1
+    assert np.array_equal(got["freq"], freq) and int(got["outputs"][0]) == count
+    last = k0 + count - 1
+    s2, poker, maxt = {}, np.zeros(8, dtype=int), {}
+    for k8 in range((k0 + 7) // 8 * 8, last - 6, 8):
+        x = r[k8 - k0:k8 - k0 + 8]
+        for t in range(4):
+            c = _bin(x[2 * t], 1024) * 1024 + _bin(x[2 * t + 1], 1024)
+            s2[c] = s2.get(c, 0) + 1
+        poker[len({_bin(v, 16) for v in x[:5]})] += 1
+    for k32 in range((k0 + 31) // 32 * 32, last - 30, 32):
+        t = float(max(r[k32 - k0:k32 - k0 + 32]))
+        for _ in range(5):
+            t = t * t                           # M^32 by five squarings, as defined
+        c = _bin(t, 1024)
+        maxt[c] = maxt.get(c, 0) + 1
+    assert {int(i): int(v) for i, v in enumerate(got["serial2"]) if v} == s2
+    assert np.array_equal(got["poker"], poker)
+    assert {int(i): int(v) for i, v in enumerate(got["maxt"]) if v} == maxt

@@ -1,0 +1,65 @@
+"""GPU statistical battery (fused consumer) against the oracle, bit for bit, and
+the p-values of a larger run inside the paper's pass band."""
+import numpy as np
+import pytest
+
+import inputs
+import oracle
+from gpu_helpers import log
+
+pytestmark = pytest.mark.gpu
+
+B = 1 << 20
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_1811_11629_amd import rsaprng
+    rsaprng.lib()
+    return rsaprng
+
+
+def _decode(rec):
+    import torch
+    torch.cuda.synchronize()
+    return oracle.battery_decode(rec.cpu().numpy().tobytes())
+
+
+SHAPES = ((256, 8, 1, 0), (256, 8, 4, 0), (512, 8, 2, 0), (256, 8, 1, 1), (256, 16, 1, 1),
+          (256, 8, 2, 2), (512, 8, 2, 2))
+
+
+def test_battery_matches_oracle(R):
+    insts = inputs.config3(3)
+    cases = [inputs.Instance(i.p, i.q, e, i.m0) for i in insts for e in (3, 17)]
+    ranges = [(0, 5, 70000), (1, B - 4000 + 3, 9000), (2, (1 << 40) + 11, 33333), (3, 0, 4096),
+              (4, 7, 1), (5, (1 << 63) + 1, 50000), (0, 3 * B, 5000)]
+    ref = oracle.battery([(cases[j], k0, cnt) for j, k0, cnt in ranges])
+    pool = R.Pool.from_instances(cases)
+    rec = R.battery_tensor()
+    for shape in SHAPES:
+        log("battery", shape)
+        cfg = R.config(variant=2, lanes_per_tile=shape[0], per_lane=shape[1],
+                       chunks_per_wave=shape[2], prefix=shape[3])
+        R.rsaprng_pool_battery(pool, [(j, k0, cnt, 0) for j, k0, cnt in ranges], rec, cfg=cfg)
+        R.rsaprng_check_device_error()
+        got = _decode(rec)
+        for name in ref:
+            if name == "reserved":
+                continue
+            assert np.array_equal(got[name], ref[name]), (shape, name)
+
+
+def test_battery_pvalues_in_band(R):
+    insts = inputs.config3(8)
+    pool = R.Pool.from_instances(insts)
+    rec = R.battery_tensor()
+    reqs = [(j, 0, 1 << 24, 0) for j in range(len(insts))]   # 2^27 outputs
+    log("battery p-values", len(reqs))
+    R.rsaprng_pool_battery(pool, reqs, rec)
+    R.rsaprng_check_device_error()
+    rep = R.battery_report(rec)
+    for name, v in rep.items():
+        assert v["samples"] > 0, name
+        # the paper's criterion: no p-value below 1e-6 or above 1 - 1e-6
+        assert 1e-6 < v["p"] < 1 - 1e-6, (name, v)

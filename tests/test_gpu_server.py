@@ -144,3 +144,4 @@ def test_server_errors(R, pool_insts):
         assert_same(out[0][0], out[0][1], c_ref, r_ref, "top of range")
     finally:
         srv.close()
+
