@@ -87,7 +87,8 @@ typedef struct {
   double qinvp;      /* q^-1 mod p (Garner's constant, Number Theory section) */
   double kp, kq;     /* 2^32 mod p, 2^32 mod q */
   double nrcp;       /* RN(1 / RN(n)) */
-  uint64_t reserved;
+  uint32_t ep, eq;   /* exponents applied mod p and mod q: both e for an ordinary
+                        instance; see rsaprng_pool_create_dual (e is then 0) */
 } rsaprng_params;    /* 128 bytes; the device-side instance record */
 
 int rsaprng_params_init(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
@@ -162,6 +163,24 @@ typedef struct rsaprng_pool_s* rsaprng_pool_t;
 rsaprng_pool_t rsaprng_pool_create(size_t n, const uint64_t* p, const uint64_t* q,
                                    const uint64_t* e, const uint64_t* seed, const uint64_t* s0,
                                    size_t* err_index);
+/* Instances with different small exponents mod p and mod q (the footnote on
+ * CRT exponents): c_p = m_p^ep mod p, c_q = m_q^eq mod q, recombined by Garner,
+ * which is m^e mod n for the large exponent e with e = ep mod (p-1) and
+ * e = eq mod (q-1) (rsaprng_dual_exponent).  Requires gcd(ep, p-1) = 1,
+ * gcd(eq, q-1) = 1 and ep = eq mod gcd(p-1, q-1) (so that e exists; always
+ * true for safe primes and odd exponents).  Launches over such a pool use the
+ * CRT variant whatever the configuration asks. */
+rsaprng_pool_t rsaprng_pool_create_dual(size_t n, const uint64_t* p, const uint64_t* q,
+                                        const uint64_t* ep, const uint64_t* eq,
+                                        const uint64_t* seed, const uint64_t* s0,
+                                        size_t* err_index);
+/* The record of one dual-exponent instance, validated as for the pool (host
+ * only; *out written on success). */
+int rsaprng_params_init_dual(uint64_t p, uint64_t q, uint64_t ep, uint64_t eq, uint64_t m0,
+                             uint64_t s0, rsaprng_params* out);
+/* The combined exponent: the smallest e >= 1 with e = ep mod (p-1) and
+ * e = eq mod (q-1).  Host only; RSAPRNG_E_BAD_EXPONENT if there is none. */
+int rsaprng_dual_exponent(uint64_t p, uint64_t q, uint64_t ep, uint64_t eq, uint64_t* e);
 void rsaprng_pool_destroy(rsaprng_pool_t pool);
 size_t rsaprng_pool_size(rsaprng_pool_t pool);
 

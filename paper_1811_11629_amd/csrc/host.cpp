@@ -138,7 +138,51 @@ int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng
   P.kp = (double)((1ull << 32) % p);
   P.kq = (double)((1ull << 32) % q);
   P.nrcp = 1.0 / P.nd;
+  P.ep = P.eq = (uint32_t)e;
   *out = P;
+  return RSAPRNG_OK;
+}
+
+// Combined exponent of a dual-exponent instance (CRT on the exponents):
+// e = ep + (p - 1) t with (p - 1) t = eq - ep mod (q - 1).
+int h_dual_exponent(u64h p, u64h q, u64h ep, u64h eq, u64h* e_out) {
+  const u64h a = p - 1, b = q - 1, g = h_gcd(a, b);
+  if (ep % g != eq % g) return RSAPRNG_E_BAD_EXPONENT;
+  const u64h bg = b / g, ag = (a / g) % bg;
+  // (eq - ep)/g mod bg, with the difference taken mod b first
+  const u64h diff = (u64h)((((u128)eq + b) - (ep % b)) % b) / g % bg;
+  u64h t = 0;
+  if (bg > 1) {
+    // inverse of ag mod bg by the extended Euclidean algorithm
+    long long r0 = (long long)bg, r1 = (long long)ag, s0 = 0, s1 = 1;
+    while (r1) {
+      const long long qq = r0 / r1, r2 = r0 - qq * r1, s2 = s0 - qq * s1;
+      r0 = r1; r1 = r2; s0 = s1; s1 = s2;
+    }
+    if (r0 != 1) return RSAPRNG_E_BAD_EXPONENT;
+    const u64h inv = (u64h)((s0 % (long long)bg + (long long)bg) % (long long)bg);
+    t = (u64h)((u128)diff * inv % bg);
+  }
+  const u64h lcm = a / g * b;
+  u64h e = (u64h)(((u128)ep + (u128)a * t) % lcm);
+  if (e == 0) e = lcm;
+  *e_out = e;
+  return RSAPRNG_OK;
+}
+
+int h_params_dual(u64h p, u64h q, u64h ep, u64h eq, u64h m0, u64h s0, rsaprng_params* out) {
+  // range, primality and seed checks as for an ordinary instance with e = 1
+  int rc = h_params(p, q, 1, m0, s0, true, out);
+  if (rc) return rc;
+  if (ep == 0 || eq == 0 || ep >= (1ull << 32) || eq >= (1ull << 32) || h_gcd(ep, p - 1) != 1 ||
+      h_gcd(eq, q - 1) != 1)
+    return RSAPRNG_E_BAD_EXPONENT;
+  u64h e;
+  if ((rc = h_dual_exponent(p, q, ep, eq, &e))) return rc;
+  out->e = 0;  // no single small exponent: the kernels take ep and eq
+  out->ce = 0;
+  out->ep = (uint32_t)ep;
+  out->eq = (uint32_t)eq;
   return RSAPRNG_OK;
 }
 
@@ -369,6 +413,7 @@ u64h tile_size(const rsaprng_config& c) {
 // Relative cost of one output for exponent e (multiplications of the ladder),
 // used for longest-first ordering.
 static u64h e_cost(uint32_t e) {
+  if (e == 0) return 4 + 64;  // dual-exponent instance: two ladders of up to 32 bits
   int bits = 31 - __builtin_clz(e);
   return 4 + bits + __builtin_popcount(e);
 }
@@ -586,6 +631,7 @@ struct rsaprng_pool_s {
   std::vector<rsaprng_params> host;
   rsaprng_params* dev = nullptr;
   int device = 0;
+  bool dual = false;  // holds dual-exponent instances: CRT variant only
 };
 
 extern "C" {
@@ -774,13 +820,11 @@ int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u
 
 // ---- pools ----------------------------------------------------------------
 
-rsaprng_pool_t rsaprng_pool_create(size_t n, const uint64_t* p, const uint64_t* q,
-                                   const uint64_t* e, const uint64_t* seed, const uint64_t* s0,
-                                   size_t* err_index) {
-  if (n == 0 || !p || !q || !e || !seed) {
-    set_last_error(RSAPRNG_E_NULL);
-    return nullptr;
-  }
+}  // extern "C"
+
+// Builds a pool from per-instance records made by `make(i, &params)`.
+template <class Make>
+static rsaprng_pool_t pool_build(size_t n, size_t* err_index, bool dual, Make make) {
   Device* d = nullptr;
   int rc = device_get(&d);
   if (rc) {
@@ -789,10 +833,9 @@ rsaprng_pool_t rsaprng_pool_create(size_t n, const uint64_t* p, const uint64_t* 
   }
   auto pool = std::make_unique<rsaprng_pool_s>();
   pool->host.resize(n);
+  pool->dual = dual;
   for (size_t i = 0; i < n; ++i) {
-    u64h nn = p[i] * q[i];
-    u64h m0 = (p[i] < (1ull << 32) && q[i] < (1ull << 32) && nn) ? seed[i] % nn : 0;
-    rc = h_params(p[i], q[i], e[i], m0, s0 ? s0[i] : 1, true, &pool->host[i]);
+    rc = make(i, &pool->host[i]);
     if (rc) {
       if (err_index) *err_index = i;
       set_last_error(rc);
@@ -814,6 +857,57 @@ rsaprng_pool_t rsaprng_pool_create(size_t n, const uint64_t* p, const uint64_t* 
   return pool.release();
 }
 
+static u64h seed_mod_n(u64h p, u64h q, u64h seed) {
+  const u64h nn = p * q;
+  return (p < (1ull << 32) && q < (1ull << 32) && nn) ? seed % nn : 0;
+}
+
+extern "C" {
+
+rsaprng_pool_t rsaprng_pool_create(size_t n, const uint64_t* p, const uint64_t* q,
+                                   const uint64_t* e, const uint64_t* seed, const uint64_t* s0,
+                                   size_t* err_index) {
+  if (n == 0 || !p || !q || !e || !seed) {
+    set_last_error(RSAPRNG_E_NULL);
+    return nullptr;
+  }
+  return pool_build(n, err_index, false, [&](size_t i, rsaprng_params* out) {
+    return h_params(p[i], q[i], e[i], seed_mod_n(p[i], q[i], seed[i]), s0 ? s0[i] : 1, true, out);
+  });
+}
+
+rsaprng_pool_t rsaprng_pool_create_dual(size_t n, const uint64_t* p, const uint64_t* q,
+                                        const uint64_t* ep, const uint64_t* eq,
+                                        const uint64_t* seed, const uint64_t* s0,
+                                        size_t* err_index) {
+  if (n == 0 || !p || !q || !ep || !eq || !seed) {
+    set_last_error(RSAPRNG_E_NULL);
+    return nullptr;
+  }
+  return pool_build(n, err_index, true, [&](size_t i, rsaprng_params* out) {
+    return h_params_dual(p[i], q[i], ep[i], eq[i], seed_mod_n(p[i], q[i], seed[i]),
+                         s0 ? s0[i] : 1, out);
+  });
+}
+
+int rsaprng_params_init_dual(uint64_t p, uint64_t q, uint64_t ep, uint64_t eq, uint64_t m0,
+                             uint64_t s0, rsaprng_params* out) {
+  if (!out) return RSAPRNG_E_NULL;
+  rsaprng_params P;
+  const int rc = h_params_dual(p, q, ep, eq, m0, s0, &P);
+  if (!rc) *out = P;
+  return rc;
+}
+
+int rsaprng_dual_exponent(uint64_t p, uint64_t q, uint64_t ep, uint64_t eq, uint64_t* e) {
+  if (!e) return RSAPRNG_E_NULL;
+  if (p < 3 || q < 3 || ep == 0 || eq == 0) return RSAPRNG_E_ARG;
+  u64h v = 0;
+  const int rc = h_dual_exponent(p, q, ep, eq, &v);
+  if (!rc) *e = v;
+  return rc;
+}
+
 void rsaprng_pool_destroy(rsaprng_pool_t pool) {
   if (!pool) return;
   if (pool->dev) (void)hipFree(pool->dev);
@@ -829,6 +923,15 @@ namespace rsaprng {
 const rsaprng_params* pool_dev(rsaprng_pool_t pool) { return pool->dev; }
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i) { return pool->host[i]; }
 int pool_device(rsaprng_pool_t pool) { return pool->device; }
+
+rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg) {
+  rsaprng_config c = resolve_config(cfg);
+  if (pool->dual && c.variant != kVariantCrt) {
+    c.variant = kVariantCrt;
+    c = resolve_config(&c);
+  }
+  return c;
+}
 
 int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
               const rsaprng_config& c, std::vector<Chain>& plan, u64h* ntiles) {
@@ -864,7 +967,7 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   int rc;
   if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
   rsaprng_config c = resolve_config(cfg);
-  if (mode == kModeBattery && c.variant != kVariantCrt) {
+  if ((mode == kModeBattery || pool->dual) && c.variant != kVariantCrt) {
     rsaprng_config c2 = c;
     c2.variant = kVariantCrt;
     c = resolve_config(&c2);
@@ -1025,7 +1128,7 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   Device* d;
   int rc;
   if ((rc = device_get(&d))) return rc;
-  rsaprng_config c = resolve_config(cfg);
+  rsaprng_config c = config_for_pool(pool, cfg);
   std::vector<Chain> plan;
   u64h ntiles;
   if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;

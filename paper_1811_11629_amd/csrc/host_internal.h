@@ -82,5 +82,7 @@ int launch_next_primes(const uint64_t* x, uint64_t n, int safe, const uint32_t* 
 const rsaprng_params* pool_dev(rsaprng_pool_t pool);
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i);
 int pool_device(rsaprng_pool_t pool);
+// The configuration a launch over `pool` uses (CRT for dual-exponent pools).
+rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg);
 
 }  // namespace rsaprng

@@ -102,7 +102,7 @@ rsaprng_server_s::~rsaprng_server_s() {
 
 int rsaprng_server_s::init() {
   t0 = Clock::now();
-  cfg = resolve_config(&opts.cfg);
+  cfg = config_for_pool(pool, &opts.cfg);
   if (!opts.iter_outputs) opts.iter_outputs = 1ull << 26;
   if (!opts.chunk_outputs) opts.chunk_outputs = 1ull << 22;
   if (!opts.max_queue) opts.max_queue = 1u << 20;

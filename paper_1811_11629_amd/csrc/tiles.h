@@ -159,8 +159,10 @@ __device__ __forceinline__ u64 encrypt_res(double mp, double mq, const rsaprng_p
     cp = fp_pow<E>(mp, P.pd, P.pinv);
     cq = fp_pow<E>(mq, P.qd, P.qinv);
   } else {
-    cp = fp_pow_rt(mp, P.pd, P.pinv, P.e);
-    cq = fp_pow_rt(mq, P.qd, P.qinv, P.e);
+    // generic ladders with the exponents of each prime (equal to e unless the
+    // instance has different exponents mod p and mod q)
+    cp = fp_pow_rt(mp, P.pd, P.pinv, P.ep);
+    cq = fp_pow_rt(mq, P.qd, P.qinv, P.eq);
   }
   return garner(cp, cq, P.pd, P.qd, P.pinv, P.qinv, P.qinvp, P.q, cd);
 }

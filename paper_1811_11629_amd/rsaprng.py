@@ -46,7 +46,7 @@ class rsaprng_params(C.Structure):
                 ("nd", C.c_double), ("pd", C.c_double), ("qd", C.c_double),
                 ("pinv", C.c_double), ("qinv", C.c_double), ("qinvp", C.c_double),
                 ("kp", C.c_double), ("kq", C.c_double), ("nrcp", C.c_double),
-                ("reserved", C.c_uint64)]
+                ("ep", C.c_uint32), ("eq", C.c_uint32)]
 
 
 class rsaprng_req(C.Structure):
@@ -111,6 +111,9 @@ _SIGS = {
     "rsaprng_consume": (_i32, [_vp, _u64, _u64, _vp, _vp]),
     "rsaprng_pool_create": (_vp, [_sz, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
                                   C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_sz)]),
+    "rsaprng_pool_create_dual": (_vp, [_sz] + [_vp] * 6 + [C.POINTER(_sz)]),
+    "rsaprng_dual_exponent": (_i32, [_u64, _u64, _u64, _u64, C.POINTER(_u64)]),
+    "rsaprng_params_init_dual": (_i32, [_u64] * 6 + [C.POINTER(rsaprng_params)]),
     "rsaprng_pool_destroy": (None, [_vp]),
     "rsaprng_pool_size": (_sz, [_vp]),
     "rsaprng_pool_generate": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp, _vp,
@@ -313,6 +316,22 @@ class Pool:
         self.size = n
 
     @classmethod
+    def dual(cls, p, q, ep, eq, seed, s0=None) -> "Pool":
+        """A pool of instances with exponents ep mod p and eq mod q."""
+        self = cls.__new__(cls)
+        n = len(p)
+        err = C.c_size_t(0)
+        h = lib().rsaprng_pool_create_dual(n, _u64arr(p), _u64arr(q), _u64arr(ep), _u64arr(eq),
+                                           _u64arr(seed), _u64arr(s0) if s0 is not None else None,
+                                           C.byref(err))
+        if not h:
+            raise RsaprngError(lib().rsaprng_last_error(),
+                               "rsaprng_pool_create_dual[%d]" % err.value)
+        self.h = h
+        self.size = n
+        return self
+
+    @classmethod
     def from_instances(cls, insts) -> "Pool":
         return cls([i.p for i in insts], [i.q for i in insts], [i.e for i in insts],
                    [i.m0 for i in insts], [i.s0 for i in insts])
@@ -467,6 +486,19 @@ def battery_report(rec) -> dict:
 
 def rsaprng_chi2_sf(chi2: float, dof: float) -> float:
     return lib().rsaprng_chi2_sf(chi2, dof)
+
+
+def rsaprng_params_init_dual(p, q, ep, eq, m0, s0=1) -> rsaprng_params:
+    out = rsaprng_params()
+    _check(lib().rsaprng_params_init_dual(p, q, ep, eq, m0, s0, C.byref(out)),
+           "rsaprng_params_init_dual")
+    return out
+
+
+def rsaprng_dual_exponent(p: int, q: int, ep: int, eq: int) -> int:
+    out = C.c_uint64(0)
+    _check(lib().rsaprng_dual_exponent(p, q, ep, eq, C.byref(out)), "rsaprng_dual_exponent")
+    return out.value
 
 
 def rsaprng_prime_count(lo: int, hi: int, safe: bool = False, stream=None) -> int:
