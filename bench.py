@@ -38,17 +38,18 @@ def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
 
-DEVICE_SOURCES = ("common.h", "devmath.h", "tiles.h")
+# The translation units of the generate-mode tile kernels and everything they include.
+DEVICE_SOURCES = ("k_crt_gen.hip", "k_mont_gen.hip", "common.h", "devmath.h", "tiles.h",
+                  "../../include/rsaprng.h")
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device-code sources (the kernels' text, not the host library)."""
+    """Hash of the sources the generate-mode tile kernels are compiled from."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1811_11629_amd", "csrc")
-    for f in sorted(os.listdir(d)):
-        if f.endswith(".hip") or f in DEVICE_SOURCES:
-            with open(os.path.join(d, f), "rb") as fh:
-                h.update(f.encode() + fh.read())
+    for f in DEVICE_SOURCES:
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(os.path.basename(f).encode() + fh.read())
     return h.hexdigest()[:16]
 
 
