@@ -123,6 +123,29 @@ int rsaprng_get_params(rsaprng_t h, rsaprng_params* out);
 int rsaprng_generate(rsaprng_t h, uint64_t k0, uint64_t count, uint64_t* out_u64,
                      double* out_f64, void* stream);
 
+/* Vector mode (Parallelization section, eq. vectorize and the stream splitting
+ * after it): the instance split into M_v = mv substreams advanced together.
+ * Substream g (0 <= g < mv) is the instance's sequence with the skip seed
+ * s0 a^(g J) mod Q, J = floor((Q-1)/mv), and the same message seed m0 (the
+ * paper leaves the message starts open; this is the library's reading).  The
+ * t-th vector call (t = 1, 2, ...) returns element g = the output of substream
+ * g after t updates, i.e. its index k = t (so the first call never returns the
+ * seed itself).  Flattened, f = (t - 1) mv + g, and this writes
+ * out_u64[j] = c and out_f64[j] = r of f = f0 + j for j < count; either
+ * pointer may be NULL.  Any f0 is allowed: a range starting inside a 2^20
+ * block walks every substream from the block start (mv (t mod 2^20) skip
+ * steps of lead-in).  variant: 0 auto (CRT), 1 Montgomery-64, 2 CRT, as in
+ * rsaprng_config; the outputs do not depend on it.
+ * Limits: 1 <= mv <= RSAPRNG_VECTOR_MAX_MV, count <= RSAPRNG_VECTOR_MAX_COUNT,
+ * f0 + count <= RSAPRNG_VECTOR_MAX_END (else RSAPRNG_E_ARG / RSAPRNG_E_RANGE).
+ * Enqueued on `stream`; grows the stream's scratch to at most 8 (2^26 + 4 ng)
+ * bytes, ng = min(mv, count) (about 16 MB when mv << 2^21). */
+#define RSAPRNG_VECTOR_MAX_MV (1ULL << 24)
+#define RSAPRNG_VECTOR_MAX_COUNT (1ULL << 56)
+#define RSAPRNG_VECTOR_MAX_END (1ULL << 62)
+int rsaprng_generate_vector(rsaprng_t h, uint64_t mv, uint64_t f0, uint64_t count,
+                            uint64_t* out_u64, double* out_f64, int variant, void* stream);
+
 /* Many instances in one launch: request i writes c_{k0+j}, r_{k0+j} of reqs[i].h
  * to out_u64[out_off + j], out_f64[out_off + j].  reqs is a host array. */
 typedef struct {
@@ -326,7 +349,7 @@ void rsaprng_server_destroy(rsaprng_server_t s);
  * ------------------------------------------------------------------------ */
 #define RSAPRNG_BAT_TESTS 8   /* frequency, serial D = 2..6, poker, max-of-32 */
 typedef struct {
-  uint64_t outputs;           /* number of r_k consumed */
+  uint64_t outputs;           /* number of r_k consumed: the sum of the requests' counts */
   uint64_t reserved;
   uint32_t freq[1 << 20];     /* bin floor(2^20 r) */
   uint32_t serial2[1 << 20];  /* 1024 bins per coordinate */

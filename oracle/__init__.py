@@ -125,6 +125,40 @@ def generate(p, q, e, m0, s0, k0, count, want_c=True, want_r=True):
     return c, r
 
 
+def substream_seed(s0, mv, g):
+    """Skip seed of substream g of mv (Parallelization section, stream splitting):
+    s0 a^(g floor((Q-1)/mv)) mod Q."""
+    return mulmod(s0, powmod(A, g * ((Q - 1) // mv), Q), Q)
+
+
+def generate_vector(p, q, e, m0, s0, mv, f0, count, want_c=True, want_r=True):
+    """Vector mode (Parallelization section, eq. vectorize): mv substreams advanced
+    together, substream g being the sequence with skip seed substream_seed(s0, mv, g)
+    and message seed m0.  The t-th vector call (t >= 1) returns substream g's output
+    after t updates, i.e. its index t; flattened, f = (t - 1) mv + g.  Returns
+    outputs f0 .. f0 + count - 1."""
+    c = np.empty(count, dtype=np.uint64) if want_c else None
+    r = np.empty(count, dtype=np.float64) if want_r else None
+    if count == 0:
+        return c, r
+    t_lo, g_lo = f0 // mv + 1, f0 % mv
+    t_hi, g_hi = (f0 + count - 1) // mv + 1, (f0 + count - 1) % mv
+    for j in range(min(count, mv)):
+        g = (g_lo + j) % mv
+        first = t_lo if g >= g_lo else t_lo + 1
+        last = t_hi if g <= g_hi else t_hi - 1
+        if first > last:
+            continue
+        n = last - first + 1
+        cg, rg = generate(p, q, e, m0, substream_seed(s0, mv, g), first, n, want_c, want_r)
+        start = (first - 1) * mv + g - f0
+        if want_c:
+            c[start:start + (n - 1) * mv + 1:mv] = cg
+        if want_r:
+            r[start:start + (n - 1) * mv + 1:mv] = rg
+    return c, r
+
+
 def messages(p, q, m0, s0, k0, count):
     m = np.empty(count, dtype=np.uint64)
     rc = lib().oracle_messages(p, q, m0, s0, k0, count, _p64(m))

@@ -110,6 +110,34 @@ struct LaunchArgs {
   uint64_t gc;             // a (a - 1)^-1 mod Q: block seed G_b = s0 gc (a^{bB} - 1)
 };
 
+// Vector mode (k_vector.hip): one launch over vector calls [t_lo, t_hi] of one
+// instance.  Lane j stands for substream g = (g_lo + j) mod mv; segment i of
+// the domain holds indices [(sig_a + i) W, (sig_a + i + 1) W), W = 2^w with
+// 6 <= w <= 19; groups of 2^glog2 consecutive segments lie inside one block.  The output of (k, g)
+// goes to out[(k - t_lo) mv + g - g_lo] when that lies in [0, count).
+struct VecArgs {
+  rsaprng_params P;
+  const uint64_t* pow2;    // a^(2^i) mod Q
+  uint64_t gc;             // a (a - 1)^-1 mod Q
+  uint64_t mv;             // M_v
+  uint64_t J;              // floor((Q - 1) / M_v)
+  uint64_t g_lo;           // substream of the first output
+  uint64_t t_lo, t_hi;     // first and last vector call (substream index k)
+  uint64_t count;          // outputs of the launch
+  uint64_t sig_a;          // first segment of the domain (a block start)
+  uint32_t ng;             // substreams in play
+  uint32_t nseg, ngrp, nblk;
+  uint32_t osig, noseg;    // segments holding outputs: [osig, osig + noseg)
+  uint32_t w, glog2;
+  uint64_t* va;            // [ng]        s0 a^(g J) mod Q
+  uint64_t* vb;            // [nseg]      a^((sig_a + i) W) mod Q
+  uint64_t* vagg;          // [nseg][ng]  segment sums, then in-group prefixes
+  uint64_t* vgrp;          // [ngrp][ng]  group totals, then message before each group
+  uint64_t* out_c;
+  double* out_r;
+};
+int launch_vector(const VecArgs& args, int variant, void* stream);
+
 // Host-callable launchers (kernels.hip).
 struct KernelShape {
   int variant;   // kVariantMont or kVariantCrt
@@ -125,7 +153,7 @@ int launch_chain_setup(const LaunchArgs& args, void* stream);
 int launch_sums(const LaunchArgs& args, void* stream);
 int launch_scan(const LaunchArgs& args, void* stream);
 int launch_tiles(const KernelShape& shape, const LaunchArgs& args, void* stream);
-int launch_battery_zero(rsaprng_battery* rec, void* stream);
+int launch_battery_zero(rsaprng_battery* rec, uint64_t outputs, void* stream);
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_stats_finalize(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t* m, uint64_t* c,

@@ -273,6 +273,7 @@ Scratch::~Scratch() {
   if (tiles) (void)hipFree(tiles);
   if (cstart) (void)hipFree(cstart);
   if (ctl) (void)hipFree(ctl);
+  if (vec) (void)hipFree(vec);
 }
 
 int Scratch::init() {
@@ -310,6 +311,18 @@ int Scratch::ensure_tiles(u64h ntiles, u64h nchunks, u64h nchains, void* stream)
     if (hipMalloc(&cstart, want * sizeof(ChainStart)) != hipSuccess) return RSAPRNG_E_OOM;
     chains_cap = want;
   }
+  return RSAPRNG_OK;
+}
+
+int Scratch::ensure_vec(u64h words, void* stream) {
+  if (words <= vec_cap) return RSAPRNG_OK;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSAPRNG_E_HIP;
+  const u64h want = std::max<u64h>(std::max<u64h>(words, vec_cap * 2), 1 << 16);
+  if (vec) (void)hipFree(vec);
+  vec = nullptr;
+  vec_cap = 0;
+  if (hipMalloc(&vec, want * 8) != hipSuccess) return RSAPRNG_E_OOM;
+  vec_cap = want;
   return RSAPRNG_OK;
 }
 
@@ -552,7 +565,6 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   };
   if ((rc = mark(0))) return rc;
   if (mode == kModeConsume && nstats && (rc = launch_stats_zero(stats, nstats, stream))) return rc;
-  if (mode == kModeBattery && (rc = launch_battery_zero(battery, stream))) return rc;
   if (ntiles == 0) {
     if (mode == kModeConsume && nstats && (rc = launch_stats_finalize(stats, nstats, stream)))
       return rc;
@@ -773,6 +785,77 @@ int rsaprng_consume(rsaprng_t h, uint64_t k0, uint64_t count, rsaprng_stats* out
   return rc ? rc : rc2;
 }
 
+int rsaprng_generate_vector(rsaprng_t h, uint64_t mv, uint64_t f0, uint64_t count,
+                            uint64_t* out_u64, double* out_f64, int variant, void* stream) {
+  if (!h) return RSAPRNG_E_NULL;
+  if (misaligned(out_u64) || misaligned(out_f64)) return RSAPRNG_E_ALIGN;
+  if (mv == 0 || mv > RSAPRNG_VECTOR_MAX_MV) return RSAPRNG_E_ARG;
+  if (variant != kVariantAuto && variant != kVariantMont && variant != kVariantCrt)
+    return RSAPRNG_E_ARG;
+  if (count > RSAPRNG_VECTOR_MAX_COUNT || f0 > RSAPRNG_VECTOR_MAX_END - count)
+    return RSAPRNG_E_RANGE;
+  if (count == 0 || (!out_u64 && !out_f64)) return RSAPRNG_OK;
+  Device* d;
+  Scratch* sc;
+  int rc;
+  if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
+  const int var = variant == kVariantMont ? kVariantMont : kVariantCrt;
+  const u64h f_end = f0 + count;
+  const u64h t_last = (f_end - 1) / mv + 1;   // last vector call of the whole range
+  const u64h J = (kQh - 1) / mv;
+  // Pieces of whole blocks of vector calls, so that the tables of one launch
+  // stay below about 2^25 words; each starts its scan at a block start.
+  constexpr u64h kLanes = 1ull << 21;   // lanes aimed at per launch
+  constexpr u64h kWords = 1ull << 25;   // segment-table budget per launch
+  u64h f = f0;
+  while (f < f_end) {
+    const u64h ng = std::min<u64h>(mv, f_end - f);
+    const u64h t_lo = f / mv + 1;
+    const u64h blk_a = t_lo >> kBlockLog2;
+    const u64h nb = std::max<u64h>(1, kWords / (2 * ng));  // >= 2 segments per block
+    const u64h t_cap = ((blk_a + nb) << kBlockLog2) - 1;   // last call of the piece's blocks
+    const u64h f_stop = t_cap >= t_last ? f_end : t_cap * mv;  // calls <= t_cap: f < t_cap mv
+    const u64h t_hi = (f_stop - 1) / mv + 1;
+    const u64h span = t_hi - (blk_a << kBlockLog2) + 1;      // indices of the domain
+    uint32_t w = 6;
+    while (w < kBlockLog2 - 1 && ((ng * span) >> w) > kLanes) ++w;
+    VecArgs a;
+    a.P = h->prm;
+    a.pow2 = d->pow2;
+    a.gc = d->gc;
+    a.mv = mv;
+    a.J = J;
+    a.g_lo = f % mv;
+    a.t_lo = t_lo;
+    a.t_hi = t_hi;
+    a.count = f_stop - f;
+    a.sig_a = (blk_a << kBlockLog2) >> w;
+    const u64h sig_b = t_hi >> w;
+    const u64h nseg = sig_b - a.sig_a + 1;
+    a.w = w;
+    a.glog2 = std::min<uint32_t>(6, kBlockLog2 - w);
+    const u64h ngrp = (nseg + (1ull << a.glog2) - 1) >> a.glog2;
+    a.ng = (uint32_t)ng;
+    a.nseg = (uint32_t)nseg;
+    a.ngrp = (uint32_t)ngrp;
+    a.nblk = (uint32_t)((t_hi >> kBlockLog2) - blk_a + 1);
+    a.osig = (uint32_t)((t_lo >> w) - a.sig_a);
+    a.noseg = (uint32_t)(sig_b - (t_lo >> w) + 1);
+    if (nseg * ng >= (1ull << 31)) return RSAPRNG_E_RANGE;  // not reached with the budget above
+    const u64h words = ng + nseg + nseg * ng + ngrp * ng;
+    if ((rc = sc->ensure_vec(words, stream))) return rc;
+    a.va = sc->vec;
+    a.vb = a.va + ng;
+    a.vagg = a.vb + nseg;
+    a.vgrp = a.vagg + nseg * ng;
+    a.out_c = out_u64 ? out_u64 + (f - f0) : nullptr;
+    a.out_r = out_f64 ? out_f64 + (f - f0) : nullptr;
+    if ((rc = launch_vector(a, var, stream))) return rc;
+    f = f_stop;
+  }
+  return RSAPRNG_OK;
+}
+
 int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u64, double* out_f64,
                            void* stream) {
   if (nreq && !reqs) return RSAPRNG_E_NULL;
@@ -976,6 +1059,11 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   u64h ntiles;
   if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
   const size_t nst = mode == kModeConsume ? stats_records(reqs, nreq) : 0;
+  if (mode == kModeBattery) {
+    u64h total = 0;
+    for (size_t i = 0; i < nreq; ++i) total += reqs[i].count;
+    if ((rc = launch_battery_zero(battery, total, stream))) return rc;
+  }
   if (plan.empty())
     return enqueue_launch(d, sc, c, mode, pool->dev, nullptr, 0, 0, out_u64, out_f64, stats, nst,
                           nullptr, stream, nullptr, battery);

@@ -44,7 +44,10 @@ struct Scratch {
   int next_slot = 0;
   ~Scratch();
   int init();
+  uint64_t* vec = nullptr;       // vector mode: substream and segment tables
+  u64h vec_cap = 0;              // in 64-bit words
   int ensure_tiles(u64h ntiles, u64h nchunks, u64h nchains, void* stream);
+  int ensure_vec(u64h words, void* stream);
   int upload(const void* data, size_t bytes, void* stream, void** dev_out, int* slot_out);
   int mark(int slot, void* stream);
 };

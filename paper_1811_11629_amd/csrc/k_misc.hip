@@ -255,17 +255,17 @@ int launch_tiles(const KernelShape& s, const LaunchArgs& a, void* stream) {
 int kernel_max_grid(const KernelShape& s, int* wg_per_cu) { return dispatch(s, nullptr, nullptr, wg_per_cu); }
 
 // Clears a battery record word by word (a kernel, so that graph capture
-// records no memset node).
-__global__ __launch_bounds__(256) void k_battery_zero(uint64_t* w, size_t nwords) {
+// records no memset node) and sets its output count (the first word).
+__global__ __launch_bounds__(256) void k_battery_zero(uint64_t* w, size_t nwords, uint64_t outputs) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < nwords;
        i += (size_t)gridDim.x * blockDim.x)
-    w[i] = 0;
+    w[i] = i == 0 ? outputs : 0;
 }
 
-int launch_battery_zero(rsaprng_battery* rec, void* stream) {
+int launch_battery_zero(rsaprng_battery* rec, uint64_t outputs, void* stream) {
   const size_t nwords = sizeof(rsaprng_battery) / 8;
   hipLaunchKernelGGL(k_battery_zero, dim3(2048), dim3(256), 0, (hipStream_t)stream,
-                     reinterpret_cast<uint64_t*>(rec), nwords);
+                     reinterpret_cast<uint64_t*>(rec), nwords, outputs);
   return hip_rc(hipGetLastError());
 }
 

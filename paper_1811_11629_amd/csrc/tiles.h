@@ -323,17 +323,13 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain
   rsaprng_battery* const B = a.battery;
   const int lane = threadIdx.x & 63;
   double rv[V];
-  u32 nout = 0;
 #pragma unroll
   for (int i = 0; i < V; ++i) {
     double cd;
     (void)msg.template enc<VAR, E>(i, P, cd);
     rv[i] = ratio(cd, P.nd, P.nrcp);
     const u64 k = laneStart + i;
-    if (k >= C.k0 && k <= C.last) {
-      bat_add(&B->freq[bin_of(rv[i], 1048576.0, 1u << 20)]);
-      ++nout;
-    }
+    if (k >= C.k0 && k <= C.last) bat_add(&B->freq[bin_of(rv[i], 1048576.0, 1u << 20)]);
   }
   double mx = 0.0;
   bool all = true;
@@ -345,6 +341,18 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain
     all = all && full;
 #pragma unroll
     for (int i = 0; i < 8; ++i) mx = r[i] > mx ? r[i] : mx;
+    // poker: the five classes counted per wave (one atomic per class), since
+    // most hands fall into two of them
+    u32 hand = 0;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) hand |= 1u << bin_of(r[j], 16.0, 16);
+    const u32 distinct = __builtin_popcount(hand);
+#pragma unroll
+    for (u32 d = 1; d <= 5; ++d) {
+      const u64 m = __ballot(full && distinct == d);
+      if (lane == 0 && m) __hip_atomic_fetch_add(&B->poker[d], (u32)__popcll(m), __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+    }
     if (!full) continue;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
@@ -360,17 +368,13 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain
       for (int j = 0; j < 4; ++j) c = c * 32 + bin_of(r[4 * t + j], 32.0, 32);
       bat_add(&B->serial4[c]);
     }
-    u32 c5 = 0, c6 = 0, hand = 0;
+    u32 c5 = 0, c6 = 0;
 #pragma unroll
-    for (int j = 0; j < 5; ++j) {
-      c5 = c5 * 16 + bin_of(r[j], 16.0, 16);
-      hand |= 1u << bin_of(r[j], 16.0, 16);
-    }
+    for (int j = 0; j < 5; ++j) c5 = c5 * 16 + bin_of(r[j], 16.0, 16);
 #pragma unroll
     for (int j = 0; j < 6; ++j) c6 = c6 * 10 + bin_of(r[j], 10.0, 10);
     bat_add(&B->serial5[c5]);
     bat_add(&B->serial6[c6]);
-    bat_add(&B->poker[__builtin_popcount(hand)]);
   }
   // maximum of 32: the lanes holding one aligned block of 32 indices
   constexpr int LPG = 32 / V;  // lanes per block of 32
@@ -386,10 +390,6 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain
     for (int j = 0; j < 5; ++j) x = x * x;  // M^32
     bat_add(&B->maxt[bin_of(x, 1024.0, 1024)]);
   }
-#pragma unroll
-  for (int m = 1; m < 64; m <<= 1) nout += __shfl_xor(nout, m, 64);
-  if (lane == 0 && nout)
-    __hip_atomic_fetch_add(&B->outputs, (u64)nout, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 template <int WG, int MODE>

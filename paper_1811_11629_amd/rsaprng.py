@@ -20,6 +20,9 @@ LIB_PATH = os.environ.get("RSAPRNG_LIB") or os.path.join(HERE, "librsaprng.so")
 BLOCK_LOG2 = 20
 Q = 9223372036854775783
 A = 2307085864
+VECTOR_MAX_MV = 1 << 24          # limits of rsaprng_generate_vector
+VECTOR_MAX_COUNT = 1 << 56
+VECTOR_MAX_END = 1 << 62
 
 OK = 0
 STATUS = {
@@ -107,6 +110,7 @@ _SIGS = {
     "rsaprng_destroy": (None, [_vp]),
     "rsaprng_get_params": (_i32, [_vp, C.POINTER(rsaprng_params)]),
     "rsaprng_generate": (_i32, [_vp, _u64, _u64, _vp, _vp, _vp]),
+    "rsaprng_generate_vector": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _i32, _vp]),
     "rsaprng_generate_batch": (_i32, [C.POINTER(rsaprng_req), _sz, _vp, _vp, _vp]),
     "rsaprng_consume": (_i32, [_vp, _u64, _u64, _vp, _vp]),
     "rsaprng_pool_create": (_vp, [_sz, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
@@ -279,6 +283,13 @@ def rsaprng_generate(gen: Generator, k0: int, count: int, out_u64=None, out_f64=
                      stream=None) -> None:
     _check(lib().rsaprng_generate(gen.h, k0, count, _ptr(out_u64), _ptr(out_f64), _stream(stream)),
            "rsaprng_generate")
+
+
+def rsaprng_generate_vector(gen: Generator, mv: int, f0: int, count: int, out_u64=None,
+                            out_f64=None, variant: int = 0, stream=None) -> None:
+    """Vector mode: outputs f0 .. f0 + count - 1 of mv substreams, f = (t - 1) mv + g."""
+    _check(lib().rsaprng_generate_vector(gen.h, mv, f0, count, _ptr(out_u64), _ptr(out_f64),
+                                         variant, _stream(stream)), "rsaprng_generate_vector")
 
 
 def rsaprng_generate_batch(reqs: Sequence, out_u64=None, out_f64=None, stream=None) -> None:

@@ -44,6 +44,8 @@ def test_battery_matches_oracle(R):
         R.rsaprng_pool_battery(pool, [(j, k0, cnt, 0) for j, k0, cnt in ranges], rec, cfg=cfg)
         R.rsaprng_check_device_error()
         got = _decode(rec)
+        # the output count is the requests' total; the frequency bins prove each was counted
+        assert int(got["freq"].sum(dtype=np.uint64)) == int(got["outputs"][0])
         for name in ref:
             if name == "reserved":
                 continue
