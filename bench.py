@@ -4,8 +4,10 @@
 Headline (one "step"): the multi-instance workload -- 1024 independent seeded
 prime pairs, e = 3, each split into 256 substreams of 2^12 starting at
 k0 = j 2^12, 2^30 outputs written to HBM as uint64 c_k and binary64 r_k -- run
-as one prepared (hipGraph-captured) batch with the autotuned kernel
-configuration.  value = outputs per second of the whole step, in Gnumbers/s.
+as one prepared batch with the autotuned kernel configuration, timed as eager
+launches with HIP events between its kernels (graph replays of the same batch
+are reported beside).  value = outputs per second of the whole step, in
+Gnumbers/s.
 
 Also reported (not the headline): the same work as plain per-instance
 rsaprng_generate launches round-robin over 4 streams; the exponent sweep in
@@ -14,8 +16,10 @@ batched uneven workload (10,000 instances, lengths log-uniform in [2^8, 2^22],
 start indices below 2^40) as one graph-captured persistent launch, beside its
 plain per-request launches; the served workload (100,000 device-resident
 instances, Poisson arrivals, continuous batching: p50/p99 latency and
-throughput at a fixed offered load); the roofline of the tile kernel; and the
-CPU oracle timed on the host's cores on a bounded sample.
+throughput at a fixed offered load); parameter generation (prime and safe-prime
+counts, next-prime queries); the statistical battery as a fused consumer; the
+vector mode (M_v substreams of one instance); the roofline of the tile kernel;
+and the CPU oracle timed on the host's cores on a bounded sample.
 """
 from __future__ import annotations
 
@@ -408,6 +412,43 @@ def run_battery(R, torch, stream, steps):
     return res
 
 
+def run_vector(R, torch, stream, steps):
+    """Vector mode: 2^30 outputs of one e = 3 instance split into M_v substreams
+    (the paper's vectorised calls), for several M_v; sampled outputs checked."""
+    import numpy as np
+
+    import inputs
+    import oracle
+    inst = inputs.config2(1)[0]
+    g = R.rsaprng_create_ex(inst.p, inst.q, inst.e, inst.m0, inst.s0)
+    N = 1 << 30
+    c = torch.empty(N, dtype=torch.int64, device="cuda")
+    r = torch.empty(N, dtype=torch.float64, device="cuda")
+    res = {"workload": "one e = 3 instance of the multi-instance workload, 2^30 outputs "
+                       "(vector calls 1 .. 2^30 / M_v), uint64 c and binary64 r"}
+    rng = np.random.default_rng(11)
+    reps = max(2, steps // 4)
+    for mv in (8, 64, 4096, 1 << 16):
+        R.rsaprng_generate_vector(g, mv, 0, N, c, r, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            R.rsaprng_generate_vector(g, mv, 0, N, c, r, stream=stream)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ok = True
+        for f in rng.integers(0, N, 8):
+            cj, rj = oracle.generate_vector(inst.p, inst.q, inst.e, inst.m0, inst.s0, mv, int(f), 1)
+            ok &= int(c[int(f)].item()) & ((1 << 64) - 1) == int(cj[0]) and \
+                float(r[int(f)].item()) == float(rj[0])
+        res["mv_%d" % mv] = {"gnumbers_per_s": N / dt / 1e9, "ms": dt * 1e3, "verified_samples": ok}
+        log("vector mode M_v=%d: %.1f Gnum/s (%.2f ms), samples %s" % (mv, N / dt / 1e9, dt * 1e3, ok))
+    R.rsaprng_check_device_error(stream)
+    del c, r
+    torch.cuda.empty_cache()
+    return res
+
+
 def run_param_gen(R, torch, stream):
     """Parameter generation: primes and safe primes in [2^31, 2^32) counted on the
     device (the paper's counts are the check), and the next prime at or above
@@ -551,6 +592,7 @@ def main():
         extras["served"] = run_served(R, torch, stream)
         extras["parameter_generation"] = run_param_gen(R, torch, stream)
         extras["battery"] = run_battery(R, torch, stream, args.steps)
+        extras["vector_mode"] = run_vector(R, torch, stream, args.steps)
 
     cpu = None if args.no_cpu else cpu_baseline(insts, 1024 * B)
     if cpu:
