@@ -596,25 +596,23 @@ __device__ __forceinline__ void walk_totals(u64 s_first, double& H, double& L) {
 }
 
 // Inclusive scan over the wave of integer-valued doubles whose partial sums
-// stay below 2^53 (exact).
-__device__ __forceinline__ double wave_scan_f64(double x, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const double y = __shfl_up(x, d, 64);
-    x += lane >= d ? y : 0.0;
-  }
+// stay below 2^53 (exact in any order): the DPP pattern of wave_scan_mod, the
+// moved bits reinterpreted as doubles (a lane with no source receives +0.0).
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double x) {
+  return __longlong_as_double((long long)dpp64<CTRL, ROW_MASK>((u64)__double_as_longlong(x)));
+}
+
+__device__ __forceinline__ double wave_scan_f64(double x, int) {
+  x += dpp_f64<0x111, 0xf>(x);  // row_shr:1
+  x += dpp_f64<0x112, 0xf>(x);  // row_shr:2
+  x += dpp_f64<0x114, 0xf>(x);  // row_shr:4
+  x += dpp_f64<0x118, 0xf>(x);  // row_shr:8
+  x += dpp_f64<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+  x += dpp_f64<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
   return x;
 }
 
-// Inclusive scan mod n over the wave (lane offsets of the messages).
-__device__ __forceinline__ u64 wave_scan_shfl(u64 x, u64 n, int lane) {
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const u64 y = __shfl_up(x, d, 64);
-    if (lane >= d) x = addmod(x, y, n);
-  }
-  return x;
-}
 
 // Dispatch of one lane's outputs on the exponent: ladders unrolled for the
 // common exponents when every index of the span is requested and the stores
@@ -782,7 +780,7 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
       } else {
         u64 X[V];
         const u64 x = walk<V>(s_first, n, X);
-        const u64 incl = wave_scan_shfl(x, n, lane);
+        const u64 incl = wave_scan_mod(x, n);
         const u64 pre = addmod(E[r], submod(incl, x, n), n);
         const MsgExact<V> msg{pre, n, X};
         if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
@@ -821,7 +819,7 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
     u64 X[V];
     const u64 s_first = mulmod_q(s_tile, my_powv);
     const u64 x = walk<V>(s_first, n, X);
-    const u64 incl = wave_scan_shfl(x, n, lane);
+    const u64 incl = wave_scan_mod(x, n);
     if (lane == 63) sh.wave_tot[wave] = incl;
     __syncthreads();
     u64 wave_off = 0, agg = 0;
@@ -963,7 +961,7 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
         for (int r = 0; r < R; ++r) {
           u64 X[V];
           const u64 x = walk<V>(sf[r], n, X);
-          const u64 incl = wave_scan_shfl(x, n, lane);
+          const u64 incl = wave_scan_mod(x, n);
           ex[r] = addmod(wt, submod(incl, x, n), n);
           wt = addmod(wt, lane_value(incl, 63), n);
         }
