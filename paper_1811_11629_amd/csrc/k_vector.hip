@@ -141,21 +141,28 @@ __device__ __forceinline__ void vgen_lane(const VecArgs& a, const rsaprng_params
   u64 m = addmod(a.vgrp[(u64)(i >> a.glog2) * a.ng + j], a.vagg[(u64)i * a.ng + j], n);
   u64 s = mulmod_q(a.va[j], a.vb[i]);
   const u64 k0 = (a.sig_a + i) << a.w;
-  // indices of this segment up to the last vector call of the launch
+  // indices of this segment up to the last vector call of the launch; those
+  // before the first call only advance the message
   const u64 kend = a.t_hi - k0 + 1;
   const u32 W = 1u << a.w;
   const u32 xend = kend < W ? (u32)kend : W;
-  for (u32 x = 0; x < xend; ++x) {
+  const u32 xout = a.t_lo > k0 ? (u32)(a.t_lo - k0) : 0u;  // <= xend
+  u32 x = 0;
+  for (; x < xout; ++x) {
     if (x) s = lcg_next(s);
     m = addmod(m, skip_mod_n(s, n), n);
-    const u64 k = k0 + x;
-    if (k < a.t_lo) continue;
-    // f - f0 = (k - t_lo) M_v + g - g_lo
-    const u64 rel = (k - a.t_lo) * a.mv + g;
-    if (rel < a.g_lo || rel - a.g_lo >= a.count) continue;
+  }
+  // output offset f - f0 = (k - t_lo) M_v + g - g_lo, negative only in the
+  // first call for g < g_lo; it advances by M_v per index
+  long long o = (long long)((k0 + x - a.t_lo) * a.mv + g) - (long long)a.g_lo;
+  const long long cnt = (long long)a.count;
+  const long long step = (long long)a.mv;
+  for (; x < xend; ++x, o += step) {
+    if (x) s = lcg_next(s);
+    m = addmod(m, skip_mod_n(s, n), n);
+    if (o < 0 || o >= cnt) continue;
     double cd;
     const u64 c = encrypt<VAR, E>(m, P, cd);
-    const u64 o = rel - a.g_lo;
     if (a.out_c) a.out_c[o] = c;
     if (a.out_r) a.out_r[o] = ratio(cd, P.nd, P.nrcp);
   }

@@ -399,6 +399,9 @@ struct TileShared {
   u64 wave_tot[WG / 64];
   u64 red[MODE == kModeConsume ? (WG / 64) * 6 : 1];
   u32 hist[MODE == kModeConsume ? 1024 : 1];
+  // consume: per-thread running sums (digit sums c0..c3, r < 0.5, count),
+  // acc[j WG + thread], flushed to the record by consume_flush
+  u64 acc[MODE == kModeConsume ? 6 * WG : 1];
   // generate: per wave, two 64 x 8 blocks (c, then r) for the coalescing transpose
   u64 xbuf[MODE == kModeGenerate ? 2 * (WG / 64) * 64 * kXRow : 1];
 };
@@ -493,56 +496,74 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
         atomicAdd(&sh.hist[(int)(r * 1024.0)], 1u);
       }
     }
-    // wave reductions (each chunk sum stays below 2^42)
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-#pragma unroll
-    for (int m = 1; m < 64; m <<= 1) {
-      c0 += __shfl_xor(c0, m, 64);
-      c1 += __shfl_xor(c1, m, 64);
-      c2 += __shfl_xor(c2, m, 64);
-      c3 += __shfl_xor(c3, m, 64);
-      lt += __shfl_xor(lt, m, 64);
-      cnt += __shfl_xor(cnt, m, 64);
-    }
-    if (lane == 0) {
-      u64* rd = sh.red + wave * 6;
-      rd[0] = c0; rd[1] = c1; rd[2] = c2; rd[3] = c3; rd[4] = lt; rd[5] = cnt;
-    }
-    __syncthreads();
-    rsaprng_stats* st = a.stats + C.slot;
-    if (threadIdx.x == 0) {
-      u64 s[4] = {0, 0, 0, 0}, tl = 0, tc = 0;
-      for (int w = 0; w < WG / 64; ++w) {
-        for (int j = 0; j < 4; ++j) s[j] += sh.red[w * 6 + j];
-        tl += sh.red[w * 6 + 4];
-        tc += sh.red[w * 6 + 5];
-      }
-      // carry-normalise into 32-bit digits so each atomic adds < 2^32
-      u64 carry = 0;
-      u32 dig[6];
-      for (int j = 0; j < 4; ++j) {
-        u64 v = s[j] + carry;
-        dig[j] = lo32(v);
-        carry = v >> 32;
-      }
-      dig[4] = lo32(carry);
-      dig[5] = hi32(carry);
-      for (int j = 0; j < 6; ++j)
-        if (dig[j]) atomicAdd((unsigned long long*)&st->acc32[j], (unsigned long long)dig[j]);
-      if (tl) atomicAdd((unsigned long long*)&st->lt_half, (unsigned long long)tl);
-      if (tc) atomicAdd((unsigned long long*)&st->count, (unsigned long long)tc);
-    }
-    for (int b = threadIdx.x; b < 1024; b += WG) {
-      const u32 h = sh.hist[b];
-      if (h) {
-        atomicAdd((unsigned long long*)&st->hist[b], (unsigned long long)h);
-        sh.hist[b] = 0;
-      }
-    }
-    // No wave may add to the histogram or the reduction slots of the next chunk
-    // (possibly another chain's record) before every bin of this one is flushed.
-    __syncthreads();
+    u64* const acc = sh.acc + threadIdx.x;
+    acc[0] += c0;
+    acc[WG] += c1;
+    acc[2 * WG] += c2;
+    acc[3 * WG] += c3;
+    acc[4 * WG] += lt;
+    acc[5 * WG] += cnt;
   }
+}
+
+// Consume: the work-group's running sums and histogram added to stats record
+// `slot` and cleared.  Called by every thread of the work-group, after the
+// last chunk of a tile (or chain) that reduced into this record.  Per thread
+// each digit sum stays below 2^32 times the thread's outputs (at most 2^14 per
+// chain of 2^20), so every total below is far from 2^64.
+template <int WG>
+__device__ __forceinline__ void consume_flush(const LaunchArgs& a, TileShared<WG, kModeConsume>& sh,
+                                              u32 slot) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  u64 v[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) {
+    v[j] = sh.acc[j * WG + threadIdx.x];
+    sh.acc[j * WG + threadIdx.x] = 0;
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) v[j] += __shfl_xor(v[j], m, 64);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int j = 0; j < 6; ++j) sh.red[wave * 6 + j] = v[j];
+  }
+  __syncthreads();
+  rsaprng_stats* st = a.stats + slot;
+  if (threadIdx.x == 0) {
+    u64 s[4] = {0, 0, 0, 0}, tl = 0, tc = 0;
+    for (int w = 0; w < WG / 64; ++w) {
+      for (int j = 0; j < 4; ++j) s[j] += sh.red[w * 6 + j];
+      tl += sh.red[w * 6 + 4];
+      tc += sh.red[w * 6 + 5];
+    }
+    // carry-normalise into 32-bit digits so each atomic adds < 2^32
+    u64 carry = 0;
+    u32 dig[6];
+    for (int j = 0; j < 4; ++j) {
+      u64 v = s[j] + carry;
+      dig[j] = lo32(v);
+      carry = v >> 32;
+    }
+    dig[4] = lo32(carry);
+    dig[5] = hi32(carry);
+    for (int j = 0; j < 6; ++j)
+      if (dig[j]) atomicAdd((unsigned long long*)&st->acc32[j], (unsigned long long)dig[j]);
+    if (tl) atomicAdd((unsigned long long*)&st->lt_half, (unsigned long long)tl);
+    if (tc) atomicAdd((unsigned long long*)&st->count, (unsigned long long)tc);
+  }
+  for (int b = threadIdx.x; b < 1024; b += WG) {
+    const u32 h = sh.hist[b];
+    if (h) {
+      atomicAdd((unsigned long long*)&st->hist[b], (unsigned long long)h);
+      sh.hist[b] = 0;
+    }
+  }
+  // No wave may add to the histogram or the sums of the next tile (possibly
+  // another record's) before every bin of this one is flushed.
+  __syncthreads();
 }
 
 // Walk of one lane: V skips from s_first (eq. congruentialgenerator1), running
@@ -740,6 +761,7 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
   for (int r = 0; r < R; ++r) pv[r] = a.powv[((u64)wave * R + r) * 64 + lane];
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
+    for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
     __syncthreads();
   }
   for (u32 t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
@@ -787,6 +809,9 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
         chain_end<V>(a, C, n, pre, X, s_first, laneStart);
       }
     }
+    if constexpr (MODE == kModeConsume) {
+      if (any_out) consume_flush<WG>(a, sh, C.slot);
+    }
   }
 }
 
@@ -801,6 +826,7 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
   const u64 my_powv = a.powv[threadIdx.x];
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
+    for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
   }
   const u32 tag = a.ctl->epoch;
   for (;;) {
@@ -852,6 +878,7 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
                          ((!a.out_c || ((uintptr_t)(a.out_c + off_t) & 15) == 0) &&
                           (!a.out_r || ((uintptr_t)(a.out_r + off_t) & 15) == 0)));
       outputs_for_e<WG, V, VAR, MODE>(a, sh, C, P, MsgExact<V>{pre, n, X}, fast, laneStart);
+      if constexpr (MODE == kModeConsume) consume_flush<WG>(a, sh, C.slot);
     }
     chain_end<V>(a, C, n, pre, X, s_first, laneStart);
     __syncthreads();
@@ -882,6 +909,7 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
   const u64 aT = load_cst(a.at + 1);  // a^T mod Q
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
+    for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
     __syncthreads();
   }
   for (u32 c = blockIdx.x; c < a.nchain; c += gridDim.x) {
@@ -945,9 +973,9 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
             const u64 laneStart = chunkStart + (u64)lane * V;
             const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
             const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
-            const MsgResWalk<V> msg{sf[r], bp, bq};
             const bool chunk_out = MODE == kModeConsume ||
                                    (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
+            const MsgResWalk<V> msg{sf[r], bp, bq};
             if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
             chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
           }
@@ -992,6 +1020,7 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
       if (clast - base < T) break;
       s_step = mulmod_q(s_step, aT);
     }
+    if constexpr (MODE == kModeConsume) consume_flush<WG>(a, sh, C.slot);
   }
 }
 
