@@ -1,7 +1,7 @@
 // gfx950 kernels of the RSA-exponentiation generator.
 //
 // The work of a launch is a list of chains (the tiles of one request inside
-// one 2^20 block) and T = WG * V consecutive indices per tile.
+// one 2^20 block) and T = WG * V * R consecutive indices per tile or step.
 //
 //   k_chain_setup  one wave per chain: the skip at the chain start,
 //                  s0 a^S mod Q, by a product tree of the table a^(2^i) over
@@ -12,16 +12,18 @@
 //                  (eq. congruentialgenerator1) summed mod n.
 //   k_scan         (two-pass) one wave per chain: exclusive prefix of the tile
 //                  sums, i.e. the message before every tile (m_k = m_{k-1} + s_k).
-//   k_gen          one work-group per tile: V skips per lane from the tile's
-//                  start skip, running sums in registers, wave + LDS scan, then
-//                  per element c = m^e mod n (Montgomery-64 or CRT with
-//                  binary64 residues) and r = RN(c)/RN(n) with the 1.0 guard,
-//                  stored to HBM (generate) or folded into exact statistics
-//                  (consume).  Two-pass: the message before the tile comes from
-//                  k_scan.  Single pass: tiles are claimed from an atomic queue
-//                  and the prefix comes from a decoupled look-back over the
-//                  preceding tiles of the chain (tagged 64-bit words, relaxed
-//                  agent-scope atomics, bounded wait).
+//   k_gen2/1/3     the tile kernels: V skips per lane, lane totals scanned
+//                  across the wave with DPP moves, then per element
+//                  c = m^e mod n (Montgomery-64 or CRT with binary64
+//                  residues) and r = RN(c)/RN(n) with the 1.0 guard, stored to
+//                  HBM through a per-wave LDS transpose (generate), folded into
+//                  exact statistics flushed once per tile or chain (consume),
+//                  or counted into the battery record (battery).  The message
+//                  before a tile comes from k_scan (k_gen2), from a decoupled
+//                  look-back over the chain's earlier tiles (k_gen1: atomic
+//                  tile queue, tagged 64-bit words, relaxed agent-scope
+//                  atomics, bounded wait), or from the carry of the previous
+//                  step when one work-group walks the whole chain (k_gen3).
 #pragma once
 #include "common.h"
 #include "devmath.h"
