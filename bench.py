@@ -506,10 +506,11 @@ def main():
     ap.add_argument("--config", default="",
                     help="fixed kernel configuration 'variant,lanes,per_lane,persistent[,prefix[,r]]' "
                          "instead of the autotuner (variant 1 = Montgomery-64, 2 = CRT; prefix 0 "
-                         "= two passes, 1 = single pass with look-back)")
+                         "= two passes, 1 = single pass with look-back, 2 = chain-serial; r = "
+                         "chunks per wave)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the generator "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the generator "
               "shards by instance or index range with no exchange; see the design notes). "
               "Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)

@@ -1,0 +1,32 @@
+"""bench.py's contract on the host: more than one GPU is refused with a message
+before anything touches a device, and the kernel-source hash keying the traffic
+record covers the generate tile kernels' sources."""
+import os
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and "--gpus 1" in r.stderr
+
+
+def test_traffic_record_is_keyed_by_the_generate_kernel_sources():
+    import json
+
+    import bench
+    h = bench.kernel_source_hash()
+    assert len(h) == 16
+    for f in bench.DEVICE_SOURCES:
+        assert os.path.exists(os.path.join(ROOT, "paper_1811_11629_amd", "csrc", f)), f
+    rec = json.load(open(os.path.join(ROOT, "profiles", "tile_kernel_traffic.json")))
+    ent = rec["multi_instance_e3"]
+    # the record names its kernel and carries both counter passes and the copy calibration
+    for k in ("kernel", "kernel_source_hash", "fetch_size_kib", "write_size_kib",
+              "copy_fetch_factor", "copy_write_factor", "hbm_bytes_per_launch"):
+        assert k in ent, k
