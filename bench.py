@@ -412,6 +412,38 @@ def run_battery(R, torch, stream, steps):
     return res
 
 
+def run_single(R, torch, stream, steps):
+    """The single-instance workload: one rsaprng_generate of k in [0, 2^20) on a
+    handle (launch- and latency-bound at this size), timed with events."""
+    import numpy as np
+
+    import inputs
+    import oracle
+    inst = inputs.config1()
+    g = R.rsaprng_create_ex(inst.p, inst.q, inst.e, inst.m0, inst.s0)
+    c = torch.empty(B, dtype=torch.int64, device="cuda")
+    r = torch.empty(B, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        R.rsaprng_generate(g, 0, B, c, r, stream=stream)
+    reps = max(10, steps)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(reps)]
+    torch.cuda.synchronize()
+    for a, b in evs:
+        a.record(stream)
+        R.rsaprng_generate(g, 0, B, c, r, stream=stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    us = sorted(a.elapsed_time(b) * 1e3 for a, b in evs)[reps // 2]
+    cref, rref = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, 0, B)
+    ok = bool(np.array_equal(c.cpu().numpy().view(np.uint64), cref) and
+              np.array_equal(r.cpu().numpy().view(np.uint64), rref.view(np.uint64)))
+    R.rsaprng_check_device_error(stream)
+    log("single instance: %.1f us per 2^20 outputs (%.1f Gnum/s), verified %s" % (us, B / us / 1e3, ok))
+    return {"workload": "one instance (e = %d), k in [0, 2^20), c and r, one rsaprng_generate" % inst.e,
+            "us": us, "gnumbers_per_s": B / us / 1e3, "verified": ok}
+
+
 def run_vector(R, torch, stream, steps):
     """Vector mode: 2^30 outputs of one e = 3 instance split into M_v substreams
     (the paper's vectorised calls), for several M_v; sampled outputs checked."""
@@ -588,6 +620,7 @@ def main():
         del gens
         del batch, oc, orr
         torch.cuda.empty_cache()
+        extras["single_instance"] = run_single(R, torch, stream, args.steps)
         extras["exponent_sweep_consume"] = run_consume_sweep(R, torch, stream, args.steps)
         extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
         extras["served"] = run_served(R, torch, stream)
