@@ -388,7 +388,7 @@ def run_battery(R, torch, stream, steps):
     best = None
     t_best = 1e30
     for cfg in (R.config(variant=2, prefix=2, lanes_per_tile=256, chunks_per_wave=4),
-                R.config(variant=2, prefix=0, lanes_per_tile=256, chunks_per_wave=4)):
+                R.config(variant=2, prefix=2, lanes_per_tile=512, chunks_per_wave=2)):
         R.rsaprng_pool_battery(pool, reqs, rec, cfg=cfg, stream=stream)
         torch.cuda.synchronize()
         t0 = time.perf_counter()

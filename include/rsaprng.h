@@ -344,10 +344,15 @@ void rsaprng_server_destroy(rsaprng_server_t s);
  * (a serial cell is the mixed-radix number of its coordinates, first index
  * most significant), the poker class is the number of distinct floor(16 r),
  * and the maximum M of 32 goes to bin floor(1024 M^32) (M^32 by five exact
- * squarings; it is uniform when the r are).  Counts are unsigned 32-bit (per
- * bin; wraps after 2^32).
+ * squarings; it is uniform when the r are).  Collisions: every aligned block
+ * of 2^14 indices is one trial of 2^14 balls thrown into 2^20 urns (urn
+ * floor(2^20 r)); C = 2^14 - (number of distinct urns) is counted in coll[C]
+ * (C >= 255 in coll[255]).  Gaps (runs of 0s and 1s, b = [r > 1/2]): in every
+ * aligned block of 64 indices, the run that starts at the block's first index
+ * has value b and length L (1..64, capped by the block): runs[b][L - 1].
+ * Counts are unsigned 32-bit (per bin; wraps after 2^32).
  * ------------------------------------------------------------------------ */
-#define RSAPRNG_BAT_TESTS 8   /* frequency, serial D = 2..6, poker, max-of-32 */
+#define RSAPRNG_BAT_TESTS 10  /* frequency, serial D = 2..6, poker, max-of-32, collisions, gaps */
 typedef struct {
   uint64_t outputs;           /* number of r_k consumed: the sum of the requests' counts */
   uint64_t reserved;
@@ -359,19 +364,27 @@ typedef struct {
   uint32_t serial6[1000000];  /* 10 */
   uint32_t poker[8];          /* [d] = hands with d distinct values, d = 1..5 */
   uint32_t maxt[1024];        /* bin floor(1024 M^32) */
+  uint32_t coll[256];         /* [C] = trials of 2^14 balls with C collisions */
+  uint32_t runs[2][64];       /* [b][L - 1] = leading runs of value b and length L */
 } rsaprng_battery;
 
 /* Zeroes *rec_dev, then accumulates every request into it (reqs[i].out_off is
- * ignored).  The CRT variant is used whatever cfg->variant says. */
+ * ignored).  Runs the chain-serial CRT kernel whatever cfg asks (its work-group
+ * walks each chain in order and holds a trial's 2^20-urn bitmap, 128 KB, in
+ * LDS); cfg->lanes_per_tile and cfg->chunks_per_wave select its shape. */
 int rsaprng_pool_battery(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
                          rsaprng_battery* rec_dev, const rsaprng_config* cfg, void* stream);
 
 /* Chi-squared statistic, degrees of freedom and p-value (the upper tail
  * P(X >= chi2) of the chi-squared distribution) of each test, in the order of
  * RSAPRNG_BAT_TESTS, from a HOST copy of a record: uniform expectations for the
- * frequency, serial and max tests, and for poker the exact probabilities
+ * frequency, serial and max tests; for poker the exact probabilities
  * S(5, d) 16 15 ... (16 - d + 1) / 16^5 (S: Stirling numbers of the second
- * kind), with the classes d = 1, 2 merged.  Host only. */
+ * kind), with the classes d = 1, 2 merged; for collisions the exact
+ * distribution of C for 2^14 balls in 2^20 urns (occupancy recursion); for
+ * gaps P(b, L) = 2^-(L+1) for L < 64 and 2^-64 for L = 64.  Collision and gap
+ * classes are merged from the tails until each expects at least 5 counts.
+ * Host only. */
 typedef struct {
   double chi2[RSAPRNG_BAT_TESTS];
   double dof[RSAPRNG_BAT_TESTS];

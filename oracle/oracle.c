@@ -432,6 +432,43 @@ int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t
     B->maxt[bin_of(t, 1024.0, 1024)]++;
     if (k32 > UINT64_MAX - 32) break;
   }
+  /* aligned blocks of 64: the run that starts at the block's first index */
+  for (uint64_t k64 = (k0 + 63) / 64 * 64; k64 >= k0 && k64 <= last && last - k64 >= 63; k64 += 64) {
+    const double* x = r + (k64 - k0);
+    const int b = x[0] > 0.5;
+    int len = 1;
+    while (len < 64 && (x[len] > 0.5) == b) ++len;
+    B->runs[b][len - 1]++;
+    if (k64 > UINT64_MAX - 64) break;
+  }
+  /* aligned blocks of 2^14: balls in 2^20 urns, collisions = balls - distinct urns */
+  const uint64_t T = 1u << 14;
+  uint64_t kt = (k0 + T - 1) / T * T;
+  if (kt >= k0 && kt <= last && last - kt >= T - 1) {
+    uint32_t* urn = (uint32_t*)calloc(1u << 15, sizeof(uint32_t));
+    if (!urn) {
+      free(r);
+      return -9;
+    }
+    for (; kt >= k0 && kt <= last && last - kt >= T - 1; kt += T) {
+      uint32_t distinct = 0;
+      for (uint64_t j = 0; j < T; ++j) {
+        const uint32_t u = bin_of(r[kt - k0 + j], 1048576.0, 1u << 20);
+        if (!(urn[u >> 5] & (1u << (u & 31)))) {
+          urn[u >> 5] |= 1u << (u & 31);
+          ++distinct;
+        }
+      }
+      const uint32_t c = (uint32_t)T - distinct;
+      B->coll[c < 255 ? c : 255]++;
+      for (uint64_t j = 0; j < T; ++j) {
+        const uint32_t u = bin_of(r[kt - k0 + j], 1048576.0, 1u << 20);
+        urn[u >> 5] = 0;
+      }
+      if (kt > UINT64_MAX - T) break;
+    }
+    free(urn);
+  }
   free(r);
   return 0;
 }

@@ -115,7 +115,12 @@ uint64_t oracle_next_prime(uint64_t x, int safe, const uint32_t* exps, int nexp)
  * coordinate: min(floor(b r), b - 1); a serial cell is the mixed-radix number
  * of its coordinates, first index most significant; the poker class is the
  * number of distinct floor(16 r); the maximum M goes to floor(1024 M^32) with
- * M^32 by five squarings.  oracle_battery_add ACCUMULATES into *b. */
+ * M^32 by five squarings.  Collision test: each aligned block of 2^14
+ * indices throws 2^14 balls into 2^20 urns floor(2^20 r); C = 2^14 minus the
+ * number of distinct urns, counted in coll[min(C, 255)].  Gaps test (runs of
+ * 0s and 1s with b = [r > 1/2]): in each aligned block of 64 indices the run
+ * starting at its first index, value b and length L <= 64, in runs[b][L - 1].
+ * oracle_battery_add ACCUMULATES into *b. */
 typedef struct {
   uint64_t outputs;
   uint64_t reserved;
@@ -127,6 +132,8 @@ typedef struct {
   uint32_t serial6[1000000];
   uint32_t poker[8];
   uint32_t maxt[1024];
+  uint32_t coll[256];
+  uint32_t runs[2][64];
 } oracle_battery;
 int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
                        uint64_t count, oracle_battery* b);

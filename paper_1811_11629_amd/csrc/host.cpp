@@ -1055,6 +1055,12 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
     c2.variant = kVariantCrt;
     c = resolve_config(&c2);
   }
+  if (mode == kModeBattery && c.prefix != kPrefixSerial) {
+    // the battery's collision trials need one work-group walking each chain
+    rsaprng_config c2 = c;
+    c2.prefix = kPrefixSerial;
+    c = resolve_config(&c2);
+  }
   std::vector<Chain> plan;
   u64h ntiles;
   if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
@@ -1131,6 +1137,73 @@ double rsaprng_chi2_sf(double chi2, double dof) {
   return std::exp(lpre) * h;
 }
 
+}  // extern "C"
+
+namespace {
+
+// P(C = c) for c < 255 and P(C >= 255) in [255], C = collisions of 2^14 balls
+// thrown into 2^20 urns: the distribution of C after each ball, where the
+// next ball collides with probability (occupied urns) / 2^20 = (t - C) / 2^20.
+const std::vector<double>& collision_probs() {
+  static const std::vector<double> P = [] {
+    const int n = 1 << 14, cmax = 600;
+    const double m = 1048576.0;
+    std::vector<double> b(cmax + 1, 0.0), nb(cmax + 1, 0.0);
+    b[0] = 1.0;
+    for (int t = 0; t < n; ++t) {
+      for (int c = 0; c <= cmax && c <= t + 1; ++c) {
+        double v = c <= t ? b[c] * (1.0 - (t - c) / m) : 0.0;
+        if (c > 0) v += b[c - 1] * ((t - (c - 1)) / m);
+        nb[c] = v;
+      }
+      std::swap(b, nb);
+    }
+    std::vector<double> q(256, 0.0);
+    double seen = 0.0;
+    for (int c = 0; c < 255; ++c) {
+      q[c] = b[c];
+      seen += b[c];
+    }
+    q[255] = 1.0 - seen;
+    return q;
+  }();
+  return P;
+}
+
+// Chi-squared over ordered classes: adjacent classes are merged from the left
+// until each expects at least 5 counts, a short remainder joining the last.
+void chi2_merged(const double* obs, const double* prob, int k, double n, double& chi2,
+                 double& dof) {
+  std::vector<double> O, E;
+  double o = 0, e = 0;
+  for (int i = 0; i < k; ++i) {
+    o += obs[i];
+    e += n * prob[i];
+    if (e >= 5.0) {
+      O.push_back(o);
+      E.push_back(e);
+      o = e = 0;
+    }
+  }
+  if (e > 0 || o > 0) {
+    if (E.empty()) {
+      O.push_back(o);
+      E.push_back(e);
+    } else {
+      O.back() += o;
+      E.back() += e;
+    }
+  }
+  chi2 = 0;
+  for (size_t i = 0; i < O.size(); ++i)
+    if (E[i] > 0) chi2 += (O[i] - E[i]) * (O[i] - E[i]) / E[i];
+  dof = (double)O.size() - 1.0;
+}
+
+}  // namespace
+
+extern "C" {
+
 int rsaprng_battery_report(const rsaprng_battery* r, rsaprng_battery_result* out) {
   if (!r || !out) return RSAPRNG_E_NULL;
   std::memset(out, 0, sizeof(*out));
@@ -1167,6 +1240,30 @@ int rsaprng_battery_report(const rsaprng_battery* r, rsaprng_battery_result* out
     out->p[6] = n > 0 ? rsaprng_chi2_sf(x, 3.0) : 0.0 / 0.0;
   }
   uniform(7, r->maxt, 1024);
+  {
+    const std::vector<double>& P = collision_probs();
+    double o[256], n = 0;
+    for (int c = 0; c < 256; ++c) n += (o[c] = r->coll[c]);
+    out->samples[8] = (uint64_t)n;
+    chi2_merged(o, P.data(), 256, n, out->chi2[8], out->dof[8]);
+    out->p[8] = n > 0 && out->dof[8] > 0 ? rsaprng_chi2_sf(out->chi2[8], out->dof[8]) : 0.0 / 0.0;
+  }
+  {
+    // each value b: lengths 1..64 with probabilities 2^-(L+1) (L < 64), 2^-64
+    double o[128], pr[128], n = 0;
+    for (int b = 0; b < 2; ++b)
+      for (int L = 1; L <= 64; ++L) {
+        n += (o[b * 64 + L - 1] = r->runs[b][L - 1]);
+        pr[b * 64 + L - 1] = std::ldexp(1.0, L < 64 ? -(L + 1) : -64);
+      }
+    double c0, d0, c1, d1;
+    chi2_merged(o, pr, 64, n, c0, d0);
+    chi2_merged(o + 64, pr + 64, 64, n, c1, d1);
+    out->samples[9] = (uint64_t)n;
+    out->chi2[9] = c0 + c1;
+    out->dof[9] = d0 + d1 + 1.0;  // one constraint (the total) over both values' classes
+    out->p[9] = n > 0 ? rsaprng_chi2_sf(out->chi2[9], out->dof[9]) : 0.0 / 0.0;
+  }
   return RSAPRNG_OK;
 }
 

@@ -304,11 +304,21 @@ struct MsgExactWalk {
 constexpr int kXRow = 9;
 
 // ---------------------------------------------------------------------------
-// Statistical battery (fused consumer): counts of one lane's V indices into
-// the device record.  Tuples live inside aligned blocks of 8 indices and the
-// maximum of 32 in aligned blocks of 32 (a block counts when all its indices
-// are requested), so the counts do not depend on the tiling.
+// Statistical battery (fused consumer), chain-serial kernel only.  Tuples live
+// inside aligned blocks of 8 indices, maxima in aligned blocks of 32, gap runs
+// in aligned blocks of 64 and collision trials in aligned blocks of 2^14 (a
+// block counts when all its indices are requested), so the counts do not
+// depend on the tiling.  Large tables (frequency, serial) take device-scope
+// atomics; the small ones (poker, maxima, runs) and the trial's urn bitmap
+// live in the work-group's LDS and are flushed per chain or per trial.
 // ---------------------------------------------------------------------------
+constexpr int kBatPoker = 0;                 // LDS counts: poker classes [0, 8)
+constexpr int kBatMax = 8;                   // maxima bins [8, 1032)
+constexpr int kBatRuns = kBatMax + 1024;     // runs[b][L - 1] [1032, 1160)
+constexpr int kBatLds = kBatRuns + 128;
+constexpr int kTrialLog2 = 14;               // 2^14 balls per collision trial
+constexpr int kUrnWords = (1 << 20) / 32;    // 2^20 urns as a bitmap
+
 __device__ __forceinline__ u32 bin_of(double r, double b, u32 nb) {
   const u32 x = (u32)(r * b);
   return x < nb ? x : nb - 1;
@@ -318,12 +328,19 @@ __device__ __forceinline__ void bat_add(u32* p) {
   __hip_atomic_fetch_add(p, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-template <int V, int VAR, u32 E, class Msg>
-__device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain& C,
+template <int WG, int MODE>
+struct TileShared;
+
+template <int WG, int V, int VAR, u32 E, class Msg>
+__device__ __forceinline__ void battery_outputs(const LaunchArgs& a,
+                                                TileShared<WG, kModeBattery>& sh, const Chain& C,
                                                 const rsaprng_params& P, Msg msg, u64 laneStart) {
-  static_assert(V % 8 == 0, "blocks of 8 indices");
+  static_assert(V == 8, "a lane holds one block of 8; 8 lanes hold a block of 64");
   rsaprng_battery* const B = a.battery;
   const int lane = threadIdx.x & 63;
+  // the chunk of 64 V indices lies inside one collision trial
+  const u64 kt = laneStart >> kTrialLog2 << kTrialLog2;
+  const bool trial = kt >= C.k0 && kt <= C.last && C.last - kt >= (1ull << kTrialLog2) - 1;
   double rv[V];
 #pragma unroll
   for (int i = 0; i < V; ++i) {
@@ -331,31 +348,28 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain
     (void)msg.template enc<VAR, E>(i, P, cd);
     rv[i] = ratio(cd, P.nd, P.nrcp);
     const u64 k = laneStart + i;
-    if (k >= C.k0 && k <= C.last) bat_add(&B->freq[bin_of(rv[i], 1048576.0, 1u << 20)]);
+    const u32 u = bin_of(rv[i], 1048576.0, 1u << 20);
+    if (k >= C.k0 && k <= C.last) bat_add(&B->freq[u]);
+    if (trial)
+      __hip_atomic_fetch_or(&sh.urn[u >> 5], 1u << (u & 31), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_WORKGROUP);
   }
+  const double* r = rv;
+  const bool full = laneStart >= C.k0 && laneStart <= C.last && C.last - laneStart >= 7;
   double mx = 0.0;
-  bool all = true;
 #pragma unroll
-  for (int b = 0; b < V / 8; ++b) {
-    const double* r = rv + 8 * b;
-    const u64 k8 = laneStart + 8 * b;
-    const bool full = k8 >= C.k0 && k8 <= C.last && C.last - k8 >= 7;
-    all = all && full;
+  for (int i = 0; i < 8; ++i) mx = r[i] > mx ? r[i] : mx;
+  // poker: the five classes counted per wave (one LDS add per class)
+  u32 hand = 0;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) mx = r[i] > mx ? r[i] : mx;
-    // poker: the five classes counted per wave (one atomic per class), since
-    // most hands fall into two of them
-    u32 hand = 0;
+  for (int j = 0; j < 5; ++j) hand |= 1u << bin_of(r[j], 16.0, 16);
+  const u32 distinct = __builtin_popcount(hand);
 #pragma unroll
-    for (int j = 0; j < 5; ++j) hand |= 1u << bin_of(r[j], 16.0, 16);
-    const u32 distinct = __builtin_popcount(hand);
-#pragma unroll
-    for (u32 d = 1; d <= 5; ++d) {
-      const u64 m = __ballot(full && distinct == d);
-      if (lane == 0 && m) __hip_atomic_fetch_add(&B->poker[d], (u32)__popcll(m), __ATOMIC_RELAXED,
-                                                 __HIP_MEMORY_SCOPE_AGENT);
-    }
-    if (!full) continue;
+  for (u32 d = 1; d <= 5; ++d) {
+    const u64 m = __ballot(full && distinct == d);
+    if (lane == 0 && m) atomicAdd(&sh.bh[kBatPoker + d], (u32)__popcll(m));
+  }
+  if (full) {
 #pragma unroll
     for (int t = 0; t < 4; ++t)
       bat_add(&B->serial2[bin_of(r[2 * t], 1024.0, 1024) * 1024 + bin_of(r[2 * t + 1], 1024.0, 1024)]);
@@ -378,20 +392,35 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a, const Chain
     bat_add(&B->serial5[c5]);
     bat_add(&B->serial6[c6]);
   }
-  // maximum of 32: the lanes holding one aligned block of 32 indices
-  constexpr int LPG = 32 / V;  // lanes per block of 32
+  // maximum of 32: the four lanes holding one aligned block of 32 indices
+  bool all = full;
 #pragma unroll
-  for (int m = 1; m < LPG; m <<= 1) {
+  for (int m = 1; m < 4; m <<= 1) {
     const double o = __shfl_xor(mx, m, 64);
     mx = o > mx ? o : mx;
     all = (__shfl_xor((int)all, m, 64) != 0) && all;
   }
-  if (all && (lane % LPG) == 0) {
+  if (all && (lane & 3) == 0) {
     double x = mx;
 #pragma unroll
     for (int j = 0; j < 5; ++j) x = x * x;  // M^32
-    bat_add(&B->maxt[bin_of(x, 1024.0, 1024)]);
+    atomicAdd(&sh.bh[kBatMax + bin_of(x, 1024.0, 1024)], 1u);
   }
+  // gaps: the run of b = [r > 1/2] that starts at an aligned block of 64
+  // (lanes g0 .. g0 + 7): full lanes continue it, the first other lane ends it
+  u32 bits = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) bits |= (r[i] > 0.5 ? 1u : 0u) << i;
+  const int g0 = lane & ~7;
+  const u32 b0 = (u32)__shfl((int)(bits & 1u), g0, 64);
+  const u32 same = b0 ? bits : (~bits & 0xffu);  // 1 where the bit equals b0
+  const u32 t = same == 0xffu ? 8u : (u32)__builtin_ctz(~same);
+  const u32 fullm = (u32)(__ballot(t == 8u) >> g0) & 0xffu;
+  const u32 m = fullm == 0xffu ? 8u : (u32)__builtin_ctz(~fullm);
+  const u32 tm = (u32)__shfl((int)t, g0 + (m < 8u ? (int)m : 7), 64);
+  const u64 k64 = laneStart - (u64)(lane & 7) * 8;
+  const bool blk64 = k64 >= C.k0 && k64 <= C.last && C.last - k64 >= 63;
+  if ((lane & 7) == 0 && blk64) atomicAdd(&sh.bh[kBatRuns + b0 * 64 + (m < 8u ? 8u * m + tm : 64u) - 1], 1u);
 }
 
 template <int WG, int MODE>
@@ -406,6 +435,9 @@ struct TileShared {
   u64 acc[MODE == kModeConsume ? 6 * WG : 1];
   // generate: per wave, two 64 x 8 blocks (c, then r) for the coalescing transpose
   u64 xbuf[MODE == kModeGenerate ? 2 * (WG / 64) * 64 * kXRow : 1];
+  // battery: the current collision trial's urns, and the small tables
+  u32 urn[MODE == kModeBattery ? kUrnWords : 1];
+  u32 bh[MODE == kModeBattery ? kBatLds : 1];
 };
 
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
@@ -477,7 +509,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       }
     }
   } else if constexpr (MODE == kModeBattery) {
-    battery_outputs<V, VAR, E>(a, C, P, msg, laneStart);
+    battery_outputs<WG, V, VAR, E>(a, sh, C, P, msg, laneStart);
   } else {
     u64 c0 = 0, c1 = 0, c2 = 0, c3 = 0, lt = 0, cnt = 0;
 #pragma unroll
@@ -565,6 +597,48 @@ __device__ __forceinline__ void consume_flush(const LaunchArgs& a, TileShared<WG
   }
   // No wave may add to the histogram or the sums of the next tile (possibly
   // another record's) before every bin of this one is flushed.
+  __syncthreads();
+}
+
+// Battery: the collision trial that just ended (all of its 2^14 indices
+// requested): C = 2^14 - (urns hit), then the bitmap is cleared.  Called by
+// every thread of the work-group.
+template <int WG>
+__device__ __forceinline__ void trial_flush(const LaunchArgs& a, TileShared<WG, kModeBattery>& sh) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  u32 hit = 0;
+  for (int i = threadIdx.x; i < kUrnWords; i += WG) {
+    hit += __builtin_popcount(sh.urn[i]);
+    sh.urn[i] = 0;
+  }
+#pragma unroll
+  for (int m = 1; m < 64; m <<= 1) hit += __shfl_xor(hit, m, 64);
+  if (lane == 0) sh.wave_tot[wave] = hit;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    u64 distinct = 0;
+    for (int w = 0; w < WG / 64; ++w) distinct += sh.wave_tot[w];
+    const u64 c = (1ull << kTrialLog2) - distinct;
+    bat_add(&a.battery->coll[c < 255 ? c : 255]);
+  }
+  __syncthreads();
+}
+
+// Battery: the work-group's small tables added to the record and cleared.
+template <int WG>
+__device__ __forceinline__ void battery_flush(const LaunchArgs& a, TileShared<WG, kModeBattery>& sh) {
+  __syncthreads();
+  rsaprng_battery* const B = a.battery;
+  for (int i = threadIdx.x; i < kBatLds; i += WG) {
+    const u32 v = sh.bh[i];
+    if (v) {
+      u32* dst = i < kBatMax ? &B->poker[i - kBatPoker]
+                             : (i < kBatRuns ? &B->maxt[i - kBatMax] : &B->runs[0][0] + (i - kBatRuns));
+      __hip_atomic_fetch_add(dst, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      sh.bh[i] = 0;
+    }
+  }
   __syncthreads();
 }
 
@@ -914,6 +988,11 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
     for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
     __syncthreads();
   }
+  if constexpr (MODE == kModeBattery) {
+    for (int i = threadIdx.x; i < kUrnWords; i += WG) sh.urn[i] = 0;
+    for (int i = threadIdx.x; i < kBatLds; i += WG) sh.bh[i] = 0;
+    __syncthreads();
+  }
   for (u32 c = blockIdx.x; c < a.nchain; c += gridDim.x) {
     const Chain C = load_cst(a.chain + c);
     const rsaprng_params P = load_cst(a.inst + C.inst);
@@ -1019,10 +1098,19 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
         }
         cm = addmod(cm, tot, n);
       }
+      if constexpr (MODE == kModeBattery) {
+        // a step that ends a collision trial whose indices were all requested
+        // (T divides 2^14, so steps never straddle a trial)
+        const u64 end = base + T;
+        if ((end & ((1ull << kTrialLog2) - 1)) == 0 && end - (1ull << kTrialLog2) >= C.k0 &&
+            end - 1 <= C.last)
+          trial_flush<WG>(a, sh);
+      }
       if (clast - base < T) break;
       s_step = mulmod_q(s_step, aT);
     }
     if constexpr (MODE == kModeConsume) consume_flush<WG>(a, sh, C.slot);
+    if constexpr (MODE == kModeBattery) battery_flush<WG>(a, sh);
   }
 }
 
@@ -1073,24 +1161,32 @@ static int launch1(const LaunchArgs& a, int grid, void* stream, int* occ) {
 // Launcher and occupancy query for every shape of one (variant, mode).
 template <int VAR, int MODE>
 int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* occ) {
-  if (s.prefix == kPrefixTwoPass) {
-    if (s.wg == 256 && s.v == 8 && s.r == 1) return launch2<256, 8, 1, VAR, MODE>(a, s.grid, stream, occ);
-    if (s.wg == 256 && s.v == 8 && s.r == 2) return launch2<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
-    if (s.wg == 256 && s.v == 8 && s.r == 4) return launch2<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
-    if (s.wg == 512 && s.v == 8 && s.r == 2) return launch2<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
-    return RSAPRNG_E_ARG;
-  }
-  if (s.prefix == kPrefixSerial) {
+  if constexpr (MODE == kModeBattery) {  // the battery needs a work-group per chain
+    if (s.prefix != kPrefixSerial) return RSAPRNG_E_ARG;
     if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
     if (s.wg == 256 && s.v == 8 && s.r == 4) return launch3<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
     if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
     return RSAPRNG_E_ARG;
+  } else {
+    if (s.prefix == kPrefixTwoPass) {
+      if (s.wg == 256 && s.v == 8 && s.r == 1) return launch2<256, 8, 1, VAR, MODE>(a, s.grid, stream, occ);
+      if (s.wg == 256 && s.v == 8 && s.r == 2) return launch2<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+      if (s.wg == 256 && s.v == 8 && s.r == 4) return launch2<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
+      if (s.wg == 512 && s.v == 8 && s.r == 2) return launch2<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+      return RSAPRNG_E_ARG;
+    }
+    if (s.prefix == kPrefixSerial) {
+      if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+      if (s.wg == 256 && s.v == 8 && s.r == 4) return launch3<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
+      if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+      return RSAPRNG_E_ARG;
+    }
+    if (s.r != 1) return RSAPRNG_E_ARG;
+    if (s.wg == 256 && s.v == 8) return launch1<256, 8, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 512 && s.v == 8) return launch1<512, 8, VAR, MODE>(a, s.grid, stream, occ);
+    if (s.wg == 256 && s.v == 16) return launch1<256, 16, VAR, MODE>(a, s.grid, stream, occ);
+    return RSAPRNG_E_ARG;
   }
-  if (s.r != 1) return RSAPRNG_E_ARG;
-  if (s.wg == 256 && s.v == 8) return launch1<256, 8, VAR, MODE>(a, s.grid, stream, occ);
-  if (s.wg == 512 && s.v == 8) return launch1<512, 8, VAR, MODE>(a, s.grid, stream, occ);
-  if (s.wg == 256 && s.v == 16) return launch1<256, 16, VAR, MODE>(a, s.grid, stream, occ);
-  return RSAPRNG_E_ARG;
 }
 
 }  // namespace rsaprng

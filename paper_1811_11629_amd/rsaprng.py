@@ -90,12 +90,12 @@ _lib = None
 
 _u64, _u32, _i32, _dbl, _sz, _vp = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_size_t, C.c_void_p
 BAT_TESTS = ("frequency", "serial2", "serial3", "serial4", "serial5", "serial6", "poker",
-             "max_of_32")
-BATTERY_BYTES = 16 + 4 * (4 * (1 << 20) + 2 * 1000000 + 8 + 1024)
+             "max_of_32", "collisions", "gaps")
+BATTERY_BYTES = 16 + 4 * (4 * (1 << 20) + 2 * 1000000 + 8 + 1024 + 256 + 128)
 
 
 class rsaprng_battery_result(C.Structure):
-    _fields_ = [("chi2", _dbl * 8), ("dof", _dbl * 8), ("p", _dbl * 8), ("samples", _u64 * 8)]
+    _fields_ = [("chi2", _dbl * 10), ("dof", _dbl * 10), ("p", _dbl * 10), ("samples", _u64 * 10)]
 
 
 _SIGS = {

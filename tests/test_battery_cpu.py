@@ -76,3 +76,70 @@ def test_oracle_battery_matches_definition():
     assert {int(i): int(v) for i, v in enumerate(got["serial2"]) if v} == s2
     assert np.array_equal(got["poker"], poker)
     assert {int(i): int(v) for i, v in enumerate(got["maxt"]) if v} == maxt
+
+
+def test_oracle_collisions_and_gaps_match_definition():
+    inst = inputs.config1()
+    k0, count = (1 << 14) * 3 - 777, (1 << 14) * 3 + 1000   # three whole trials, ragged ends
+    _, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, count)
+    got = oracle.battery([(inst, k0, count)])
+    last = k0 + count - 1
+    coll = np.zeros(256, dtype=int)
+    for kt in range((k0 + (1 << 14) - 1) >> 14 << 14, last - (1 << 14) + 2, 1 << 14):
+        urns = {_bin(v, 1 << 20) for v in r[kt - k0:kt - k0 + (1 << 14)]}
+        coll[min((1 << 14) - len(urns), 255)] += 1
+    assert coll.sum() == 3 and np.array_equal(got["coll"], coll)
+    runs = np.zeros(128, dtype=int)
+    for k64 in range((k0 + 63) // 64 * 64, last - 62, 64):
+        bits = [v > 0.5 for v in r[k64 - k0:k64 - k0 + 64]]
+        n = 1
+        while n < 64 and bits[n] == bits[0]:
+            n += 1
+        runs[int(bits[0]) * 64 + n - 1] += 1
+    assert np.array_equal(got["runs"], runs)
+
+
+def _collision_distribution(n=1 << 14, m=1 << 20, cmax=600):
+    # distribution of the number of collisions, one ball at a time (numpy, float64)
+    b = np.zeros(cmax + 2)
+    b[0] = 1.0
+    for t in range(n):
+        c = np.arange(cmax + 1)
+        stay = b[:cmax + 1] * (1.0 - np.maximum(t - c, 0) / m)
+        move = np.zeros(cmax + 1)
+        move[1:] = b[:cmax] * ((t - c[:-1]) / m).clip(min=0)
+        b[:cmax + 1] = stay + move
+    return b[:cmax + 1]
+
+
+def test_collision_distribution_and_report(R):
+    dist = _collision_distribution()
+    n, m = 1 << 14, 1 << 20
+    # closed form of the mean: n - m (1 - (1 - 1/m)^n)
+    mean_exact = n - m * (1.0 - (1.0 - 1.0 / m) ** n)
+    assert abs(dist.sum() - 1.0) < 1e-12
+    assert abs((dist * np.arange(dist.size)).sum() - mean_exact) < 1e-6
+    # a record whose collision counts follow the distribution closely: p far from 0
+    rec = np.zeros(R.BATTERY_BYTES, dtype=np.uint8)
+    offs, off = {}, 0
+    for name, k, t in oracle.BATTERY_FIELDS:
+        offs[name] = (off, k, t)
+        off += k * np.dtype(t).itemsize
+    view = {name: rec[o:o + k * np.dtype(t).itemsize].view(t) for name, (o, k, t) in offs.items()}
+    trials = 1 << 20
+    expect = np.concatenate([dist[:255], [dist[255:].sum()]]) * trials
+    view["coll"][:] = np.rint(expect).astype(np.uint32)
+    out = R.battery_report(rec.tobytes())
+    assert out["collisions"]["samples"] == int(view["coll"].sum())
+    assert out["collisions"]["p"] > 0.99 and out["collisions"]["dof"] > 20
+    # shifting every count by one class is detected
+    view["coll"][:] = np.rint(np.concatenate([[0], expect[:-1]])).astype(np.uint32)
+    assert R.battery_report(rec.tobytes())["collisions"]["p"] < 1e-6
+    # gaps: counts at their expectations give p near 1; too many short runs do not
+    view["coll"][:] = 0
+    g = np.array([2.0 ** -(L + 1) if L < 64 else 2.0 ** -64 for L in range(1, 65)]) * (1 << 24)
+    view["runs"][:64] = np.rint(g).astype(np.uint32)
+    view["runs"][64:] = np.rint(g).astype(np.uint32)
+    assert R.battery_report(rec.tobytes())["gaps"]["p"] > 0.99
+    view["runs"][0] += 100000
+    assert R.battery_report(rec.tobytes())["gaps"]["p"] < 1e-6
