@@ -90,7 +90,10 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   if (lane == 0) a.s_tile[t] = s_tile;
 }
 
-// One wave per chain: excl[chunk] = message before the wave chunk.
+// One wave per chain: excl[chunk] = message before the wave chunk.  Lane t
+// takes tile t of a group of 64: the tile total from its chunk sums, a wave
+// scan of the totals, then the tile's chunks in order from the message before
+// the tile (the serial part is one scan per 64 tiles, not per 64 chunks).
 __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const int lane = threadIdx.x & 63;
   const u32 c = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -98,14 +101,24 @@ __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const Chain C = a.chain[c];
   const u64 n = a.inst[C.inst].n;
   const int nw_log2 = a.tile_log2 - a.chunk_log2;
-  const u64 first = (u64)C.first << nw_log2;
-  const u64 cnt = (u64)C.ntiles << nw_log2;
+  const int CH = 1 << nw_log2;  // chunks per tile
   u64 E = a.cstart[c].m_base;
-  for (u64 base = 0; base < cnt; base += 64) {
-    const u64 i = base + lane;
-    const u64 v = i < cnt ? a.agg[first + i] : 0;
-    const u64 incl = wave_scan_mod(v, n);
-    if (i < cnt) a.excl[first + i] = addmod(E, submod(incl, v, n), n);
+  for (u64 base = 0; base < C.ntiles; base += 64) {
+    const u64 t = base + lane;
+    const bool live = t < C.ntiles;
+    const u64 q0 = ((u64)C.first + t) << nw_log2;  // first chunk of tile t
+    u64 tot = 0;
+    if (live)
+      for (int j = 0; j < CH; ++j) tot = addmod(tot, a.agg[q0 + j], n);
+    const u64 incl = wave_scan_mod(tot, n);
+    if (live) {
+      u64 x = addmod(E, submod(incl, tot, n), n);  // message before tile t
+      for (int j = 0; j < CH; ++j) {
+        const u64 v = a.agg[q0 + j];
+        a.excl[q0 + j] = x;
+        x = addmod(x, v, n);
+      }
+    }
     E = addmod(E, lane_value(incl, 63), n);
   }
 }
