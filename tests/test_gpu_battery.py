@@ -67,3 +67,26 @@ def test_battery_pvalues_in_band(R):
         assert v["samples"] > 0, name
         # the paper's criterion: no p-value below 1e-6 or above 1 - 1e-6
         assert 1e-6 < v["p"] < 1 - 1e-6, (name, v)
+
+
+def test_battery_persistent_many_chains(R):
+    # more chains than resident work-groups (one per CU with the urn bitmap), so
+    # work-groups walk several chains and must leave LDS clean between them
+    insts = inputs.config3(6)
+    ranges = [(j % 6, (j * 37 % 64) * (1 << 15) + (j % 3) * 5, (1 << 15) + 77 * (j % 4))
+              for j in range(320)]
+    ref = oracle.battery([(insts[j], k0, cnt) for j, k0, cnt in ranges])
+    pool = R.Pool.from_instances(insts)
+    rec = R.battery_tensor()
+    for persistent in (1, 0):
+        log("battery persistent", persistent, len(ranges))
+        cfg = R.config(variant=2, prefix=2, lanes_per_tile=256, chunks_per_wave=2,
+                       persistent=persistent)
+        R.rsaprng_pool_battery(pool, [(j, k0, cnt, 0) for j, k0, cnt in ranges], rec, cfg=cfg)
+        R.rsaprng_check_device_error()
+        got = _decode(rec)
+        assert int(got["coll"].sum()) > 0 and int(got["runs"].sum()) > 0
+        for name in ref:
+            if name == "reserved":
+                continue
+            assert np.array_equal(got[name], ref[name]), (persistent, name)
