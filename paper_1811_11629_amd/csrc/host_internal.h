@@ -5,10 +5,9 @@
 #include <vector>
 
 #include "common.h"
+#include "plan.h"
 
 namespace rsaprng {
-
-typedef unsigned long long u64h;
 
 void set_last_error(int e);
 bool h_is_prime(u64h n);
@@ -52,16 +51,6 @@ struct Scratch {
   int mark(int slot, void* stream);
 };
 int scratch_for_stream(void* stream, Scratch** out);
-
-// A request before planning.
-struct PlanIn {
-  uint32_t inst;
-  uint32_t e;
-  u64h k0, count, out_off;
-  u64h S;          // continuation scan start (flags & kReqContinue)
-  uint32_t slot;
-  uint32_t flags;
-};
 
 rsaprng_config resolve_config(const rsaprng_config* cfg);
 u64h tile_size(const rsaprng_config& c);

@@ -9,7 +9,8 @@
 #include <map>
 #include <vector>
 
-#include "host_internal.h"
+#include "common.h"
+#include "plan.h"
 
 namespace rsaprng {
 

@@ -19,6 +19,7 @@
 #include <thread>
 #include <unordered_map>
 
+#include "host_internal.h"
 #include "scheduler.h"
 
 using namespace rsaprng;
