@@ -407,6 +407,21 @@ def run_battery(R, torch, stream, steps):
            "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep.values())}
     log("battery: %.1f Gnum/s (%.2f ms); p-values %s" % (
         res["gnumbers_per_s"], t_best * 1e3, " ".join("%s=%.3f" % (k, v["p"]) for k, v in rep.items())))
+    # the same instances over four 2^20 blocks each: 2^34 outputs across three
+    # re-seedings per instance, which must leave no trace in any test
+    reqs4 = [(i, 0, 1 << 22, 0) for i in range(len(insts))]
+    t0 = time.perf_counter()
+    R.rsaprng_pool_battery(pool, reqs4, rec, cfg=best, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    R.rsaprng_check_device_error(stream)
+    rep4 = R.battery_report(rec)
+    res["across_reseeding"] = {
+        "workload": "the same 4096 instances, k in [0, 2^22) (four blocks each): 2^34 outputs",
+        "seconds": dt, "tests": rep4,
+        "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep4.values())}
+    log("battery over 2^34 outputs (3 re-seedings per instance, %.2f s): p-values %s" % (
+        dt, " ".join("%s=%.3f" % (k, v["p"]) for k, v in rep4.items())))
     del rec, pool
     torch.cuda.empty_cache()
     return res
