@@ -490,6 +490,17 @@ def run_vector(R, torch, stream, steps):
                 float(r[int(f)].item()) == float(rj[0])
         res["mv_%d" % mv] = {"gnumbers_per_s": N / dt / 1e9, "ms": dt * 1e3, "verified_samples": ok}
         log("vector mode M_v=%d: %.1f Gnum/s (%.2f ms), samples %s" % (mv, N / dt / 1e9, dt * 1e3, ok))
+        if mv == 64:
+            # the battery over the flattened output: 64 substreams seen interleaved
+            rec = R.battery_tensor()
+            R.rsaprng_battery_values(r, rec, stream=stream)
+            rep = R.battery_report(rec)
+            res["interstream_battery_mv_64"] = {
+                "values": N, "tests": rep,
+                "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep.values())}
+            log("battery of the M_v=64 interleaved output: p-values %s" % " ".join(
+                "%s=%.3f" % (k, v["p"]) for k, v in rep.items()))
+            del rec
     R.rsaprng_check_device_error(stream)
     del c, r
     torch.cuda.empty_cache()

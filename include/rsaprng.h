@@ -375,6 +375,14 @@ typedef struct {
 int rsaprng_pool_battery(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
                          rsaprng_battery* rec_dev, const rsaprng_config* cfg, void* stream);
 
+/* The same battery over values already in device memory: r_dev[j] stands at
+ * index j (the groups are aligned to j), j < count, for instance the flattened
+ * output of rsaprng_generate_vector, where the tests then see the substreams
+ * interleaved (interstream correlations, Tests section).  Zeroes *rec_dev
+ * first; enqueued on `stream`.  r_dev must be 8-byte aligned. */
+int rsaprng_battery_values(const double* r_dev, uint64_t count, rsaprng_battery* rec_dev,
+                           void* stream);
+
 /* Chi-squared statistic, degrees of freedom and p-value (the upper tail
  * P(X >= chi2) of the chi-squared distribution) of each test, in the order of
  * RSAPRNG_BAT_TESTS, from a HOST copy of a record: uniform expectations for the

@@ -79,6 +79,7 @@ def lib():
                 "oracle_stats_of": (None, [PD, u64, C.POINTER(Stats)]),
                 "oracle_count_primes": (u64, [u64, u64, i32]),
                 "oracle_battery_add": (i32, [u64] * 7 + [C.c_void_p]),
+                "oracle_battery_values": (i32, [PD, u64, u64, C.c_void_p]),
                 "oracle_next_prime": (u64, [u64, i32, C.c_void_p, i32]),
             }
             for name, (res, args) in sig.items():
@@ -232,6 +233,16 @@ def battery_decode(buf):
         out[name] = raw[off:off + size].view(t).copy()
         off += size
     return out
+
+
+def battery_values(r, k0=0):
+    """Battery counts of the given values, standing at indices k0 .. k0 + len(r) - 1."""
+    r = np.ascontiguousarray(r, dtype=np.float64)
+    buf = np.zeros(BATTERY_BYTES, dtype=np.uint8)
+    rc = lib().oracle_battery_values(_pd(r), k0, r.size, buf.ctypes.data)
+    if rc:
+        raise ValueError("oracle_battery_values: %d" % rc)
+    return battery_decode(buf.tobytes())
 
 
 def battery(ranges):

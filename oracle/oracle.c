@@ -383,10 +383,13 @@ int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t
   double* r = (double*)malloc(count * sizeof(double));
   if (!r) return -9;
   int rc = oracle_generate(p, q, e, m0, s0, k0, count, NULL, r);
-  if (rc) {
-    free(r);
-    return rc;
-  }
+  if (rc == 0) rc = oracle_battery_values(r, k0, count, B);
+  free(r);
+  return rc;
+}
+
+int oracle_battery_values(const double* r, uint64_t k0, uint64_t count, oracle_battery* B) {
+  if (count == 0) return 0;
   const uint64_t last = k0 + (count - 1);
   for (uint64_t i = 0; i < count; ++i) B->freq[bin_of(r[i], 1048576.0, 1u << 20)]++;
   B->outputs += count;
@@ -446,10 +449,7 @@ int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t
   uint64_t kt = (k0 + T - 1) / T * T;
   if (kt >= k0 && kt <= last && last - kt >= T - 1) {
     uint32_t* urn = (uint32_t*)calloc(1u << 15, sizeof(uint32_t));
-    if (!urn) {
-      free(r);
-      return -9;
-    }
+    if (!urn) return -9;
     for (; kt >= k0 && kt <= last && last - kt >= T - 1; kt += T) {
       uint32_t distinct = 0;
       for (uint64_t j = 0; j < T; ++j) {
@@ -469,6 +469,5 @@ int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t
     }
     free(urn);
   }
-  free(r);
   return 0;
 }

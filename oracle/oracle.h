@@ -137,6 +137,9 @@ typedef struct {
 } oracle_battery;
 int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
                        uint64_t count, oracle_battery* b);
+/* The same counts over given values r[0 .. count) standing at absolute indices
+ * k0 .. k0 + count - 1 (the groups are aligned to those indices); ACCUMULATES. */
+int oracle_battery_values(const double* r, uint64_t k0, uint64_t count, oracle_battery* b);
 
 #ifdef __cplusplus
 }

@@ -154,6 +154,7 @@ int launch_sums(const LaunchArgs& args, void* stream);
 int launch_scan(const LaunchArgs& args, void* stream);
 int launch_tiles(const KernelShape& shape, const LaunchArgs& args, void* stream);
 int launch_battery_zero(rsaprng_battery* rec, uint64_t outputs, void* stream);
+int launch_battery_values(const LaunchArgs& args, const double* r, uint64_t count, void* stream);
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_stats_finalize(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t* m, uint64_t* c,

@@ -1103,6 +1103,20 @@ int rsaprng_pool_battery(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
                      rec_dev);
 }
 
+int rsaprng_battery_values(const double* r_dev, uint64_t count, rsaprng_battery* rec_dev,
+                           void* stream) {
+  if (!rec_dev || (count && !r_dev)) return RSAPRNG_E_NULL;
+  if (misaligned(r_dev) || misaligned(rec_dev)) return RSAPRNG_E_ALIGN;
+  Device* d;
+  int rc;
+  if ((rc = device_get(&d))) return rc;
+  if ((rc = launch_battery_zero(rec_dev, count, stream))) return rc;
+  LaunchArgs a;
+  std::memset(&a, 0, sizeof(a));
+  a.battery = rec_dev;
+  return launch_battery_values(a, r_dev, count, stream);
+}
+
 // Upper tail of the chi-squared distribution: the regularised upper incomplete
 // gamma function Q(k/2, x/2), by its power series for P below a + 1 and by the
 // continued fraction for Q above (evaluated with the modified Lentz method).

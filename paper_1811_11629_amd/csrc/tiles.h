@@ -331,31 +331,28 @@ __device__ __forceinline__ void bat_add(u32* p) {
 template <int WG, int MODE>
 struct TileShared;
 
-template <int WG, int V, int VAR, u32 E, class Msg>
-__device__ __forceinline__ void battery_outputs(const LaunchArgs& a,
-                                                TileShared<WG, kModeBattery>& sh, const Chain& C,
-                                                const rsaprng_params& P, Msg msg, u64 laneStart) {
-  static_assert(V == 8, "a lane holds one block of 8; 8 lanes hold a block of 64");
+// Counts of one lane's 8 consecutive values r[0..8), standing at absolute
+// indices laneStart .. laneStart + 7, of which [k0, last] are requested; the 64
+// lanes of the wave hold 512 consecutive indices (a chunk, aligned to 512).
+template <int WG>
+__device__ __forceinline__ void battery_count(const LaunchArgs& a, TileShared<WG, kModeBattery>& sh,
+                                              u64 k0, u64 last, const double (&r)[8],
+                                              u64 laneStart) {
   rsaprng_battery* const B = a.battery;
   const int lane = threadIdx.x & 63;
-  // the chunk of 64 V indices lies inside one collision trial
+  // the chunk lies inside one collision trial
   const u64 kt = laneStart >> kTrialLog2 << kTrialLog2;
-  const bool trial = kt >= C.k0 && kt <= C.last && C.last - kt >= (1ull << kTrialLog2) - 1;
-  double rv[V];
+  const bool trial = kt >= k0 && kt <= last && last - kt >= (1ull << kTrialLog2) - 1;
 #pragma unroll
-  for (int i = 0; i < V; ++i) {
-    double cd;
-    (void)msg.template enc<VAR, E>(i, P, cd);
-    rv[i] = ratio(cd, P.nd, P.nrcp);
+  for (int i = 0; i < 8; ++i) {
     const u64 k = laneStart + i;
-    const u32 u = bin_of(rv[i], 1048576.0, 1u << 20);
-    if (k >= C.k0 && k <= C.last) bat_add(&B->freq[u]);
+    const u32 u = bin_of(r[i], 1048576.0, 1u << 20);
+    if (k >= k0 && k <= last) bat_add(&B->freq[u]);
     if (trial)
       __hip_atomic_fetch_or(&sh.urn[u >> 5], 1u << (u & 31), __ATOMIC_RELAXED,
                             __HIP_MEMORY_SCOPE_WORKGROUP);
   }
-  const double* r = rv;
-  const bool full = laneStart >= C.k0 && laneStart <= C.last && C.last - laneStart >= 7;
+  const bool full = laneStart >= k0 && laneStart <= last && last - laneStart >= 7;
   double mx = 0.0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) mx = r[i] > mx ? r[i] : mx;
@@ -419,8 +416,23 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a,
   const u32 m = fullm == 0xffu ? 8u : (u32)__builtin_ctz(~fullm);
   const u32 tm = (u32)__shfl((int)t, g0 + (m < 8u ? (int)m : 7), 64);
   const u64 k64 = laneStart - (u64)(lane & 7) * 8;
-  const bool blk64 = k64 >= C.k0 && k64 <= C.last && C.last - k64 >= 63;
+  const bool blk64 = k64 >= k0 && k64 <= last && last - k64 >= 63;
   if ((lane & 7) == 0 && blk64) atomicAdd(&sh.bh[kBatRuns + b0 * 64 + (m < 8u ? 8u * m + tm : 64u) - 1], 1u);
+}
+
+template <int WG, int V, int VAR, u32 E, class Msg>
+__device__ __forceinline__ void battery_outputs(const LaunchArgs& a,
+                                                TileShared<WG, kModeBattery>& sh, const Chain& C,
+                                                const rsaprng_params& P, Msg msg, u64 laneStart) {
+  static_assert(V == 8, "a lane holds one block of 8; 8 lanes hold a block of 64");
+  double rv[8];
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    double cd;
+    (void)msg.template enc<VAR, E>(i, P, cd);
+    rv[i] = ratio(cd, P.nd, P.nrcp);
+  }
+  battery_count<WG>(a, sh, C.k0, C.last, rv, laneStart);
 }
 
 template <int WG, int MODE>

@@ -139,6 +139,7 @@ _SIGS = {
     "rsaprng_pool_battery": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp,
                                      C.POINTER(rsaprng_config), _vp]),
     "rsaprng_battery_report": (_i32, [_vp, C.POINTER(rsaprng_battery_result)]),
+    "rsaprng_battery_values": (_i32, [_vp, _u64, _vp, _vp]),
     "rsaprng_chi2_sf": (_dbl, [_dbl, _dbl]),
     "rsaprng_prime_count": (_i32, [_u64, _u64, _i32, C.POINTER(_u64), _vp]),
     "rsaprng_next_primes": (_i32, [_vp, _u64, _i32, _vp, _i32, _vp, _vp]),
@@ -476,6 +477,13 @@ def rsaprng_pool_battery(pool: "Pool", reqs, rec, cfg=None, stream=None) -> None
     _check(lib().rsaprng_pool_battery(pool.h, arr, len(arr), _ptr(rec),
                                       C.byref(cfg) if cfg is not None else None, _stream(stream)),
            "rsaprng_pool_battery")
+
+
+def rsaprng_battery_values(r, rec, count=None, stream=None) -> None:
+    """The battery over a device array of values (r[j] at index j)."""
+    n = r.numel() if count is None else count
+    _check(lib().rsaprng_battery_values(_ptr(r), n, _ptr(rec), _stream(stream)),
+           "rsaprng_battery_values")
 
 
 def battery_report(rec) -> dict:

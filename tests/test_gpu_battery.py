@@ -90,3 +90,41 @@ def test_battery_persistent_many_chains(R):
             if name == "reserved":
                 continue
             assert np.array_equal(got[name], ref[name]), (persistent, name)
+
+
+def test_battery_of_stored_values(R):
+    import torch
+    inst = inputs.config3(1)[0]
+    # a generated range from index 0: the stored values' battery equals the fused one
+    n = 5 * (1 << 14) + 1234
+    pool = R.Pool.from_instances([inst])
+    c = torch.empty(n, dtype=torch.int64, device="cuda")
+    r = torch.empty(n, dtype=torch.float64, device="cuda")
+    R.rsaprng_pool_generate(pool, [(0, 0, n, 0)], c, r)
+    rec_v, rec_f = R.battery_tensor(), R.battery_tensor()
+    log("battery of stored values", n)
+    R.rsaprng_battery_values(r, rec_v)
+    R.rsaprng_pool_battery(pool, [(0, 0, n, 0)], rec_f)
+    R.rsaprng_check_device_error()
+    got_v, got_f = _decode(rec_v), _decode(rec_f)
+    ref = oracle.battery_values(r.cpu().numpy())
+    for name in ref:
+        if name == "reserved":
+            continue
+        assert np.array_equal(got_v[name], ref[name]), name
+        assert np.array_equal(got_f[name], ref[name]), name
+    # the flattened vector-mode output: substreams seen interleaved
+    g = R.rsaprng_create_ex(inst.p, inst.q, inst.e, inst.m0, 1)
+    m = 3 * (1 << 14) + 999
+    rv = torch.empty(m, dtype=torch.float64, device="cuda")
+    R.rsaprng_generate_vector(g, 64, 12345, m, None, rv)
+    log("battery of vector-mode values", m)
+    R.rsaprng_battery_values(rv, rec_v)
+    R.rsaprng_check_device_error()
+    got = _decode(rec_v)
+    ref = oracle.battery_values(rv.cpu().numpy())
+    for name in ref:
+        if name == "reserved":
+            continue
+        assert np.array_equal(got[name], ref[name]), name
+    assert int(got["coll"].sum()) == 3 and int(got["outputs"][0]) == m
