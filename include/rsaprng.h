@@ -89,7 +89,16 @@ typedef struct {
   double nrcp;       /* RN(1 / RN(n)) */
   uint32_t ep, eq;   /* exponents applied mod p and mod q: both e for an ordinary
                         instance; see rsaprng_pool_create_dual (e is then 0) */
-} rsaprng_params;    /* 128 bytes; the device-side instance record */
+  /* Split forms of the CRT variant's constants.  For K = 2^32 mod p:
+   * kp_hi = K - (K mod 2^17), kp_lo = K mod 2^17, kp_quo = RN(K RN(1/p)); the
+   * kernels reduce H K mod p for integers |H| < 2^35 as
+   * fma(H, kp_lo, fma(-rint(H kp_quo), p, H kp_hi)), every step exact.  The same
+   * for 2^32 mod q (kq_*) and for Garner's q^-1 mod p (gp_*). */
+  double kp_lo, kp_hi, kp_quo;
+  double kq_lo, kq_hi, kq_quo;
+  double gp_lo, gp_hi, gp_quo;
+  double nrcp_lo;    /* RN(RN(1 - nd nrcp) nrcp): nrcp + nrcp_lo = 1/nd to ~2^-105 */
+} rsaprng_params;    /* 208 bytes; the device-side instance record */
 
 int rsaprng_params_init(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
                         rsaprng_params* out);

@@ -32,11 +32,13 @@ __device__ __forceinline__ u64 reduce_q_small(u64 r) {
 
 // One skip step s -> a s mod Q (eq. congruentialgenerator1).  a < 2^32 and
 // s < 2^63, so a s < 2^95 = t1 2^32 + lo32(t0); splitting it as H 2^63 + L gives
-// a s = 25 H + L (mod Q) with H < 2^32.  Three full-rate v_mad_u64_u32.
+// a s = 25 H + L (mod Q) with H < 2^32.  Three full-rate v_mad_u64_u32.  H is
+// taken with an explicit funnel shift (bits 31..62 of t1): written as a shift
+// and a truncation, the compiler widened it and added a zero term.
 __device__ __forceinline__ u64 lcg_next(u64 s) {
   u64 t0 = (u64)(u32)kA * lo32(s);
   u64 t1 = mad32((u32)kA, hi32(s), hi32(t0));  // < 2^63: hi32(s) < 2^31
-  u32 H = (u32)(t1 >> 31);
+  const u32 H = __builtin_amdgcn_alignbit(hi32(t1), lo32(t1), 31);
   u64 L = ((t1 & 0x7fffffffull) << 32) | lo32(t0);
   return reduce_q_small(mad32(H, 25u, L));     // < 2^63 + 2^37
 }
@@ -148,24 +150,36 @@ __device__ __forceinline__ double fmm(double x, double y, double P, double Pinv)
   return __fma_rn(-qt, P, h) + l;
 }
 
+// H K mod P up to a multiple of P, in (-P, P), for an integer-valued |H| < 2^35
+// and a constant 0 <= K < P < 2^32 given split as K = hi + lo (hi a multiple of
+// 2^17, lo < 2^17) with quo = RN(K RN(1/P)):
+//   H hi and H lo are exact (below 2^50 and 2^52);
+//   H quo is within 2^-16 of H K / P (|H K / P| < 2^35, three roundings of
+//   relative size 2^-53), so qt = rint(H quo) is within 1/2 + 2^-16 of it and
+//   r = H K - qt P lies in (-P, P);
+//   fma(-qt, P, H hi) = r - H lo is an integer below 2^53 in magnitude (exact),
+//   and the last fma adds H lo back exactly.
+// Five operations, against six for the product split of fmm.
+__device__ __forceinline__ double fold_split(double H, double P, double lo, double hi,
+                                             double quo) {
+  const double qt = __builtin_rint(H * quo);
+  return __fma_rn(H, lo, __fma_rn(-qt, P, H * hi));
+}
+
 // m mod P from m = mh 2^32 + ml: (mh (2^32 mod P) + ml) reduced, in (-P, P).
-__device__ __forceinline__ double residue(u64 m, double P, double Pinv, double K) {
-  double t = fmm((double)hi32(m), K, P, Pinv);
-  double t2 = t + (double)lo32(m);                // exact, |t2| < 2^33
+__device__ __forceinline__ double residue(u64 m, double P, double Pinv, double lo, double hi,
+                                          double quo) {
+  const double t2 = fold_split((double)hi32(m), P, lo, hi, quo) + (double)lo32(m);  // |t2| < 2^33
   double qt = __builtin_rint(t2 * Pinv);
   return __fma_rn(-qt, P, t2);
 }
 
-// m mod P without the final reduction: h + l = mh (2^32 mod P) exactly, and
-// h - rint(h/P) P + l + ml is an integer of magnitude below 2^33.  Valid as
-// the input of a squaring (|x|^2 < 2^66 keeps every fmm step exact: h < 2^67,
+// m mod P without the final reduction: an integer in (-P, P + 2^32).  Valid
+// as the input of a squaring (|x|^2 < 2^66 keeps every fmm step exact: h < 2^67,
 // |l| <= 2^14, |h - qt P| < P).
-__device__ __forceinline__ double residue_lazy(u64 m, double P, double Pinv, double K) {
-  const double mh = (double)hi32(m);
-  double h = mh * K;
-  double l = __fma_rn(mh, K, -h);
-  double qt = __builtin_rint(h * Pinv);
-  return (__fma_rn(-qt, P, h) + l) + (double)lo32(m);
+__device__ __forceinline__ double residue_lazy(u64 m, double P, double lo, double hi,
+                                               double quo) {
+  return fold_split((double)hi32(m), P, lo, hi, quo) + (double)lo32(m);
 }
 
 template <u32 E>
@@ -199,12 +213,14 @@ __device__ __forceinline__ double to_unsigned_residue(double x, double P, double
 }
 
 // Garner's recombination c = ((c_p - c_q) q^-1 mod p) q + c_q.  Returns the
-// integer c and RN(c) (one rounding of t q + c_q by the fma).
+// integer c and RN(c) (one rounding of t q + c_q by the fma).  q^-1 mod p is
+// given split (g_lo, g_hi, g_quo) as for fold_split; |d| < 2^33.
 __device__ __forceinline__ u64 garner(double cp, double cq, double pd, double qd, double pinv,
-                                      double qinv, double qinvp, u32 q, double& cd) {
+                                      double qinv, double g_lo, double g_hi, double g_quo, u32 q,
+                                      double& cd) {
   const double cqn = to_unsigned_residue(cq, qd, qinv);   // [0, q)
   const double d = cp - cqn;                              // exact, |d| < 2^33
-  const double t = to_unsigned_residue(fmm(d, qinvp, pd, pinv), pd, pinv);  // [0, p)
+  const double t = to_unsigned_residue(fold_split(d, pd, g_lo, g_hi, g_quo), pd, pinv);  // [0, p)
   cd = __fma_rn(t, qd, cqn);
   return mad32((u32)t, q, (u64)(u32)cqn);
 }
@@ -216,17 +232,17 @@ __device__ __forceinline__ double u64_to_f64_rn(u64 c) {
 }
 
 // r = RN(RN(c) / RN(n)) with the guard against 1.0 (eq. CodeFloatingPointStep).
-// The quotient uses y = RN(1/nd) and two corrections (Markstein):
-//   q0 = RN(cd y) lies within 1.5 ulp of cd/nd (y has relative error <= 2^-53);
-//   q1 = RN(q0 + RN(cd - q0 nd) y) lies within 1 ulp, so cd - q1 nd is exactly
-//   representable and the fma returns it exactly; with y within half an ulp of
-//   1/nd, q2 = RN(q1 + (cd - q1 nd) y) is the correctly rounded cd/nd
-//   (Markstein's theorem, IBM J. Res. Dev. 1990).  0 <= cd <= nd, no
-//   underflow or overflow is possible.
-__device__ __forceinline__ double ratio(double cd, double nd, double y) {
-  const double q0 = cd * y;
-  const double q1 = __fma_rn(__fma_rn(-q0, nd, cd), y, q0);
-  const double r = __fma_rn(__fma_rn(-q1, nd, cd), y, q1);
+// With y = RN(1/nd) and its low part yl (y + yl = 1/nd to about 2^-105
+// relative):
+//   q0 = RN(cd y + RN(cd yl)) lies within half an ulp of cd/nd plus a relative
+//   2^-103, so within one ulp;
+//   hence cd - q0 nd is exactly representable and the fma returns it exactly,
+//   and with y within half an ulp of 1/nd, q1 = RN(q0 + (cd - q0 nd) y) is the
+//   correctly rounded cd/nd (Markstein's theorem, IBM J. Res. Dev. 1990).
+// 0 <= cd <= nd: no underflow or overflow is possible.
+__device__ __forceinline__ double ratio(double cd, double nd, double y, double yl) {
+  const double q0 = __fma_rn(cd, y, cd * yl);
+  const double r = __fma_rn(__fma_rn(-q0, nd, cd), y, q0);
   // r <= 1; the guard replaces exactly 1.0 by the largest double below it
   return __builtin_fmin(r, 0x1.fffffffffffffp-1);
 }

@@ -102,6 +102,14 @@ u64h h_block_seed(u64h s0, u64h b) {
   return h_mulmod(h_mulmod(s0, h_gc(), kQh), (aN + kQh - 1) % kQh, kQh);
 }
 
+// A constant K < 2^32 as K = hi + lo, hi a multiple of 2^17 and lo < 2^17, with
+// the quotient factor RN(K pinv): the kernels' exact reduction of H K mod P.
+static void split_constant(u64h K, double pinv, double* lo, double* hi, double* quo) {
+  *lo = (double)(K & ((1ull << 17) - 1));
+  *hi = (double)(K - (K & ((1ull << 17) - 1)));
+  *quo = (double)K * pinv;
+}
+
 int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng_params* out) {
   if (check_range) {
     if (p < (1ull << 31) || p >= (1ull << 32) || q < (1ull << 31) || q >= (1ull << 32))
@@ -139,6 +147,10 @@ int h_params(u64h p, u64h q, u64h e, u64h m0, u64h s0, bool check_range, rsaprng
   P.kq = (double)((1ull << 32) % q);
   P.nrcp = 1.0 / P.nd;
   P.ep = P.eq = (uint32_t)e;
+  split_constant((1ull << 32) % p, P.pinv, &P.kp_lo, &P.kp_hi, &P.kp_quo);
+  split_constant((1ull << 32) % q, P.qinv, &P.kq_lo, &P.kq_hi, &P.kq_quo);
+  split_constant(h_inv_prime(q % p, p), P.pinv, &P.gp_lo, &P.gp_hi, &P.gp_quo);
+  P.nrcp_lo = std::fma(-P.nrcp, P.nd, 1.0) * P.nrcp;
   *out = P;
   return RSAPRNG_OK;
 }

@@ -214,7 +214,7 @@ __global__ void k_debug_encrypt(rsaprng_params P, const u64* m, u64* c, double* 
   double cd;
   u64 v = encrypt<VAR, 0>(m[i], P, cd);
   if (c) c[i] = v;
-  if (r) r[i] = ratio(cd, P.nd, P.nrcp);
+  if (r) r[i] = ratio_of(cd, P);
 }
 
 // ---------------------------------------------------------------------------

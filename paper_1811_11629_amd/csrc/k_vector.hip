@@ -164,7 +164,7 @@ __device__ __forceinline__ void vgen_lane(const VecArgs& a, const rsaprng_params
     double cd;
     const u64 c = encrypt<VAR, E>(m, P, cd);
     if (a.out_c) a.out_c[o] = c;
-    if (a.out_r) a.out_r[o] = ratio(cd, P.nd, P.nrcp);
+    if (a.out_r) a.out_r[o] = ratio_of(cd, P);
   }
 }
 

@@ -64,11 +64,19 @@ __device__ __forceinline__ T load_cst(const T* p) {
 }
 
 // 64-bit DPP move: lanes whose source is outside the row pattern (or whose row
-// is masked off) receive 0.
+// is masked off) receive 0.  With every row enabled the zero comes from the
+// bound control (an out-of-range source reads 0), so no zeroed destination
+// has to be prepared; masked-off rows keep the destination's old value, 0.
 template <int CTRL, int ROW_MASK>
 __device__ __forceinline__ u64 dpp64(u64 v) {
-  const u32 lo = (u32)__builtin_amdgcn_update_dpp(0, (int)lo32(v), CTRL, ROW_MASK, 0xf, false);
-  const u32 hi = (u32)__builtin_amdgcn_update_dpp(0, (int)hi32(v), CTRL, ROW_MASK, 0xf, false);
+  u32 lo, hi;
+  if constexpr (ROW_MASK == 0xf) {
+    lo = (u32)__builtin_amdgcn_mov_dpp((int)lo32(v), CTRL, 0xf, 0xf, true);
+    hi = (u32)__builtin_amdgcn_mov_dpp((int)hi32(v), CTRL, 0xf, 0xf, true);
+  } else {
+    lo = (u32)__builtin_amdgcn_update_dpp(0, (int)lo32(v), CTRL, ROW_MASK, 0xf, false);
+    hi = (u32)__builtin_amdgcn_update_dpp(0, (int)hi32(v), CTRL, ROW_MASK, 0xf, false);
+  }
   return ((u64)hi << 32) | lo;
 }
 
@@ -150,6 +158,23 @@ __device__ u64 look_back(const LaunchArgs& a, u32 t, u32 first, u32 tag, u64 n, 
 // ---------------------------------------------------------------------------
 // encryption of one message
 // ---------------------------------------------------------------------------
+// The instance's reductions mod p and mod q (devmath.h, fold_split and residue).
+__device__ __forceinline__ double fold_p(double H, const rsaprng_params& P) {
+  return fold_split(H, P.pd, P.kp_lo, P.kp_hi, P.kp_quo);
+}
+__device__ __forceinline__ double fold_q(double H, const rsaprng_params& P) {
+  return fold_split(H, P.qd, P.kq_lo, P.kq_hi, P.kq_quo);
+}
+__device__ __forceinline__ double res_p(u64 m, const rsaprng_params& P) {
+  return residue(m, P.pd, P.pinv, P.kp_lo, P.kp_hi, P.kp_quo);
+}
+__device__ __forceinline__ double res_q(u64 m, const rsaprng_params& P) {
+  return residue(m, P.qd, P.qinv, P.kq_lo, P.kq_hi, P.kq_quo);
+}
+__device__ __forceinline__ double ratio_of(double cd, const rsaprng_params& P) {
+  return ratio(cd, P.nd, P.nrcp, P.nrcp_lo);
+}
+
 // CRT form from the residues of m: m^E mod p and mod q, then Garner.  For
 // E >= 2 the residues may be unreduced (|x| < 2^42: the ladder opens with a
 // squaring), otherwise they must lie in (-P, P).
@@ -166,7 +191,7 @@ __device__ __forceinline__ u64 encrypt_res(double mp, double mq, const rsaprng_p
     cp = fp_pow_rt(mp, P.pd, P.pinv, P.ep);
     cq = fp_pow_rt(mq, P.qd, P.qinv, P.eq);
   }
-  return garner(cp, cq, P.pd, P.qd, P.pinv, P.qinv, P.qinvp, P.q, cd);
+  return garner(cp, cq, P.pd, P.qd, P.pinv, P.qinv, P.gp_lo, P.gp_hi, P.gp_quo, P.q, cd);
 }
 
 template <int VAR, u32 E>
@@ -182,11 +207,11 @@ __device__ __forceinline__ u64 encrypt(u64 m, const rsaprng_params& P, double& c
   } else {
     double mp, mq;
     if constexpr (E >= 2) {  // the ladder starts with a squaring
-      mp = residue_lazy(m, P.pd, P.pinv, P.kp);
-      mq = residue_lazy(m, P.qd, P.qinv, P.kq);
+      mp = residue_lazy(m, P.pd, P.kp_lo, P.kp_hi, P.kp_quo);
+      mq = residue_lazy(m, P.qd, P.kq_lo, P.kq_hi, P.kq_quo);
     } else {
-      mp = residue(m, P.pd, P.pinv, P.kp);
-      mq = residue(m, P.qd, P.qinv, P.kq);
+      mp = res_p(m, P);
+      mq = res_q(m, P);
     }
     return encrypt_res<E>(mp, mq, P, cd);
   }
@@ -230,32 +255,27 @@ __device__ __forceinline__ double reduce_res(double x, double P, double Pinv) {
   return __fma_rn(-__builtin_rint(x * Pinv), P, x);
 }
 
-// H 2^32 + L modulo P up to a multiple of P, for integer-valued H < 2^35 and
-// 0 <= L < 2^36: h + l = H (2^32 mod P) exactly, h - rint(h/P) P is exact and
-// below P in magnitude, so the result lies in (-P - 2^14, P + 2^14 + L).
-__device__ __forceinline__ double fold_hl(double H, double L, double P, double Pinv, double K) {
-  const double h = H * K;
-  const double l = __fma_rn(H, K, -h);
-  return (__fma_rn(-__builtin_rint(h * Pinv), P, h) + l) + L;
-}
-
 // Residue messages (CRT variant).  With the lane's skips s_0..s_{V-1} and the
-// residues bp, bq of the message before its first index, m_i is congruent to
-// b + S_i where S_i = s_0 + ... + s_i = H_i 2^32 + L_i, H_i and L_i the exact
-// sums of the skips' upper and lower halves (below 2^34 and 2^35 for V = 8).
-// Only m mod p and m mod q enter the encryption, so no 64-bit modular
-// addition is done; the residues handed to the ladder stay below 2^37.
+// residues bp, bq of the message before its first index (in (-p, p), (-q, q)),
+// m_i is congruent to b + S_i where S_i = s_0 + ... + s_i = H_i 2^32 + L_i, H_i
+// and L_i the exact sums of the skips' upper and lower halves (below 2^34 and
+// 2^35 for V = 8).  Only m mod p and m mod q enter the encryption, so no
+// 64-bit modular addition is done.  The running values Lp = bp + L_i and
+// Lq = bq + L_i are kept instead of L_i, so m_i mod p is fold_p(H_i) + Lp: an
+// integer below 2^36 in magnitude, a valid input of the ladder's squaring.
 template <int V>
 struct MsgRes {
   const u64 (&S)[V];
-  double bp, bq;
-  double H = 0.0, L = 0.0;
+  double Lp, Lq;  // bp, bq on entry
+  double H = 0.0;
   template <int VAR, u32 E>
   __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
     H += (double)hi32(S[i]);
-    L += (double)lo32(S[i]);
-    double mp = bp + fold_hl(H, L, P.pd, P.pinv, P.kp);
-    double mq = bq + fold_hl(H, L, P.qd, P.qinv, P.kq);
+    const double l = (double)lo32(S[i]);
+    Lp += l;
+    Lq += l;
+    double mp = fold_p(H, P) + Lp;
+    double mq = fold_q(H, P) + Lq;
     if constexpr (E < 2) {  // no opening squaring: Garner needs reduced residues
       mp = reduce_res(mp, P.pd, P.pinv);
       mq = reduce_res(mq, P.qd, P.qinv);
@@ -269,15 +289,17 @@ struct MsgRes {
 template <int V>
 struct MsgResWalk {
   u64 s;
-  double bp, bq;
-  double H = 0.0, L = 0.0;
+  double Lp, Lq;  // bp, bq on entry
+  double H = 0.0;
   template <int VAR, u32 E>
   __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
     if (i) s = lcg_next(s);
     H += (double)hi32(s);
-    L += (double)lo32(s);
-    double mp = bp + fold_hl(H, L, P.pd, P.pinv, P.kp);
-    double mq = bq + fold_hl(H, L, P.qd, P.qinv, P.kq);
+    const double l = (double)lo32(s);
+    Lp += l;
+    Lq += l;
+    double mp = fold_p(H, P) + Lp;
+    double mq = fold_q(H, P) + Lq;
     if constexpr (E < 2) {
       mp = reduce_res(mp, P.pd, P.pinv);
       mq = reduce_res(mq, P.qd, P.qinv);
@@ -430,7 +452,7 @@ __device__ __forceinline__ void battery_outputs(const LaunchArgs& a,
   for (int i = 0; i < 8; ++i) {
     double cd;
     (void)msg.template enc<VAR, E>(i, P, cd);
-    rv[i] = ratio(cd, P.nd, P.nrcp);
+    rv[i] = ratio_of(cd, P);
   }
   battery_count<WG>(a, sh, C.k0, C.last, rv, laneStart);
 }
@@ -476,7 +498,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
         double cd;
         const u64 c = msg.template enc<VAR, E>(i, P, cd);
         xc[lane * kXRow + i] = c;
-        xr[lane * kXRow + i] = (u64)__double_as_longlong(ratio(cd, P.nd, P.nrcp));
+        xr[lane * kXRow + i] = (u64)__double_as_longlong(ratio_of(cd, P));
       }
       const u64 chunk0 = C.out_off + (laneStart - (u64)lane * V - C.k0);
       const int src = (lane >> 3) * kXRow + (lane & 7);
@@ -505,7 +527,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
         if (oc) *reinterpret_cast<ulonglong2*>(oc + off0 + i) = make_ulonglong2(c0, c1);
         if (orr)
           *reinterpret_cast<double2*>(orr + off0 + i) =
-              make_double2(ratio(cd0, P.nd, P.nrcp), ratio(cd1, P.nd, P.nrcp));
+              make_double2(ratio_of(cd0, P), ratio_of(cd1, P));
       }
     } else {
 #pragma unroll
@@ -516,7 +538,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
         if (k >= C.k0 && k <= C.last) {
           const u64 off = C.out_off + (k - C.k0);
           if (oc) oc[off] = c;
-          if (orr) orr[off] = ratio(cd, P.nd, P.nrcp);
+          if (orr) orr[off] = ratio_of(cd, P);
         }
       }
     }
@@ -529,7 +551,7 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       const u64 k = laneStart + i;
       double cd;
       (void)msg.template enc<VAR, E>(i, P, cd);
-      const double r = ratio(cd, P.nd, P.nrcp);
+      const double r = ratio_of(cd, P);
       if (full || (k >= C.k0 && k <= C.last)) {
         u64 lo, hi;
         fixed128(r, lo, hi);
@@ -689,19 +711,28 @@ __device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H,
   L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
 }
 
-// The same sums without keeping the skips (steps that only walk).
+// The lane total of V skips without keeping them, as H 2^32 + L.  Two skips
+// (each below 2^63) add without overflow; the pair sums go into a 64-bit
+// accumulator with a carry count, so the total S = carry 2^64 + acc (below
+// V 2^63) gives H = carry 2^32 + hi32(acc) < 2^35 and L = lo32(acc) exactly.
 template <int V>
 __device__ __forceinline__ void walk_totals(u64 s_first, double& H, double& L) {
+  static_assert(V % 2 == 0 && V <= 16, "pairs of skips; H below 2^35");
   u64 s = s_first;
-  u64 h = 0, l = 0;
+  u64 acc = 0;
+  u32 carry = 0;
 #pragma unroll
-  for (int i = 0; i < V; ++i) {
+  for (int i = 0; i < V; i += 2) {
     if (i) s = lcg_next(s);
-    h += hi32(s);
-    l += lo32(s);
+    const u64 s1 = lcg_next(s);
+    const u64 pair = s + s1;
+    const u64 t = acc + pair;
+    carry += t < pair;
+    acc = t;
+    s = s1;
   }
-  H = __fma_rn((double)hi32(h), 4294967296.0, (double)lo32(h));
-  L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
+  H = __fma_rn((double)carry, 4294967296.0, (double)hi32(acc));
+  L = (double)lo32(acc);
 }
 
 // Inclusive scan over the wave of integer-valued doubles whose partial sums
@@ -779,11 +810,11 @@ __device__ __forceinline__ void chain_end_res(const LaunchArgs& a, const Chain& 
         s_last = s;
       }
     }
-    const double mp = reduce_res(bp + fold_hl(H, L, P.pd, P.pinv, P.kp), P.pd, P.pinv);
-    const double mq = reduce_res(bq + fold_hl(H, L, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+    const double mp = reduce_res(bp + (fold_p(H, P) + L), P.pd, P.pinv);
+    const double mq = reduce_res(bq + (fold_q(H, P) + L), P.qd, P.qinv);
     double cd;
     ChainState cs;
-    cs.m_prev = garner(mp, mq, P.pd, P.qd, P.pinv, P.qinv, P.qinvp, P.q, cd);
+    cs.m_prev = garner(mp, mq, P.pd, P.qd, P.pinv, P.qinv, P.gp_lo, P.gp_hi, P.gp_quo, P.q, cd);
     cs.s_at = lcg_next(s_last);
     a.state[C.slot] = cs;
   }
@@ -876,14 +907,14 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
         u64 S[V];
         double Ht, Lt;
         walk_halves<V>(s_first, S, Ht, Lt);
-        const double tp = reduce_res(fold_hl(Ht, Lt, P.pd, P.pinv, P.kp), P.pd, P.pinv);
-        const double tq = reduce_res(fold_hl(Ht, Lt, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+        const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
+        const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
         const double ip = wave_scan_f64(tp, lane);
         const double iq = wave_scan_f64(tq, lane);
         const double bp =
-            reduce_res(residue(E[r], P.pd, P.pinv, P.kp) + (ip - tp), P.pd, P.pinv);
+            reduce_res(res_p(E[r], P) + (ip - tp), P.pd, P.pinv);
         const double bq =
-            reduce_res(residue(E[r], P.qd, P.qinv, P.kq) + (iq - tq), P.qd, P.qinv);
+            reduce_res(res_q(E[r], P) + (iq - tq), P.qd, P.qinv);
         const MsgRes<V> msg{S, bp, bq};
         if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
         chain_end_res<V>(a, C, P, s_first, bp, bq, laneStart);
@@ -1016,8 +1047,8 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
     double cp = 0.0, cq = 0.0;  // CRT carry: residues of the message before the step
     u64 cm = 0;                 // Montgomery carry: the message before the step
     if constexpr (VAR == kVariantCrt) {
-      cp = residue(cs0.m_base, P.pd, P.pinv, P.kp);
-      cq = residue(cs0.m_base, P.qd, P.qinv, P.kq);
+      cp = res_p(cs0.m_base, P);
+      cq = res_q(cs0.m_base, P);
     } else {
       cm = cs0.m_base;
     }
@@ -1037,8 +1068,8 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
         for (int r = 0; r < R; ++r) {
           double Ht, Lt;
           walk_totals<V>(sf[r], Ht, Lt);
-          const double tp = reduce_res(fold_hl(Ht, Lt, P.pd, P.pinv, P.kp), P.pd, P.pinv);
-          const double tq = reduce_res(fold_hl(Ht, Lt, P.qd, P.qinv, P.kq), P.qd, P.qinv);
+          const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
+          const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
           const double ip = wave_scan_f64(tp, lane);
           const double iq = wave_scan_f64(tq, lane);
           ep[r] = wp + (ip - tp);
@@ -1052,10 +1083,11 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
           const double2 v = xch[par][w];
-          if (w < (int)wave) {
-            op += v.x;
-            oq += v.y;
-          }
+          // a wave-uniform 1 for the waves before this one: one fma instead of
+          // a select and an add (integers below 2^53, every step exact)
+          const double f = w < (int)wave ? 1.0 : 0.0;
+          op = __fma_rn(f, v.x, op);
+          oq = __fma_rn(f, v.y, oq);
           Tp += v.x;
           Tq += v.y;
         }

@@ -49,7 +49,11 @@ class rsaprng_params(C.Structure):
                 ("nd", C.c_double), ("pd", C.c_double), ("qd", C.c_double),
                 ("pinv", C.c_double), ("qinv", C.c_double), ("qinvp", C.c_double),
                 ("kp", C.c_double), ("kq", C.c_double), ("nrcp", C.c_double),
-                ("ep", C.c_uint32), ("eq", C.c_uint32)]
+                ("ep", C.c_uint32), ("eq", C.c_uint32),
+                ("kp_lo", C.c_double), ("kp_hi", C.c_double), ("kp_quo", C.c_double),
+                ("kq_lo", C.c_double), ("kq_hi", C.c_double), ("kq_quo", C.c_double),
+                ("gp_lo", C.c_double), ("gp_hi", C.c_double), ("gp_quo", C.c_double),
+                ("nrcp_lo", C.c_double)]
 
 
 class rsaprng_req(C.Structure):

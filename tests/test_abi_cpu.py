@@ -3,6 +3,7 @@ include/rsaprng.h, and its host-side logic (validation, per-instance constants,
 jumps) agrees with independent computations.  No kernel is launched."""
 import ctypes as C
 import math
+from fractions import Fraction
 import os
 import re
 
@@ -57,6 +58,15 @@ def test_params_constants(R):
         assert int(P.qinvp) == pow(i.q, -1, i.p)
         assert int(P.kp) == (1 << 32) % i.p and int(P.kq) == (1 << 32) % i.q
         assert P.nrcp == 1.0 / float(n)
+        # split constants: K = hi + lo, hi a multiple of 2^17, lo < 2^17, quo = RN(K RN(1/P))
+        for K, P_, lo, hi, quo in (((1 << 32) % i.p, i.p, P.kp_lo, P.kp_hi, P.kp_quo),
+                                   ((1 << 32) % i.q, i.q, P.kq_lo, P.kq_hi, P.kq_quo),
+                                   (pow(i.q, -1, i.p), i.p, P.gp_lo, P.gp_hi, P.gp_quo)):
+            assert int(lo) + int(hi) == K and int(hi) % (1 << 17) == 0 and 0 <= lo < (1 << 17)
+            assert quo == float(K) * (1.0 / P_)
+        # nrcp + nrcp_lo approximates 1/nd far beyond double precision
+        err = (Fraction(P.nrcp) + Fraction(P.nrcp_lo)) * Fraction(P.nd) - 1
+        assert abs(err) < Fraction(1, 1 << 100)
 
 
 def test_params_validation_codes(R):
