@@ -321,6 +321,9 @@ struct MsgExactWalk {
   }
 };
 
+// Two 64-bit words as one 16-byte vector (non-temporal stores of pairs).
+typedef u64 u64x2 __attribute__((ext_vector_type(2)));
+
 // Row stride (64-bit words) of a wave's transpose buffer: 8 values per lane
 // plus one word of padding against LDS bank conflicts.
 constexpr int kXRow = 9;
@@ -487,9 +490,11 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
     double* const orr = a.out_r;
     if constexpr (FAST && V == 8) {
       // Each lane's 8 results go to its row of the wave's LDS buffers (c and r)
-      // as they are produced; then store j writes elements 64 j + lane of the
-      // chunk, so every store instruction covers 512 contiguous bytes (full
-      // cache lines).  No result waits in registers.
+      // as they are produced; then store j writes elements 128 j + 2 lane and
+      // the next of the chunk (rows 16 j + lane / 4, columns 2 (lane % 4) and
+      // the next), so every 16-byte store instruction covers 1 KiB of
+      // contiguous output.  The stores are non-temporal: the outputs are not
+      // read again by this kernel.  No result waits in registers.
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
       u64* xc = sh.xbuf + wave * (2 * 64 * kXRow);
       u64* xr = xc + 64 * kXRow;
@@ -501,18 +506,22 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
         xr[lane * kXRow + i] = (u64)__double_as_longlong(ratio_of(cd, P));
       }
       const u64 chunk0 = C.out_off + (laneStart - (u64)lane * V - C.k0);
-      const int src = (lane >> 3) * kXRow + (lane & 7);
+      const int src = (lane >> 2) * kXRow + 2 * (lane & 3);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       if (oc) {
 #pragma unroll
-        for (int j = 0; j < V; ++j) oc[chunk0 + (u64)j * 64 + lane] = xc[j * 8 * kXRow + src];
+        for (int j = 0; j < V / 2; ++j)
+          __builtin_nontemporal_store(u64x2{xc[j * 16 * kXRow + src], xc[j * 16 * kXRow + src + 1]},
+                                      reinterpret_cast<u64x2*>(oc + chunk0 + (u64)j * 128 + 2 * lane));
       }
       if (orr) {
         u64* const dr = reinterpret_cast<u64*>(orr);
 #pragma unroll
-        for (int j = 0; j < V; ++j) dr[chunk0 + (u64)j * 64 + lane] = xr[j * 8 * kXRow + src];
+        for (int j = 0; j < V / 2; ++j)
+          __builtin_nontemporal_store(u64x2{xr[j * 16 * kXRow + src], xr[j * 16 * kXRow + src + 1]},
+                                      reinterpret_cast<u64x2*>(dr + chunk0 + (u64)j * 128 + 2 * lane));
       }
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
@@ -1080,12 +1089,16 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
         if (lane == 63) xch[par][wave] = make_double2(wp, wq);
         __syncthreads();
         double op = 0.0, oq = 0.0, Tp = 0.0, Tq = 0.0;
+        // the wave index re-read each step: otherwise the NW factors below are
+        // hoisted out of the chain loop and held in scalar registers
+        u32 wv = wave;
+        asm volatile("" : "+s"(wv));
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
           const double2 v = xch[par][w];
           // a wave-uniform 1 for the waves before this one: one fma instead of
           // a select and an add (integers below 2^53, every step exact)
-          const double f = w < (int)wave ? 1.0 : 0.0;
+          const double f = w < (int)wv ? 1.0 : 0.0;
           op = __fma_rn(f, v.x, op);
           oq = __fma_rn(f, v.y, oq);
           Tp += v.x;
