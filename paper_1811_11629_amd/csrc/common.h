@@ -147,6 +147,7 @@ struct KernelShape {
   int prefix;    // kPrefixTwoPass, kPrefixLookback or kPrefixSerial
   int r;         // two passes: consecutive wave chunks per wave (tile = wg v r)
   int grid;      // number of work-groups (they loop if fewer than tiles)
+  uint32_t e;    // the exponent of every instance of the launch, or 0 if they differ
 };
 int launch_begin(DevCtl* ctl, void* stream);
 int launch_chain_setup(const LaunchArgs& args, void* stream);

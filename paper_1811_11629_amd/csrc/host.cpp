@@ -565,11 +565,18 @@ static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c
 // Enqueue one launch: chain setup, then either [sums, scan, generate] (two
 // passes) or [queue reset, single-pass generate]; consume mode adds the zero
 // and finalize kernels around it.  `inst` and `chains` are device pointers.
+uint32_t shared_exponent(const PlanIn* in, size_t n) {
+  if (n == 0) return 0;
+  for (size_t i = 1; i < n; ++i)
+    if (in[i].e != in[0].e) return 0;
+  return in[0].e;
+}
+
 int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks,
-                   rsaprng_battery* battery) {
+                   rsaprng_battery* battery, uint32_t shared_e) {
   int rc;
   auto mark = [&](int i) {
     return !marks || hipEventRecord(marks[i], (hipStream_t)stream) == hipSuccess ? RSAPRNG_OK
@@ -594,6 +601,7 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   shape.mode = mode;
   shape.prefix = c.prefix;
   shape.r = c.chunks_per_wave;
+  shape.e = shared_e;
   shape.grid = grid_for(d, shape, c, c.prefix == kPrefixSerial ? (u64h)nchain : ntiles);
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
@@ -766,7 +774,8 @@ int rsaprng_generate(rsaprng_t h, uint64_t k0, uint64_t count, uint64_t* out_u64
   if ((rc = sc->upload(chains.data(), chains.size() * sizeof(Chain), stream, &dch, &slot)))
     return rc;
   rc = enqueue_launch(d, sc, c, kModeGenerate, h->dev, (const Chain*)dch, (uint32_t)chains.size(),
-                      ntiles, out_u64, out_f64, nullptr, 0, nullptr, stream);
+                      ntiles, out_u64, out_f64, nullptr, 0, nullptr, stream, nullptr, nullptr,
+                      shared_exponent(&in, 1));
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -908,7 +917,8 @@ int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u
   if ((rc = sc->upload(buf.data(), buf.size(), stream, &dbuf, &slot))) return rc;
   rc = enqueue_launch(d, sc, c, kModeGenerate, (const rsaprng_params*)dbuf,
                       (const Chain*)((char*)dbuf + ib), (uint32_t)plan.size(), ntiles, out_u64,
-                      out_f64, nullptr, 0, nullptr, stream);
+                      out_f64, nullptr, 0, nullptr, stream, nullptr, nullptr,
+                      shared_exponent(in.data(), nreq));
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -1029,7 +1039,8 @@ rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg) {
 }
 
 int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
-              const rsaprng_config& c, std::vector<Chain>& plan, u64h* ntiles) {
+              const rsaprng_config& c, std::vector<Chain>& plan, u64h* ntiles,
+              uint32_t* shared_e = nullptr) {
   std::vector<PlanIn> in(nreq);
   const size_t np = pool->host.size();
   for (size_t i = 0; i < nreq; ++i) {
@@ -1039,6 +1050,7 @@ int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, in
                    mode == kModeConsume ? (uint32_t)reqs[i].out_off : 0u, 0};
     if (mode == kModeConsume && reqs[i].out_off > 0xffffffffull) return RSAPRNG_E_ARG;
   }
+  if (shared_e) *shared_e = shared_exponent(in.data(), nreq);
   return plan_chains(in.data(), nreq, c, mode, plan, ntiles);
 }
 
@@ -1075,7 +1087,8 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   }
   std::vector<Chain> plan;
   u64h ntiles;
-  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
+  uint32_t se = 0;
+  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles, &se))) return rc;
   const size_t nst = mode == kModeConsume ? stats_records(reqs, nreq) : 0;
   if (mode == kModeBattery) {
     u64h total = 0;
@@ -1089,7 +1102,7 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   int slot;
   if ((rc = sc->upload(plan.data(), plan.size() * sizeof(Chain), stream, &dreq, &slot))) return rc;
   rc = enqueue_launch(d, sc, c, mode, pool->dev, (const Chain*)dreq, (uint32_t)plan.size(), ntiles,
-                      out_u64, out_f64, stats, nst, nullptr, stream, nullptr, battery);
+                      out_u64, out_f64, stats, nst, nullptr, stream, nullptr, battery, se);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -1314,6 +1327,7 @@ struct rsaprng_batch_s {
   double* out_r = nullptr;
   rsaprng_stats* stats = nullptr;
   size_t nst = 0;
+  uint32_t shared_e = 0;                      // exponent of every request, or 0
   std::vector<std::array<hipEvent_t, 5>> ev;  // per timed run
   size_t ev_used = 0;
   ~rsaprng_batch_s() {
@@ -1342,9 +1356,11 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   rsaprng_config c = config_for_pool(pool, cfg);
   std::vector<Chain> plan;
   u64h ntiles;
-  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles))) return rc;
+  uint32_t se = 0;
+  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles, &se))) return rc;
   auto b = std::make_unique<rsaprng_batch_s>();
   b->pool = pool;
+  b->shared_e = se;
   if ((rc = b->sc.init())) return rc;
   // sized before the capture so that the captured launch allocates nothing
   if ((rc = b->sc.ensure_tiles(ntiles, ntiles * (tile_size(c) / (64ull * c.per_lane)), plan.size(),
@@ -1362,7 +1378,8 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   if (hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return RSAPRNG_E_HIP;
   rc = enqueue_launch(d, &b->sc, c, mode, pool->dev, (const Chain*)b->dreq, (uint32_t)plan.size(),
-                      ntiles, out_u64, out_f64, stats_dev, nst, nullptr, b->cap_stream);
+                      ntiles, out_u64, out_f64, stats_dev, nst, nullptr, b->cap_stream, nullptr,
+                      nullptr, se);
   hipGraph_t g = nullptr;
   hipError_t e1 = hipStreamEndCapture(b->cap_stream, &g);
   if (rc) {
@@ -1407,7 +1424,7 @@ int rsaprng_batch_run_timed(rsaprng_batch_t b, void* stream) {
   hipEvent_t* marks = b->ev[b->ev_used].data();
   const int rc = enqueue_launch(b->dev, &b->sc, b->cfg, b->mode, b->pool->dev,
                                 (const Chain*)b->dreq, b->nchain, b->ntiles, b->out_c, b->out_r,
-                                b->stats, b->nst, nullptr, stream, marks);
+                                b->stats, b->nst, nullptr, stream, marks, nullptr, b->shared_e);
   if (!rc) ++b->ev_used;
   return rc;
 }

@@ -64,7 +64,10 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks = nullptr,
-                   rsaprng_battery* battery = nullptr);
+                   rsaprng_battery* battery = nullptr, uint32_t shared_e = 0);
+// The exponent shared by every request (0 if they differ; dual-exponent
+// instances have e = 0): lets a launch take kernels specialised to it.
+uint32_t shared_exponent(const PlanIn* in, size_t n);
 // Parameter generation kernels (k_primes.hip).
 int launch_count_primes(uint64_t lo, uint64_t hi, int safe, unsigned long long* count_dev,
                         void* stream);

@@ -25,6 +25,8 @@
 //                  atomics, bounded wait), or from the carry of the previous
 //                  step when one work-group walks the whole chain (k_gen3).
 #pragma once
+#include <type_traits>
+
 #include "common.h"
 #include "devmath.h"
 
@@ -41,6 +43,15 @@ __device__ __forceinline__ u64 submod(u64 x, u64 y, u64 n) {
 }
 
 __device__ __forceinline__ u32 uniform(u32 v) { return __builtin_amdgcn_readfirstlane(v); }
+
+// f(integral_constant<int, I>) for I = B .. E-1, each call its own instantiation.
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
 
 // Read-only launch data (chains, instance records, per-tile and per-chunk
 // prefixes) seen through the constant address space: with wave-uniform
@@ -720,12 +731,13 @@ __device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H,
   L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
 }
 
-// The lane total of V skips without keeping them, as H 2^32 + L.  Two skips
-// (each below 2^63) add without overflow; the pair sums go into a 64-bit
-// accumulator with a carry count, so the total S = carry 2^64 + acc (below
-// V 2^63) gives H = carry 2^32 + hi32(acc) < 2^35 and L = lo32(acc) exactly.
-template <int V>
-__device__ __forceinline__ void walk_totals(u64 s_first, double& H, double& L) {
+// The lane total of V skips as H 2^32 + L, the skips kept in S[0..V) when
+// KEEP.  Two skips (each below 2^63) add without overflow; the pair sums go
+// into a 64-bit accumulator with a carry count, so the total S = carry 2^64 +
+// acc (below V 2^63) gives H = carry 2^32 + hi32(acc) < 2^35 and L = lo32(acc)
+// exactly.
+template <int V, bool KEEP>
+__device__ __forceinline__ void walk_sum(u64 s_first, u64* S, double& H, double& L) {
   static_assert(V % 2 == 0 && V <= 16, "pairs of skips; H below 2^35");
   u64 s = s_first;
   u64 acc = 0;
@@ -734,6 +746,10 @@ __device__ __forceinline__ void walk_totals(u64 s_first, double& H, double& L) {
   for (int i = 0; i < V; i += 2) {
     if (i) s = lcg_next(s);
     const u64 s1 = lcg_next(s);
+    if constexpr (KEEP) {
+      S[i] = s;
+      S[i + 1] = s1;
+    }
     const u64 pair = s + s1;
     const u64 t = acc + pair;
     carry += t < pair;
@@ -765,12 +781,17 @@ __device__ __forceinline__ double wave_scan_f64(double x, int) {
 
 // Dispatch of one lane's outputs on the exponent: ladders unrolled for the
 // common exponents when every index of the span is requested and the stores
-// are 16-byte aligned, a generic ladder with predicated stores otherwise.
-template <int WG, int V, int VAR, int MODE, class Msg>
+// are 16-byte aligned, a generic ladder with predicated stores otherwise.  EK
+// != 0: every instance of the launch has exponent EK.
+template <int WG, int V, int VAR, int MODE, int EK = 0, class Msg>
 __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, bool fast, u64 laneStart) {
-  if (fast) {
+  if (!fast) {
+    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, msg, laneStart);
+  } else if constexpr (EK != 0) {
+    tile_outputs<WG, V, VAR, MODE, EK, true>(a, sh, C, P, msg, laneStart);
+  } else {
     switch (P.e) {
       case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, msg, laneStart); break;
       case 3: tile_outputs<WG, V, VAR, MODE, 3, true>(a, sh, C, P, msg, laneStart); break;
@@ -781,13 +802,11 @@ __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG
       case 65537: tile_outputs<WG, V, VAR, MODE, 65537, true>(a, sh, C, P, msg, laneStart); break;
       default: tile_outputs<WG, V, VAR, MODE, 0, true>(a, sh, C, P, msg, laneStart); break;
     }
-  } else {
-    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, msg, laneStart);
   }
 }
 
 // Outputs of one wave chunk (64 V indices starting at chunkStart).
-template <int WG, int V, int VAR, int MODE, class Msg>
+template <int WG, int V, int VAR, int MODE, int EK = 0, class Msg>
 __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, u64 chunkStart, u64 laneStart) {
@@ -797,7 +816,7 @@ __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG
                     (MODE == kModeConsume ||
                      ((!a.out_c || ((uintptr_t)(a.out_c + off_c) & 15) == 0) &&
                       (!a.out_r || ((uintptr_t)(a.out_r + off_c) & 15) == 0)));
-  outputs_for_e<WG, V, VAR, MODE>(a, sh, C, P, msg, fast, laneStart);
+  outputs_for_e<WG, V, VAR, MODE, EK>(a, sh, C, P, msg, fast, laneStart);
 }
 
 // The same state from residue messages (b the residues of the message before
@@ -1020,10 +1039,15 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
 // for the Montgomery variant.  The waves exchange their totals through LDS
 // once per step (double-buffered by step parity: one barrier per step).  The
 // output pass walks each chunk again from its first skip instead of keeping
-// R V skips across the barrier.  Steps before the chain's first requested
-// index only walk.  No prefix pass is needed.
-template <int WG, int V, int R, int VAR, int MODE>
-__global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
+// R V skips across the barrier, except in the kernels specialised to one
+// exponent (EK != 0, generate mode): with a single ladder in the kernel the
+// skips fit the register budget of four waves per SIMD (which the transpose
+// buffers' LDS caps residency at anyway), so they are kept.  Steps before the
+// chain's first requested index only walk.  No prefix pass is needed.
+template <int WG, int V, int R, int VAR, int MODE, int EK = 0>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(EK != 0 ? 4 : 1)))
+void k_gen3(LaunchArgs a) {
+  static_assert(EK == 0 || (MODE == kModeGenerate && VAR == kVariantCrt), "specialised generate");
   constexpr int NW = WG / 64;
   constexpr u64 T = (u64)WG * V * R;
   constexpr u64 CHUNK = 64ull * V;
@@ -1073,10 +1097,12 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
         // totals of the wave's earlier chunks
         double ep[R], eq[R];
         double wp = 0.0, wq = 0.0;
+        constexpr bool kKeep = EK != 0;
+        u64 S[R][kKeep ? V : 1];  // the kept skips of each chunk
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           double Ht, Lt;
-          walk_totals<V>(sf[r], Ht, Lt);
+          walk_sum<V, kKeep>(sf[r], S[r], Ht, Lt);
           const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
           const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
           const double ip = wave_scan_f64(tp, lane);
@@ -1105,17 +1131,33 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
           Tq += v.y;
         }
         if (step_out) {
+          if constexpr (kKeep) {
+            // unrolled by instantiation: the kept skips are indexed statically
+            static_for<0, R>([&](auto rc) {
+              constexpr int r = decltype(rc)::value;
+              const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+              const u64 laneStart = chunkStart + (u64)lane * V;
+              const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
+              const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
+              if (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast) {
+                const MsgRes<V> msg{S[r], bp, bq};
+                chunk_outputs<WG, V, VAR, MODE, EK>(a, sh, C, P, msg, chunkStart, laneStart);
+              }
+              chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
+            });
+          } else {
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
-            const u64 laneStart = chunkStart + (u64)lane * V;
-            const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
-            const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
-            const bool chunk_out = MODE == kModeConsume ||
-                                   (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
-            const MsgResWalk<V> msg{sf[r], bp, bq};
-            if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-            chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
+            for (int r = 0; r < R; ++r) {
+              const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+              const u64 laneStart = chunkStart + (u64)lane * V;
+              const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
+              const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
+              const bool chunk_out = MODE == kModeConsume ||
+                                     (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
+              const MsgResWalk<V> msg{sf[r], bp, bq};
+              if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+              chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
+            }
           }
         }
         cp = reduce_res(cp + Tp, P.pd, P.pinv);
@@ -1171,18 +1213,18 @@ __global__ __launch_bounds__(WG) void k_gen3(LaunchArgs a) {
   }
 }
 
-template <int WG, int V, int R, int VAR, int MODE>
+template <int WG, int V, int R, int VAR, int MODE, int EK = 0>
 static int launch3(const LaunchArgs& a, int grid, void* stream, int* occ) {
   if (occ) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen3<WG, V, R, VAR, MODE>, WG, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen3<WG, V, R, VAR, MODE, EK>, WG,
+                                                     0) != hipSuccess)
       blocks = 1;
     *occ = blocks > 0 ? blocks : 1;
     return RSAPRNG_OK;
   }
-  hipLaunchKernelGGL((k_gen3<WG, V, R, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream,
-                     a);
+  hipLaunchKernelGGL((k_gen3<WG, V, R, VAR, MODE, EK>), dim3(grid), dim3(WG), 0,
+                     (hipStream_t)stream, a);
   return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
@@ -1233,6 +1275,14 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
       return RSAPRNG_E_ARG;
     }
     if (s.prefix == kPrefixSerial) {
+      if constexpr (MODE == kModeGenerate && VAR == kVariantCrt) {
+        // every instance of the launch has e = 3: the kernels specialised to
+        // it (not for four chunks per wave, whose kept skips would spill)
+        if (s.e == 3) {
+          if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
+          if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
+        }
+      }
       if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
       if (s.wg == 256 && s.v == 8 && s.r == 4) return launch3<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
       if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);

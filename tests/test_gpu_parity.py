@@ -173,6 +173,28 @@ def test_substreams_config2_subset_all_shapes(R):
                     assert_same(c, r, cref, rref, "config2 %s %s %s %s" % (var, shape, pers, prefix))
 
 
+def test_exponent_specialised_chain_serial(R):
+    # Launches whose instances all have e = 3 take the chain-serial kernels
+    # specialised to that exponent (skips kept for the output pass); ragged
+    # ranges put partial chunks and partial steps at both ends of each chain.
+    # A pool that mixes e = 3 and e = 5 takes the general kernels.
+    insts3 = inputs.config2(6)
+    ranges = [(0, 0, B), (1, 17, 5000), (2, B - 777, 4096 + 1000), (3, 3 * B + 8191, 8193),
+              (4, 12345, 2 * 8192 + 64 * 8 + 3), (5, (1 << 40) + 5, 70001)]
+    # the exponent-sweep instances are valid for e = 5
+    mixed = insts3[:3] + [inputs.Instance(i.p, i.q, 5, i.m0) for i in inputs.config3(3)]
+    for shape in ((256, 8, 2), (512, 8, 2)):
+        for pers in (0, 1):
+            cfg = R.config(variant=R.VARIANT_CRT, lanes_per_tile=shape[0], per_lane=shape[1],
+                           chunks_per_wave=shape[2], persistent=pers, order=pers, prefix=2)
+            log("e=3 specialised", shape, pers)
+            c, r, _ = _gen_pool(R, insts3, ranges, cfg)
+            _check_ranges(insts3, ranges, c, r, "e=3 specialised %s %d" % (shape, pers))
+            log("mixed exponents", shape, pers)
+            c, r, _ = _gen_pool(R, mixed, ranges, cfg)
+            _check_ranges(mixed, ranges, c, r, "mixed %s %d" % (shape, pers))
+
+
 def test_consume_matches_oracle(R):
     import torch
     insts = inputs.config3(3)
