@@ -108,12 +108,16 @@ def time_graph(batch, stream, steps, warmup, torch):
     return wall, kms
 
 
-def tile_kernel_name(cfg) -> str:
-    """The tile kernel of a configuration, as rocprofv3 lists it."""
+def tile_kernel_name(cfg, exponent=0) -> str:
+    """The tile kernel of a configuration, as rocprofv3 lists it.  A launch whose
+    instances all have e = 3 takes the chain-serial CRT kernels specialised to it
+    (two chunks per wave), whose name carries the exponent."""
     form = {0: "k_gen2", 1: "k_gen1", 2: "k_gen3"}[cfg.prefix]
     r = "" if cfg.prefix == 1 else ", %d" % cfg.chunks_per_wave
-    return "%s<%d, %d%s, %d, 0> (%s, generate)" % (
-        form, cfg.lanes_per_tile, cfg.per_lane, r, cfg.variant,
+    ek = ", 3" if (exponent == 3 and cfg.prefix == 2 and cfg.variant == 2
+                   and cfg.chunks_per_wave == 2) else ""
+    return "%s<%d, %d%s, %d, 0%s> (%s, generate)" % (
+        form, cfg.lanes_per_tile, cfg.per_lane, r, cfg.variant, ek,
         "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64")
 
 
@@ -627,10 +631,10 @@ def main():
 
     alg_bytes = 16 * N                                      # 8 B c_k + 8 B r_k per output
     achieved = alg_bytes / (k_ms / 1e3) / 1e9
-    traffic = traffic_from_profiles("multi_instance_e3", tile_kernel_name(best))
+    traffic = traffic_from_profiles("multi_instance_e3", tile_kernel_name(best, exponent=3))
     roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": tile_kernel_name(best),
+                "kernel": tile_kernel_name(best, exponent=3),
                 "algorithmic_bytes_per_launch": alg_bytes, "avg_launch_ms": k_ms,
                 "other_kernels_ms": {"setup": kt["setup"], "prefix": kt["prefix"]},
                 "graph_replay_ms_per_step": gwall / args.steps * 1e3}
