@@ -268,25 +268,24 @@ __device__ __forceinline__ double reduce_res(double x, double P, double Pinv) {
 
 // Residue messages (CRT variant).  With the lane's skips s_0..s_{V-1} and the
 // residues bp, bq of the message before its first index (in (-p, p), (-q, q)),
-// m_i is congruent to b + S_i where S_i = s_0 + ... + s_i = H_i 2^32 + L_i, H_i
-// and L_i the exact sums of the skips' upper and lower halves (below 2^34 and
-// 2^35 for V = 8).  Only m mod p and m mod q enter the encryption, so no
-// 64-bit modular addition is done.  The running values Lp = bp + L_i and
-// Lq = bq + L_i are kept instead of L_i, so m_i mod p is fold_p(H_i) + Lp: an
-// integer below 2^36 in magnitude, a valid input of the ladder's squaring.
+// m_i is congruent to b + s_0 + ... + s_i.  Only m mod p and m mod q enter the
+// encryption, so no 64-bit modular addition is done: each skip s = h 2^32 + l
+// adds fold_p(h) + l to the running residue mp (fold_p(h) in (-p, p)), so after
+// V <= 8 skips |mp| < p + 8 (p + 2^32) < 2^37, a valid input of the ladder's
+// squaring (likewise mod q).
 template <int V>
 struct MsgRes {
   const u64 (&S)[V];
-  double Lp, Lq;  // bp, bq on entry
-  double H = 0.0;
+  double Ap, Aq;  // bp, bq on entry; then the residues of the latest message
   template <int VAR, u32 E>
   __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
-    H += (double)hi32(S[i]);
+    static_assert(V <= 8, "residue bound");
+    const double h = (double)hi32(S[i]);
     const double l = (double)lo32(S[i]);
-    Lp += l;
-    Lq += l;
-    double mp = fold_p(H, P) + Lp;
-    double mq = fold_q(H, P) + Lq;
+    Ap += fold_p(h, P) + l;
+    Aq += fold_q(h, P) + l;
+    double mp = Ap;
+    double mq = Aq;
     if constexpr (E < 2) {  // no opening squaring: Garner needs reduced residues
       mp = reduce_res(mp, P.pd, P.pinv);
       mq = reduce_res(mq, P.qd, P.qinv);
@@ -300,17 +299,17 @@ struct MsgRes {
 template <int V>
 struct MsgResWalk {
   u64 s;
-  double Lp, Lq;  // bp, bq on entry
-  double H = 0.0;
+  double Ap, Aq;  // bp, bq on entry; then the residues of the latest message
   template <int VAR, u32 E>
   __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
+    static_assert(V <= 8, "residue bound");
     if (i) s = lcg_next(s);
-    H += (double)hi32(s);
+    const double h = (double)hi32(s);
     const double l = (double)lo32(s);
-    Lp += l;
-    Lq += l;
-    double mp = fold_p(H, P) + Lp;
-    double mq = fold_q(H, P) + Lq;
+    Ap += fold_p(h, P) + l;
+    Aq += fold_q(h, P) + l;
+    double mp = Ap;
+    double mq = Aq;
     if constexpr (E < 2) {
       mp = reduce_res(mp, P.pd, P.pinv);
       mq = reduce_res(mq, P.qd, P.qinv);
@@ -788,7 +787,7 @@ __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, bool fast, u64 laneStart) {
   if (!fast) {
-    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, msg, laneStart);
+    tile_outputs<WG, V, VAR, MODE, EK, false>(a, sh, C, P, msg, laneStart);
   } else if constexpr (EK != 0) {
     tile_outputs<WG, V, VAR, MODE, EK, true>(a, sh, C, P, msg, laneStart);
   } else {
