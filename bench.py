@@ -69,9 +69,13 @@ def traffic_from_profiles(workload: str, kernel: str):
     ent = rec.get(workload)
     if not ent or ent.get("kernel_source_hash") != kernel_source_hash():
         return None
-    if ent.get("kernel") != kernel.split(" (")[0]:
-        return None
-    return ent.get("hbm_bytes_per_launch")
+    name = kernel.split(" (")[0]
+    # the profiled kernel, or another shape the autotuner may pick, measured by
+    # the same two counter passes and calibration on the same sources
+    for e in [ent] + list(ent.get("other_kernels", [])):
+        if e.get("kernel") == name:
+            return e.get("hbm_bytes_per_launch")
+    return None
 
 
 def time_timed(batch, stream, steps, warmup, torch):

@@ -30,3 +30,7 @@ def test_traffic_record_is_keyed_by_the_generate_kernel_sources():
     for k in ("kernel", "kernel_source_hash", "fetch_size_kib", "write_size_kib",
               "copy_fetch_factor", "copy_write_factor", "hbm_bytes_per_launch"):
         assert k in ent, k
+    # other shapes measured on the same sources carry their own two passes
+    for o in ent.get("other_kernels", []):
+        for k in ("kernel", "command", "fetch_size_kib", "write_size_kib", "hbm_bytes_per_launch"):
+            assert k in o, k
