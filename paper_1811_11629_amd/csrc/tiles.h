@@ -338,6 +338,31 @@ typedef u64 u64x2 __attribute__((ext_vector_type(2)));
 // plus one word of padding against LDS bank conflicts.
 constexpr int kXRow = 9;
 
+// Stores a wave's 64 x 8 transposed block x (row = lane, 8 consecutive outputs)
+// to dst[0 .. 512).  With dst 16-byte aligned, store j writes elements 128 j +
+// 2 lane and the next (rows 16 j + lane / 4, columns 2 (lane % 4) and the
+// next): each 16-byte store instruction covers 1 KiB of contiguous output, with
+// the non-temporal hint (the outputs are not read again by the kernel).
+// Otherwise (an output range packed at an odd element) store j writes element
+// 64 j + lane: each 8-byte store instruction covers 512 contiguous bytes.
+// A16: 1 or 0 when the caller knows the alignment, -1 to test it here (a
+// wave-uniform branch).
+// src: (lane / 4) kXRow + 2 (lane % 4), formed by the caller before its wave
+// barrier.
+template <int A16>
+__device__ __forceinline__ void store_chunk(u64* dst, const u64* x, int src, int lane) {
+  if (A16 == 1 || (A16 == -1 && ((uintptr_t)dst & 15) == 0)) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      __builtin_nontemporal_store(u64x2{x[j * 16 * kXRow + src], x[j * 16 * kXRow + src + 1]},
+                                  reinterpret_cast<u64x2*>(dst + (u64)j * 128 + 2 * lane));
+  } else {
+    const int src8 = (lane >> 3) * kXRow + (lane & 7);
+#pragma unroll
+    for (int j = 0; j < 8; ++j) dst[(u64)j * 64 + lane] = x[j * 8 * kXRow + src8];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Statistical battery (fused consumer), chain-serial kernel only.  Tuples live
 // inside aligned blocks of 8 indices, maxima in aligned blocks of 32, gap runs
@@ -490,7 +515,7 @@ struct TileShared {
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
 // every index of the tile is requested and both outputs are 16-byte aligned at
 // every lane's first index, so pairs are stored without predicates.
-template <int WG, int V, int VAR, int MODE, u32 E, bool FAST, class Msg>
+template <int WG, int V, int VAR, int MODE, u32 E, bool FAST, int A16 = -1, class Msg>
 __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                              const Chain& C, const rsaprng_params& P, Msg msg,
                                              u64 laneStart) {
@@ -500,11 +525,8 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
     double* const orr = a.out_r;
     if constexpr (FAST && V == 8) {
       // Each lane's 8 results go to its row of the wave's LDS buffers (c and r)
-      // as they are produced; then store j writes elements 128 j + 2 lane and
-      // the next of the chunk (rows 16 j + lane / 4, columns 2 (lane % 4) and
-      // the next), so every 16-byte store instruction covers 1 KiB of
-      // contiguous output.  The stores are non-temporal: the outputs are not
-      // read again by this kernel.  No result waits in registers.
+      // as they are produced, then store_chunk writes them coalesced.  No
+      // result waits in registers.
       const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
       u64* xc = sh.xbuf + wave * (2 * 64 * kXRow);
       u64* xr = xc + 64 * kXRow;
@@ -520,19 +542,8 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      if (oc) {
-#pragma unroll
-        for (int j = 0; j < V / 2; ++j)
-          __builtin_nontemporal_store(u64x2{xc[j * 16 * kXRow + src], xc[j * 16 * kXRow + src + 1]},
-                                      reinterpret_cast<u64x2*>(oc + chunk0 + (u64)j * 128 + 2 * lane));
-      }
-      if (orr) {
-        u64* const dr = reinterpret_cast<u64*>(orr);
-#pragma unroll
-        for (int j = 0; j < V / 2; ++j)
-          __builtin_nontemporal_store(u64x2{xr[j * 16 * kXRow + src], xr[j * 16 * kXRow + src + 1]},
-                                      reinterpret_cast<u64x2*>(dr + chunk0 + (u64)j * 128 + 2 * lane));
-      }
+      if (oc) store_chunk<A16>(oc + chunk0, xc, src, lane);
+      if (orr) store_chunk<A16>(reinterpret_cast<u64*>(orr) + chunk0, xr, src, lane);
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -780,16 +791,23 @@ __device__ __forceinline__ double wave_scan_f64(double x, int) {
 
 // Dispatch of one lane's outputs on the exponent: ladders unrolled for the
 // common exponents when every index of the span is requested and the stores
-// are 16-byte aligned, a generic ladder with predicated stores otherwise.  EK
-// != 0: every instance of the launch has exponent EK.
+// are suitably aligned, a generic ladder with predicated stores otherwise.  EK
+// != 0: every instance of the launch has exponent EK; the caller passes fast
+// only for 16-byte-aligned outputs, so that this path carries no second store
+// sequence (the register budget of those kernels is tight), and other chunks
+// take the EK ladder with predicated stores.  The general kernels' fast path
+// takes any 8-byte-aligned output (store_chunk tests the alignment).
 template <int WG, int V, int VAR, int MODE, int EK = 0, class Msg>
 __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, bool fast, u64 laneStart) {
-  if (!fast) {
-    tile_outputs<WG, V, VAR, MODE, EK, false>(a, sh, C, P, msg, laneStart);
-  } else if constexpr (EK != 0) {
-    tile_outputs<WG, V, VAR, MODE, EK, true>(a, sh, C, P, msg, laneStart);
+  if constexpr (EK != 0) {
+    if (fast)
+      tile_outputs<WG, V, VAR, MODE, EK, true, 1>(a, sh, C, P, msg, laneStart);
+    else
+      tile_outputs<WG, V, VAR, MODE, EK, false>(a, sh, C, P, msg, laneStart);
+  } else if (!fast) {
+    tile_outputs<WG, V, VAR, MODE, 0, false>(a, sh, C, P, msg, laneStart);
   } else {
     switch (P.e) {
       case 1: tile_outputs<WG, V, VAR, MODE, 1, true>(a, sh, C, P, msg, laneStart); break;
@@ -804,18 +822,29 @@ __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG
   }
 }
 
-// Outputs of one wave chunk (64 V indices starting at chunkStart).
+// Outputs of one wave chunk (64 V indices starting at chunkStart).  The fast
+// path needs every index of the chunk requested; in the general kernels with
+// V = 8 its stores take any 8-byte-aligned output (store_chunk), the pair
+// stores of other V and the kernels specialised to one exponent need 16-byte
+// alignment.
 template <int WG, int V, int VAR, int MODE, int EK = 0, class Msg>
 __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, u64 chunkStart, u64 laneStart) {
   constexpr u64 CHUNK = 64ull * V;
   const u64 off_c = C.out_off + (chunkStart - C.k0);
-  const bool fast = chunkStart >= C.k0 && chunkStart + (CHUNK - 1) <= C.last &&
-                    (MODE == kModeConsume ||
-                     ((!a.out_c || ((uintptr_t)(a.out_c + off_c) & 15) == 0) &&
-                      (!a.out_r || ((uintptr_t)(a.out_r + off_c) & 15) == 0)));
-  outputs_for_e<WG, V, VAR, MODE, EK>(a, sh, C, P, msg, fast, laneStart);
+  // 16-byte-aligned outputs (evaluated only for a full chunk)
+  const auto a16 = [&] {
+    return (!a.out_c || ((uintptr_t)(a.out_c + off_c) & 15) == 0) &&
+           (!a.out_r || ((uintptr_t)(a.out_r + off_c) & 15) == 0);
+  };
+  const bool full = chunkStart >= C.k0 && chunkStart + (CHUNK - 1) <= C.last;
+  if constexpr (EK != 0)
+    outputs_for_e<WG, V, VAR, MODE, EK>(a, sh, C, P, msg, full && a16(), laneStart);
+  else
+    outputs_for_e<WG, V, VAR, MODE, EK>(a, sh, C, P, msg,
+                                        full && (MODE != kModeGenerate || V == 8 || a16()),
+                                        laneStart);
 }
 
 // The same state from residue messages (b the residues of the message before
@@ -1020,7 +1049,7 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
       // the fast path is decided per tile here so every wave takes the same barriers
       const u64 off_t = C.out_off + (tileStart - C.k0);
       const bool fast = tileStart >= C.k0 && tileStart + (T - 1) <= C.last &&
-                        (MODE == kModeConsume ||
+                        (MODE == kModeConsume || V == 8 ||
                          ((!a.out_c || ((uintptr_t)(a.out_c + off_t) & 15) == 0) &&
                           (!a.out_r || ((uintptr_t)(a.out_r + off_t) & 15) == 0)));
       outputs_for_e<WG, V, VAR, MODE>(a, sh, C, P, MsgExact<V>{pre, n, X}, fast, laneStart);
