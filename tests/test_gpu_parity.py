@@ -173,6 +173,27 @@ def test_substreams_config2_subset_all_shapes(R):
                     assert_same(c, r, cref, rref, "config2 %s %s %s %s" % (var, shape, pers, prefix))
 
 
+def test_odd_output_offsets_every_shape(R):
+    # Ranges packed back to back after ranges of odd length start at odd
+    # elements of the output arrays: full chunks there take the fast path's
+    # 8-byte stores (store_chunk), on every shape of both variants.
+    insts = inputs.config2(4)
+    ranges = [(0, 0, 1), (1, 4096, 3 * 8192 + 1), (2, B - 8192 * 2, 8192 * 5), (3, 77, 40001),
+              (0, 5 * B + 3, 2 * 8192 + 511)]
+    offs, o = [], 0
+    for _, _, cnt in ranges:
+        offs.append(o)
+        o += cnt
+    assert any(x % 2 for x in offs)
+    for var, name in _variants(R):
+        for shape in SHAPES:
+            log("odd offsets", name, shape)
+            cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                           chunks_per_wave=shape[2], prefix=shape[3])
+            c, r, _ = _gen_pool(R, insts, ranges, cfg)
+            _check_ranges(insts, ranges, c, r, "odd offsets %s %s" % (name, shape))
+
+
 def test_exponent_specialised_chain_serial(R):
     # Launches whose instances all have e = 3 take the chain-serial kernels
     # specialised to that exponent (skips kept for the output pass); ragged
