@@ -48,22 +48,28 @@ __global__ __launch_bounds__(256) void k_chain_setup(LaunchArgs a) {
 // wave chunks (64 V indices each, 64/NW consecutive lanes here) mod n.
 __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   const int lane = threadIdx.x & 63;
-  const u32 t = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const u32 t = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (t >= a.ntiles) return;
-  const u32 c = uniform(a.tile_chain[t]);
-  const Chain C = a.chain[c];
-  const u64 n = a.inst[C.inst].n;
-  const u32 j = t - C.first;
-  const u64 s_tile = mulmod_q(a.cstart[c].s_S, a.at[j]);
+  // wave-uniform records through the constant address space (scalar loads)
+  const u32 c = cst(a.tile_chain)[t];
+  const u32 first = cst(&a.chain[c].first)[0];
+  const u32 inst = cst(&a.chain[c].inst)[0];
+  const u64 n = cst(&a.inst[inst].n)[0];
+  const u32 j = t - first;
+  const u64 s_tile = mulmod_q(cst(&a.cstart[c].s_S)[0], cst(a.at)[j]);
   u64 s = mulmod_q(s_tile, a.pl[lane]);
-  const int per = 1 << (a.tile_log2 - 6);
-  // exact integer sum of the lane's skips: lo + 2^64 hi, hi < per / 2 (skips < 2^63)
-  u64 lo = s, hi = 0;
-  for (int i = 1; i < per; ++i) {
-    s = lcg_next(s);
-    const u64 t2 = lo + s;
-    hi += t2 < lo;
+  const int per = 1 << (a.tile_log2 - 6);  // even: T >= 2048
+  // exact integer sum of the lane's skips: lo + 2^64 hi, hi < per / 2 (skips <
+  // 2^63); two skips add without overflow, so the carry is taken once per pair
+  u64 lo = 0, hi = 0;
+  for (int i = 0; i < per; i += 2) {
+    if (i) s = lcg_next(s);
+    const u64 s1 = lcg_next(s);
+    const u64 pair = s + s1;
+    const u64 t2 = lo + pair;
+    hi += t2 < pair;
     lo = t2;
+    s = s1;
   }
   // reduce mod n: lo mod n (lo < 2^64 <= 4n), plus hi (2^64 mod n) by doubling
   u64 x = lo;
