@@ -102,17 +102,19 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
 // the tile (the serial part is one scan per 64 tiles, not per 64 chunks).
 __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const int lane = threadIdx.x & 63;
-  const u32 c = blockIdx.x * 4 + (threadIdx.x >> 6);
+  const u32 c = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
   if (c >= a.nchain) return;
-  const Chain C = a.chain[c];
-  const u64 n = a.inst[C.inst].n;
+  // wave-uniform records through the constant address space (scalar loads)
+  const u32 ntiles = cst(&a.chain[c].ntiles)[0];
+  const u32 first = cst(&a.chain[c].first)[0];
+  const u64 n = cst(&a.inst[cst(&a.chain[c].inst)[0]].n)[0];
   const int nw_log2 = a.tile_log2 - a.chunk_log2;
   const int CH = 1 << nw_log2;  // chunks per tile
-  u64 E = a.cstart[c].m_base;
-  for (u64 base = 0; base < C.ntiles; base += 64) {
+  u64 E = cst(&a.cstart[c].m_base)[0];
+  for (u64 base = 0; base < ntiles; base += 64) {
     const u64 t = base + lane;
-    const bool live = t < C.ntiles;
-    const u64 q0 = ((u64)C.first + t) << nw_log2;  // first chunk of tile t
+    const bool live = t < ntiles;
+    const u64 q0 = ((u64)first + t) << nw_log2;  // first chunk of tile t
     u64 tot = 0;
     if (live)
       for (int j = 0; j < CH; ++j) tot = addmod(tot, a.agg[q0 + j], n);
