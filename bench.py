@@ -231,7 +231,7 @@ def run_consume_sweep(R, torch, stream, steps):
     return out
 
 
-def run_batched_uneven(R, torch, stream, steps):
+def run_batched_uneven(R, torch, stream, steps, cfg=None, plain=True):
     import inputs
     t0 = time.perf_counter()
     insts, reqs4 = inputs.config4()
@@ -244,23 +244,28 @@ def run_batched_uneven(R, torch, stream, steps):
     oc = torch.empty(total, dtype=torch.int64, device="cuda")
     orr = torch.empty(total, dtype=torch.float64, device="cuda")
     pool = R.Pool.from_instances(insts)
-    best, _ = R.rsaprng_autotune(pool, reqs, R.MODE_GENERATE, oc, orr, stream=stream)
+    if cfg is None:
+        best, _ = R.rsaprng_autotune(pool, reqs, R.MODE_GENERATE, oc, orr, stream=stream)
+    else:
+        best = cfg
     b = R.Batch(pool, reqs, R.MODE_GENERATE, oc, orr, cfg=best, stream=stream)
     wall, kms = time_graph(b, stream, max(2, steps // 4), 1, torch)
     b.check()
     ms = sum(kms) / len(kms)
     batched = total / (ms / 1e3) / 1e9
-    # plain per-request launches, round-robin over 4 streams
-    gens = [R.rsaprng_create_ex(i.p, i.q, i.e, i.m0, i.s0) for i in insts]
-    streams = [torch.cuda.Stream() for _ in range(4)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for j, (i, k0, cnt, o) in enumerate(reqs):
-        R.rsaprng_generate(gens[i], k0, cnt, oc[o:], orr[o:], stream=streams[j % 4])
-    torch.cuda.synchronize()
-    plain_s = time.perf_counter() - t1
-    for s in streams:
-        R.rsaprng_check_device_error(s)
+    plain_s = None
+    if plain:
+        # plain per-request launches, round-robin over 4 streams
+        gens = [R.rsaprng_create_ex(i.p, i.q, i.e, i.m0, i.s0) for i in insts]
+        streams = [torch.cuda.Stream() for _ in range(4)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for j, (i, k0, cnt, o) in enumerate(reqs):
+            R.rsaprng_generate(gens[i], k0, cnt, oc[o:], orr[o:], stream=streams[j % 4])
+        torch.cuda.synchronize()
+        plain_s = time.perf_counter() - t1
+        for s in streams:
+            R.rsaprng_check_device_error(s)
     # spot check against the oracle (untimed)
     import numpy as np
 
@@ -277,10 +282,11 @@ def run_batched_uneven(R, torch, stream, steps):
     res = {"workload": "10000 instances, e from {3,5,7,17,257,65537}, lengths log-uniform in "
                        "[2^8, 2^22], k0 < 2^40, %d outputs u64+f64" % total,
            "batched_gnumbers_per_s": batched, "batched_ms": ms,
-           "plain_per_request_gnumbers_per_s": total / plain_s / 1e9,
-           "batched_vs_plain": (total / (ms / 1e3)) / (total / plain_s),
+           "plain_per_request_gnumbers_per_s": total / plain_s / 1e9 if plain_s else None,
+           "batched_vs_plain": (total / (ms / 1e3)) / (total / plain_s) if plain_s else None,
            "config": best.as_dict(), "verified_samples": bool(ok)}
-    log("batched uneven: %.1f Gnum/s graph vs %.1f plain" % (batched, res["plain_per_request_gnumbers_per_s"]))
+    log("batched uneven: %.1f Gnum/s graph" % batched +
+        (" vs %.1f plain" % res["plain_per_request_gnumbers_per_s"] if plain_s else ""))
     del b, oc, orr
     torch.cuda.empty_cache()
     return res
@@ -569,6 +575,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device five times (counter calibration)")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only the batched uneven workload, without the plain per-request "
+                         "launches (with --config: that configuration, no autotuning)")
     ap.add_argument("--config", default="",
                     help="fixed kernel configuration 'variant,lanes,per_lane,persistent[,prefix[,r]]' "
                          "instead of the autotuner (variant 1 = Montgomery-64, 2 = CRT; prefix 0 "
@@ -600,6 +609,17 @@ def main():
     R.lib()
     torch.cuda.set_device(0)
     stream = torch.cuda.Stream()
+    fixed = None
+    if args.config:
+        f = [int(x) for x in args.config.split(",")] + [0, 0]
+        v, lanes, per, pers, prefix, r = f[:6]
+        fixed = R.config(variant=v, lanes_per_tile=lanes, per_lane=per, persistent=pers,
+                         order=pers, prefix=prefix, chunks_per_wave=r)
+    if args.batched_only:
+        res = run_batched_uneven(R, torch, stream, args.steps, cfg=fixed, plain=False)
+        print(json.dumps(res))
+        return
+
     insts = inputs.config2()
     pool = R.Pool.from_instances(insts)
     reqs = R.pool_reqs(config2_requests())
@@ -607,11 +627,8 @@ def main():
     oc = torch.empty(N, dtype=torch.int64, device="cuda")
     orr = torch.empty(N, dtype=torch.float64, device="cuda")
 
-    if args.config:
-        f = [int(x) for x in args.config.split(",")] + [0, 0]
-        v, lanes, per, pers, prefix, r = f[:6]
-        best = R.config(variant=v, lanes_per_tile=lanes, per_lane=per, persistent=pers, order=pers,
-                        prefix=prefix, chunks_per_wave=r)
+    if fixed is not None:
+        best = fixed
         log("fixed config", best.as_dict())
     else:
         cache = os.environ.get("RSAPRNG_TUNE_CACHE")
