@@ -96,10 +96,13 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   if (lane == 0) a.s_tile[t] = s_tile;
 }
 
-// One wave per chain: excl[chunk] = message before the wave chunk.  Lane t
-// takes tile t of a group of 64: the tile total from its chunk sums, a wave
-// scan of the totals, then the tile's chunks in order from the message before
-// the tile (the serial part is one scan per 64 tiles, not per 64 chunks).
+// One wave per chain: excl[chunk] = message before the wave chunk.  A chain
+// lies inside one block of 2^20 indices, so it has at most 2^20 / 512 = 2048
+// chunks: lane l takes a run of up to kScanPer = 32 consecutive chunks, loads
+// their sums at once, and after one wave scan of the run totals writes the
+// run's prefixes in order.  A longer chain (none is planned) would take further
+// rounds of 2048 chunks, carrying the message.
+constexpr u32 kScanPer = 32;
 __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const int lane = threadIdx.x & 63;
   const u32 c = uniform(blockIdx.x * 4 + (threadIdx.x >> 6));
@@ -109,23 +112,26 @@ __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const u32 first = cst(&a.chain[c].first)[0];
   const u64 n = cst(&a.inst[cst(&a.chain[c].inst)[0]].n)[0];
   const int nw_log2 = a.tile_log2 - a.chunk_log2;
-  const int CH = 1 << nw_log2;  // chunks per tile
+  const u64 q_first = (u64)first << nw_log2;         // first chunk of the chain
+  const u64 nq = (u64)ntiles << nw_log2;             // chunks of the chain
   u64 E = cst(&a.cstart[c].m_base)[0];
-  for (u64 base = 0; base < ntiles; base += 64) {
-    const u64 t = base + lane;
-    const bool live = t < ntiles;
-    const u64 q0 = ((u64)first + t) << nw_log2;  // first chunk of tile t
+  for (u64 base = 0; base < nq; base += 64 * kScanPer) {
+    const u64 left = nq - base;
+    const u64 per = left >= 64 * kScanPer ? kScanPer : (left + 63) / 64;  // <= kScanPer
+    const u64 q0 = base + (u64)lane * per;           // this lane's run [q0, q1)
+    const u64 q1 = q0 + per < left + base ? q0 + per : left + base;
+    u64 v[kScanPer];
+#pragma unroll
+    for (u32 j = 0; j < kScanPer; ++j) v[j] = q0 + j < q1 ? a.agg[q_first + q0 + j] : 0;
     u64 tot = 0;
-    if (live)
-      for (int j = 0; j < CH; ++j) tot = addmod(tot, a.agg[q0 + j], n);
+#pragma unroll
+    for (u32 j = 0; j < kScanPer; ++j) tot = addmod(tot, v[j], n);
     const u64 incl = wave_scan_mod(tot, n);
-    if (live) {
-      u64 x = addmod(E, submod(incl, tot, n), n);  // message before tile t
-      for (int j = 0; j < CH; ++j) {
-        const u64 v = a.agg[q0 + j];
-        a.excl[q0 + j] = x;
-        x = addmod(x, v, n);
-      }
+    u64 x = addmod(E, submod(incl, tot, n), n);      // message before the run
+#pragma unroll
+    for (u32 j = 0; j < kScanPer; ++j) {
+      if (q0 + j < q1) a.excl[q_first + q0 + j] = x;
+      x = addmod(x, v[j], n);
     }
     E = addmod(E, lane_value(incl, 63), n);
   }
