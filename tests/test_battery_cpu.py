@@ -78,6 +78,59 @@ def test_oracle_battery_matches_definition():
     assert {int(i): int(v) for i, v in enumerate(got["maxt"]) if v} == maxt
 
 
+# The serial test in D dimensions (Tests section, D = 2 .. 6): tuples of D
+# consecutive outputs inside each aligned block of 8 indices, at offsets
+# 0, D, 2D, ... while the tuple fits in the block, with b bins per coordinate;
+# a cell is the tuple's mixed-radix number, first index most significant.
+SERIAL = {2: 1024, 3: 100, 4: 32, 5: 16, 6: 10}
+
+
+def _serial_cells(x, d, b):
+    cells = []
+    for off in range(0, 8 - d + 1, d):
+        cell = 0
+        for v in x[off:off + d]:
+            cell = cell * b + _bin(v, b)
+        cells.append(cell)
+    return cells
+
+
+def test_serial_tables_match_definition():
+    inst = inputs.config1()
+    # ragged at both ends (not 8-aligned), crossing the re-seeding at 2^20
+    k0, count = (1 << 20) - 4093, 8190
+    _, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, count)
+    got = oracle.battery([(inst, k0, count)])
+    last = k0 + count - 1
+    want = {d: {} for d in SERIAL}
+    blocks = 0
+    for k8 in range(-(-k0 // 8) * 8, last - 6, 8):
+        x = [float(v) for v in r[k8 - k0:k8 - k0 + 8]]
+        blocks += 1
+        for d, b in SERIAL.items():
+            for c in _serial_cells(x, d, b):
+                want[d][c] = want[d].get(c, 0) + 1
+    assert blocks == (last + 1) // 8 - -(-k0 // 8)
+    for d, b in SERIAL.items():
+        tab = got["serial%d" % d]
+        assert tab.size >= b ** d
+        have = {int(i): int(v) for i, v in zip(np.nonzero(tab)[0], tab[np.nonzero(tab)[0]])}
+        assert have == want[d], "serial D=%d" % d
+        assert sum(have.values()) == blocks * (8 // d)
+
+
+def test_serial_cell_order_detects_transposition():
+    # the restatement must tell a first-index-most-significant cell from its
+    # reverse and from a wrong radix, so a consistent misreading of either
+    # in the oracle fails the test above
+    x = [0.015, 0.34, 0.72, 0.5, 0.99, 0.001, 0.25, 0.6]
+    assert _serial_cells(x, 3, 100) == [1 * 10000 + 34 * 100 + 72, 50 * 10000 + 99 * 100 + 0]
+    assert _serial_cells(x, 6, 10) == [((((0 * 10 + 3) * 10 + 7) * 10 + 5) * 10 + 9) * 10 + 0]
+    assert _serial_cells(x, 5, 16) == [((((0 * 16 + 5) * 16 + 11) * 16 + 8) * 16 + 15)]
+    assert _serial_cells(x, 4, 32) == [(((0 * 32 + 10) * 32 + 23) * 32 + 16),
+                                       (((31 * 32 + 0) * 32 + 8) * 32 + 19)]
+
+
 def test_oracle_collisions_and_gaps_match_definition():
     inst = inputs.config1()
     k0, count = (1 << 14) * 3 - 777, (1 << 14) * 3 + 1000   # three whole trials, ragged ends

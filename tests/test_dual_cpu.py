@@ -7,6 +7,7 @@ import random
 import pytest
 
 import oracle
+from crt_helpers import combined_exponent as _combined
 
 
 @pytest.fixture(scope="module")
@@ -14,15 +15,6 @@ def R():
     from paper_1811_11629_amd import rsaprng
     rsaprng.lib()
     return rsaprng
-
-
-def _combined(p, q, ep, eq):
-    a, b = p - 1, q - 1
-    g = math.gcd(a, b)
-    assert (ep - eq) % g == 0
-    t = ((eq - ep) // g * pow(a // g, -1, b // g)) % (b // g)
-    lcm = a // g * b
-    return (ep + a * t) % lcm or lcm
 
 
 def _safe_primes(count, seed):
