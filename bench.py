@@ -566,6 +566,55 @@ def run_param_gen(R, torch, stream):
     return res
 
 
+def run_issue_probe(R, torch, stream, iters=1 << 16, store_elems=1 << 30):
+    """The ceilings behind the roofline figures, measured on this device: the
+    issue rate of each VALU instruction class the kernels use (lane-instructions
+    per second, and the clock it implies if the class issues one lane-operation
+    per lane and cycle), and the store bandwidth of the tile kernels' output
+    pattern and of a plain linear write."""
+    res = {"nominal_lane_instr_per_s": VALU_PEAK_TOPS * 1e12,
+           "issue": {}, "store": {}}
+    for name, kind in R.PROBES.items():
+        R.rsaprng_probe(kind, 64, stream=stream)            # warm-up
+        times = []
+        for _ in range(3):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            work = R.rsaprng_probe(kind, iters, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = sorted(times)[1]
+        rate = work / (ms / 1e3)
+        res["issue"][name] = {"lane_instr_per_s": rate, "ms": ms,
+                              "frac_of_nominal": rate / (VALU_PEAK_TOPS * 1e12),
+                              "implied_ghz_if_full_rate": rate / (256 * 64) / 1e9}
+        log("issue %-16s %.2f T lane-instr/s (%.3f of nominal, %.3f ms)" % (
+            name, rate / 1e12, rate / (VALU_PEAK_TOPS * 1e12), ms))
+    oc = torch.empty(store_elems, dtype=torch.int64, device="cuda")
+    orr = torch.empty(store_elems, dtype=torch.float64, device="cuda")
+    for name, kind in (("tile_pattern", R.PROBE_STORE_TILE), ("linear", R.PROBE_STORE_LINEAR)):
+        R.rsaprng_probe(kind, store_elems, oc, orr, stream=stream)
+        times = []
+        for _ in range(5):
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            work = R.rsaprng_probe(kind, store_elems, oc, orr, stream=stream)
+            b.record(stream)
+            b.synchronize()
+            times.append(a.elapsed_time(b))
+        ms = sorted(times)[2]
+        res["store"][name] = {"bytes": work, "ms": ms, "gb_per_s": work / (ms / 1e3) / 1e9,
+                              "frac_of_hbm_peak": work / (ms / 1e3) / 1e9 / HBM_PEAK_GBS}
+        log("store %-12s %.0f GB/s (%.3f ms for %.1f GiB)" % (
+            name, work / (ms / 1e3) / 1e9, ms, work / 2 ** 30))
+    ok = bool((oc[:8].cpu() == torch.arange(8)).all())
+    del oc, orr
+    torch.cuda.empty_cache()
+    res["store_values_checked"] = ok
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -575,6 +624,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only copy BYTES device-to-device five times (counter calibration)")
+    ap.add_argument("--issue-probe", action="store_true",
+                    help="only the throughput probes (VALU issue rates, store bandwidth)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched uneven workload, without the plain per-request "
                          "launches (with --config: that configuration, no autotuning)")
@@ -615,6 +666,9 @@ def main():
         v, lanes, per, pers, prefix, r = f[:6]
         fixed = R.config(variant=v, lanes_per_tile=lanes, per_lane=per, persistent=pers,
                          order=pers, prefix=prefix, chunks_per_wave=r)
+    if args.issue_probe:
+        print(json.dumps(run_issue_probe(R, torch, stream)), flush=True)
+        return
     if args.batched_only:
         res = run_batched_uneven(R, torch, stream, args.steps, cfg=fixed, plain=False)
         print(json.dumps(res))

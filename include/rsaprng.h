@@ -444,6 +444,41 @@ int rsaprng_check_device_error(void* stream);
 int rsaprng_debug_encrypt(uint64_t p, uint64_t q, uint64_t e, int variant, const uint64_t* m,
                           uint64_t* c, double* r, uint64_t count, void* stream);
 
+/* ---------------------------------------------------------------------------
+ * Throughput probes (measurement only; nothing is generated).  The roofline
+ * figures of the benchmark compare the generator's kernels with ceilings that
+ * these measure on the device at hand.
+ *  - Issue probes (kind RSAPRNG_PROBE_FMA_F64 .. RSAPRNG_PROBE_MUL_U32_U24):
+ *    every lane of 8 waves per SIMD on every compute unit runs n loop trips of
+ *    32 instructions of one class (8 independent dependency chains of 4), so
+ *    the launch is bound by that class's issue rate.  The out pointers are
+ *    ignored (a per-device sink of the library receives one word per lane).
+ *    1 <= n <= 2^32.  *work = the lane-instructions of the class issued.
+ *  - Store probes: n elements written to each of out_u64 and out_f64
+ *    (device, 16-byte aligned, n a positive multiple of 2^20, n <= 2^36) with
+ *    the chain-serial tile kernels' store pattern (RSAPRNG_PROBE_STORE_TILE:
+ *    one 512-lane work-group per 2^20 elements, 16-byte non-temporal stores,
+ *    each store instruction covering 1 KiB) or a plain linear write
+ *    (RSAPRNG_PROBE_STORE_LINEAR).  *work = the bytes written, 16 n.
+ * Enqueued on `stream`; the caller times the launch.  RSAPRNG_E_ARG for an
+ * unknown kind or a bad n, RSAPRNG_E_ALIGN for misaligned store buffers.
+ * ------------------------------------------------------------------------ */
+#define RSAPRNG_PROBE_FMA_F64 0
+#define RSAPRNG_PROBE_MUL_F64 1
+#define RSAPRNG_PROBE_ADD_F64 2
+#define RSAPRNG_PROBE_RNDNE_F64 3
+#define RSAPRNG_PROBE_MAD_U64_U32 4
+#define RSAPRNG_PROBE_MUL_LO_U32 5
+#define RSAPRNG_PROBE_MUL_HI_U32 6
+#define RSAPRNG_PROBE_ADD_U32 7
+#define RSAPRNG_PROBE_CVT_F64_U32 8
+#define RSAPRNG_PROBE_LSHL_ADD_U64 9
+#define RSAPRNG_PROBE_MUL_U32_U24 10
+#define RSAPRNG_PROBE_STORE_TILE 16
+#define RSAPRNG_PROBE_STORE_LINEAR 17
+int rsaprng_probe(int kind, uint64_t n, uint64_t* out_u64, double* out_f64, double* work,
+                  void* stream);
+
 /* Library version string. */
 const char* rsaprng_version(void);
 

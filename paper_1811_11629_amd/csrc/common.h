@@ -162,5 +162,10 @@ int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t*
                          double* r, uint64_t count, void* stream);
 int kernel_max_grid(const KernelShape& shape, int* wg_per_cu);
 int launch_checksum(const uint64_t* p, uint64_t n, uint64_t* out_dev, void* stream);
+// Throughput probes (k_probe.hip).
+int probe_grid(int ncu);
+uint64_t probe_threads(int ncu);
+uint64_t probe_ops_per_thread(uint64_t iters);
+int launch_probe(int kind, int ncu, uint64_t n, uint64_t* out_u64, double* out_f64, void* stream);
 
 }  // namespace rsaprng

@@ -1673,6 +1673,39 @@ int rsaprng_check_device_error(void* stream) {
   return RSAPRNG_OK;
 }
 
+int rsaprng_probe(int kind, uint64_t n, uint64_t* out_u64, double* out_f64, double* work,
+                  void* stream) {
+  if (!work) return RSAPRNG_E_NULL;
+  Device* d;
+  int rc;
+  if ((rc = device_get(&d))) return rc;
+  if (kind >= RSAPRNG_PROBE_FMA_F64 && kind <= RSAPRNG_PROBE_MUL_U32_U24) {
+    if (n == 0 || n > (1ull << 32)) return RSAPRNG_E_ARG;
+    // one sink word per lane, per device, kept for the life of the process
+    static std::map<int, uint64_t*> sinks;
+    uint64_t* sink = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_mu);
+      uint64_t*& s = sinks[d->id];
+      if (!s && hipMalloc(&s, probe_threads(d->ncu) * 8) != hipSuccess) {
+        s = nullptr;
+        return RSAPRNG_E_OOM;
+      }
+      sink = s;
+    }
+    *work = (double)probe_threads(d->ncu) * (double)probe_ops_per_thread(n);
+    return launch_probe(kind, d->ncu, n, sink, nullptr, stream);
+  }
+  if (kind == RSAPRNG_PROBE_STORE_TILE || kind == RSAPRNG_PROBE_STORE_LINEAR) {
+    if (!out_u64 || !out_f64) return RSAPRNG_E_NULL;
+    if (((uintptr_t)out_u64 & 15) || ((uintptr_t)out_f64 & 15)) return RSAPRNG_E_ALIGN;
+    if (n == 0 || (n & ((1ull << 20) - 1)) || n > (1ull << 36)) return RSAPRNG_E_ARG;
+    *work = 16.0 * (double)n;
+    return launch_probe(kind, d->ncu, n, out_u64, out_f64, stream);
+  }
+  return RSAPRNG_E_ARG;
+}
+
 int rsaprng_debug_encrypt(uint64_t p, uint64_t q, uint64_t e, int variant, const uint64_t* m,
                           uint64_t* c, double* r, uint64_t count, void* stream) {
   if (!m && count) return RSAPRNG_E_NULL;

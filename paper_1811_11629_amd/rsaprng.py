@@ -159,6 +159,7 @@ _SIGS = {
     "rsaprng_check_device_error": (_i32, [_vp]),
     "rsaprng_debug_encrypt": (_i32, [_u64, _u64, _u64, _i32, _vp, _vp, _vp, _u64, _vp]),
     "rsaprng_version": (C.c_char_p, []),
+    "rsaprng_probe": (_i32, [_i32, _u64, _vp, _vp, C.POINTER(_dbl), _vp]),
 }
 
 
@@ -538,6 +539,21 @@ def rsaprng_next_primes(x, out, safe: bool = False, exps=(), stream=None) -> Non
     arr = (C.c_uint32 * max(1, len(exps)))(*exps)
     _check(lib().rsaprng_next_primes(_ptr(x), n, 1 if safe else 0, arr, len(exps), _ptr(out),
                                      _stream(stream)), "rsaprng_next_primes")
+
+
+PROBES = {"v_fma_f64": 0, "v_mul_f64": 1, "v_add_f64": 2, "v_rndne_f64": 3,
+          "v_mad_u64_u32": 4, "v_mul_lo_u32": 5, "v_mul_hi_u32": 6, "v_add_u32": 7,
+          "v_cvt_f64_u32": 8, "v_lshl_add_u64": 9, "v_mul_u32_u24": 10}
+PROBE_STORE_TILE, PROBE_STORE_LINEAR = 16, 17
+
+
+def rsaprng_probe(kind: int, n: int, out_u64=None, out_f64=None, stream=None) -> float:
+    """Enqueue one throughput probe; returns the work it does (lane-instructions
+    of the probed class, or bytes written)."""
+    work = C.c_double(0)
+    _check(lib().rsaprng_probe(kind, n, _ptr(out_u64), _ptr(out_f64), C.byref(work),
+                               _stream(stream)), "rsaprng_probe")
+    return work.value
 
 
 class Server:
