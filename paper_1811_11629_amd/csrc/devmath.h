@@ -3,7 +3,9 @@
 // and the CRT form of the exponentiation with residues held in binary64.
 //
 // On gfx950 v_mad_u64_u32, v_mul_lo_u32 and v_mul_hi_u32 issue at the full
-// VALU rate (as do binary64 fma/mul/rndne), so the 64-bit products below are
+// VALU rate, as do binary64 fma/mul/rndne (the throughput probes of
+// rsaprng_probe measure 0.90-0.96 of 256 CUs x 64 lanes x 2.4 GHz for each of
+// these classes on an MI355X), so the 64-bit products below are
 // written as 32x32->64 multiply-adds that the compiler maps onto
 // v_mad_u64_u32; every bound on an intermediate is stated where it is formed.
 #pragma once
