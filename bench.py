@@ -38,6 +38,46 @@ VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12   # lane-operations/s: 256 CUs x 64 lan
 B = 1 << 20
 
 
+def ladder_length(e: int) -> int:
+    """L(e): squarings plus multiplies of the binary ladder for e."""
+    return e.bit_length() - 1 + bin(e).count("1") - 1
+
+
+def alg_instr(e: int, consume: bool = False) -> int:
+    """Algorithmic VALU lane-instructions per output for exponent e: the cheaper
+    of the two forms of the method's arithmetic (64-bit Montgomery products, 18
+    per product plus 21 for the skip step, the add mod n, the conversion and the
+    quotient; or CRT residues in binary64, 12 per ladder step over both primes
+    plus 49 for the skip step, the residue updates, Garner's recombination, the
+    conversion and the quotient), plus 12 for the fused statistics in consume
+    mode."""
+    L = ladder_length(e)
+    return min(18 * L + 21, 12 * L + 49) + (12 if consume else 0)
+
+
+def roofline_of(counts_by_e, seconds, consume, kernel, launch_what):
+    """Roofline entry for a launch over outputs of several exponents: the binding
+    bound of max(bytes / HBM peak, algorithmic instructions / VALU peak)."""
+    n = sum(counts_by_e.values())
+    instr = sum(c * alg_instr(e, consume) for e, c in counts_by_e.items())
+    nbytes = 0 if consume else 16 * n
+    t_alu = instr / (VALU_PEAK_TOPS * 1e12)
+    t_hbm = nbytes / (HBM_PEAK_GBS * 1e9)
+    out = {"kernel": kernel, "avg_launch_ms": seconds * 1e3, "launch": launch_what,
+           "outputs_per_launch": n, "algorithmic_instr_per_output": instr / n,
+           "algorithmic_bytes_per_output": nbytes / n,
+           "bound_gnumbers_per_s": n / max(t_alu, t_hbm) / 1e9}
+    if t_hbm >= t_alu:
+        ach = nbytes / seconds / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": ach / HBM_PEAK_GBS, "traffic": None})
+    else:
+        ach = instr / seconds / 1e12
+        out.update({"bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                    "unit": "T lane-instr/s", "frac": ach / VALU_PEAK_TOPS, "traffic": None})
+    return out
+
+
 def log(*a):
     print("[bench]", *a, file=sys.stderr, flush=True)
 
@@ -112,17 +152,17 @@ def time_graph(batch, stream, steps, warmup, torch):
     return wall, kms
 
 
-def tile_kernel_name(cfg, exponent=0) -> str:
-    """The tile kernel of a configuration, as rocprofv3 lists it.  A launch whose
-    instances all have e = 3 takes the chain-serial CRT kernels specialised to it
-    (two chunks per wave), whose name carries the exponent."""
+def tile_kernel_name(cfg, exponent=0, mode="generate") -> str:
+    """The tile kernel of a configuration, as rocprofv3 lists it.  A generate
+    launch whose instances all have e = 3 takes the chain-serial CRT kernels
+    specialised to it (two chunks per wave), whose name carries the exponent."""
     form = {0: "k_gen2", 1: "k_gen1", 2: "k_gen3"}[cfg.prefix]
     r = "" if cfg.prefix == 1 else ", %d" % cfg.chunks_per_wave
-    ek = ", 3" if (exponent == 3 and cfg.prefix == 2 and cfg.variant == 2
+    ek = ", 3" if (mode == "generate" and exponent == 3 and cfg.prefix == 2 and cfg.variant == 2
                    and cfg.chunks_per_wave == 2) else ""
-    return "%s<%d, %d%s, %d, 0%s> (%s, generate)" % (
-        form, cfg.lanes_per_tile, cfg.per_lane, r, cfg.variant, ek,
-        "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64")
+    return "%s<%d, %d%s, %d, %d%s> (%s, %s)" % (
+        form, cfg.lanes_per_tile, cfg.per_lane, r, cfg.variant, 0 if mode == "generate" else 1,
+        ek, "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64", mode)
 
 
 def config2_requests():
@@ -192,6 +232,100 @@ def cpu_baseline(insts, budget_outputs):
             "single_thread_value": single}
 
 
+def cpu_host_info():
+    """The host's processor model, clock and thread count, from lscpu (or
+    /proc/cpuinfo)."""
+    import subprocess
+    info = {"nproc": os.cpu_count()}
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            k, _, v = line.partition(":")
+            k, v = k.strip(), v.strip()
+            if k in ("Model name", "CPU max MHz", "CPU MHz", "Socket(s)", "Core(s) per socket",
+                     "Thread(s) per core"):
+                info[k] = v
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if "Model name" not in info:
+        try:
+            with open("/proc/cpuinfo") as f:
+                for line in f:
+                    if line.startswith("model name"):
+                        info["Model name"] = line.split(":", 1)[1].strip()
+                        break
+        except OSError:
+            pass
+    return info
+
+
+def _oracle_rate(work, threads, fn):
+    """Outputs per second (G) of fn over the work items on `threads` host threads."""
+    import concurrent.futures as cf
+    t0 = time.perf_counter()
+    if threads == 1:
+        n = sum(fn(w) for w in work)
+    else:
+        with cf.ThreadPoolExecutor(threads) as ex:
+            n = sum(ex.map(fn, work))
+    dt = time.perf_counter() - t0
+    return n / dt / 1e9, n, dt
+
+
+def cpu_baselines(threads=None):
+    """The oracle, unmodified, on bounded samples of the exponent sweep (fused
+    statistics), the batched uneven workload and the served request trace, at
+    one thread and at the host's thread share."""
+    import numpy as np
+
+    import inputs
+    import oracle
+    threads = threads or min(16, os.cpu_count() or 1)
+    oracle.lib()
+    out = {"host": cpu_host_info(), "threads": threads}
+
+    def consume(w):
+        inst, k0, cnt = w
+        oracle.consume(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, cnt)
+        return cnt
+
+    def generate(w):
+        inst, k0, cnt = w
+        oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, cnt)
+        return cnt
+
+    base = inputs.config3()
+    sweep = {}
+    for e in inputs.SWEEP_EXPONENTS:
+        insts = [inputs.Instance(b.p, b.q, e, b.m0) for b in base[:64 * threads]]
+        work = [(i, 0, 1 << 18) for i in insts]
+        v, n, dt = _oracle_rate(work, threads, consume)
+        v1, n1, dt1 = _oracle_rate(work[:32], 1, consume)
+        sweep["e%d" % e] = {"value": v, "single_thread_value": v1,
+                            "sample": "%d instances x 2^18 outputs (fused statistics): %.2f s; "
+                                      "one thread: 32 instances, %.2f s" % (len(work), dt, dt1)}
+    out["exponent_sweep_consume"] = sweep
+    insts4, reqs4 = inputs.config4()
+    work = [(insts4[r.inst], r.k0, r.count) for r in reqs4[::10]]
+    v, n, dt = _oracle_rate(work, threads, generate)
+    v1, n1, dt1 = _oracle_rate(work[::20], 1, generate)
+    out["batched_uneven"] = {"value": v, "single_thread_value": v1,
+                             "sample": "every 10th request (%d requests, %d outputs, each with its "
+                                       "lead-in walk): %.2f s; one thread: every 200th (%d "
+                                       "outputs), %.2f s" % (len(work), n, dt, n1, dt1)}
+    insts5, rng5 = inputs.config5_instances(100000)
+    trace = inputs.config5_requests(rng5, len(insts5), 256)
+    work = [(insts5[r.inst], r.k0, r.count) for r in trace]
+    v, n, dt = _oracle_rate(work, threads, generate)
+    v1, n1, dt1 = _oracle_rate(work[:16], 1, generate)
+    out["served"] = {"value": v, "single_thread_value": v1,
+                     "sample": "256 served requests back to back (%d outputs): %.2f s; one "
+                               "thread: 16 of them (%d outputs), %.2f s" % (n, dt, n1, dt1)}
+    out["unit"] = "Gnumbers/s"
+    out["kind"] = "oracle"
+    return out
+
+
 def run_plain_config2(R, gens, oc, orr, torch, reps=2):
     streams = [torch.cuda.Stream() for _ in range(4)]
     for g in gens[:8]:
@@ -209,29 +343,84 @@ def run_plain_config2(R, gens, oc, orr, torch, reps=2):
     return best
 
 
-def run_consume_sweep(R, torch, stream, steps):
+def run_consume_sweep(R, torch, stream, steps, exponents=None, cfg=None):
     import inputs
     base = inputs.config3()
     out = {}
     st = R.stats_tensor(len(base))
-    for e in inputs.SWEEP_EXPONENTS:
+    for e in exponents or inputs.SWEEP_EXPONENTS:
         insts = [inputs.Instance(i.p, i.q, e, i.m0) for i in base]
         pool = R.Pool.from_instances(insts)
         reqs = [(i, 0, 1 << 18, i) for i in range(len(insts))]
-        best, _ = R.rsaprng_autotune(pool, reqs, R.MODE_CONSUME, stats=st, stream=stream)
+        if cfg is None:
+            best, _ = R.rsaprng_autotune(pool, reqs, R.MODE_CONSUME, stats=st, stream=stream)
+        else:
+            best = cfg
         b = R.Batch(pool, reqs, R.MODE_CONSUME, stats=st, cfg=best, stream=stream)
         wall, kms = time_graph(b, stream, max(2, steps // 4), 1, torch)
         b.check()
         n = len(insts) << 18
         ms = sum(kms) / len(kms)
         out["e%d" % e] = {"gnumbers_per_s": n / (ms / 1e3) / 1e9, "ms_per_launch": ms,
-                          "variant": int(best.variant), "config": best.as_dict()}
+                          "variant": int(best.variant), "config": best.as_dict(),
+                          "roofline": roofline_of({e: n}, ms / 1e3, True,
+                                                  tile_kernel_name(best, mode="consume"),
+                                                  "one graph replay (statistics zeroing, chain "
+                                                  "setup, prefix pass, tile kernel, finalisation)")}
         log("consume e=%d: %.1f Gnum/s (%.3f ms)" % (e, out["e%d" % e]["gnumbers_per_s"], ms))
         del b, pool
     return out
 
 
-def run_batched_uneven(R, torch, stream, steps, cfg=None, plain=True):
+def verify_requests(insts, reqs, oc, orr, cap_s=120.0, threads=None):
+    """Untimed: every output of the given requests, (inst, k0, count, out_off),
+    compared bit for bit with the oracle on the host's threads.  Requests are
+    taken in the order j = 0, 4, 8, ..., then 1, 5, ..., 2, 6, ..., 3, 7, ...,
+    so that if the time cap stops the comparison early, what was compared is
+    every 4th request first, a stated deterministic subset."""
+    import collections
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    threads = threads or min(16, os.cpu_count() or 1)
+    order = [j for s in range(4) for j in range(s, len(reqs), 4)]
+
+    def one(j):
+        i, k0, cnt, o = reqs[j]
+        inst = insts[i]
+        cref, rref = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, cnt)
+        cg = oc[o:o + cnt].cpu().numpy().view(np.uint64)
+        rg = orr[o:o + cnt].cpu().numpy().view(np.uint64)
+        return bool(np.array_equal(cg, cref) and np.array_equal(rg, rref.view(np.uint64))), cnt
+
+    t0 = time.perf_counter()
+    ok, n_out, n_req = True, 0, 0
+    with cf.ThreadPoolExecutor(threads) as ex:
+        pend = collections.deque()
+        for j in order:
+            if time.perf_counter() - t0 > cap_s:
+                break
+            pend.append(ex.submit(one, j))
+            while len(pend) >= 2 * threads:
+                eq, cnt = pend.popleft().result()
+                ok &= eq
+                n_out += cnt
+                n_req += 1
+        for f in pend:
+            eq, cnt = f.result()
+            ok &= eq
+            n_out += cnt
+            n_req += 1
+    return {"all_equal": bool(ok), "outputs_compared": n_out, "requests_compared": n_req,
+            "requests": len(reqs), "complete": n_req == len(reqs),
+            "seconds": time.perf_counter() - t0, "threads": threads,
+            "order": "requests j = 0, 4, 8, ... first, then 1 mod 4, 2 mod 4, 3 mod 4; "
+                     "time cap %.0f s" % cap_s}
+
+
+def run_batched_uneven(R, torch, stream, steps, cfg=None, plain=True, verify_cap_s=120.0):
     import inputs
     t0 = time.perf_counter()
     insts, reqs4 = inputs.config4()
@@ -253,6 +442,15 @@ def run_batched_uneven(R, torch, stream, steps, cfg=None, plain=True):
     b.check()
     ms = sum(kms) / len(kms)
     batched = total / (ms / 1e3) / 1e9
+    # untimed: the graph's own outputs against the oracle, before anything else
+    # writes these buffers
+    stream.synchronize()
+    ver = verify_requests(insts, reqs, oc, orr, cap_s=verify_cap_s)
+    log("batched uneven verified: %d of %d outputs (%d requests) in %.1f s, equal: %s" % (
+        ver["outputs_compared"], total, ver["requests_compared"], ver["seconds"], ver["all_equal"]))
+    by_e = {}
+    for r in reqs4:
+        by_e[insts[r.inst].e] = by_e.get(insts[r.inst].e, 0) + r.count
     plain_s = None
     if plain:
         # plain per-request launches, round-robin over 4 streams
@@ -266,25 +464,16 @@ def run_batched_uneven(R, torch, stream, steps, cfg=None, plain=True):
         plain_s = time.perf_counter() - t1
         for s in streams:
             R.rsaprng_check_device_error(s)
-    # spot check against the oracle (untimed)
-    import numpy as np
-
-    import oracle
-    ok = True
-    rng = np.random.default_rng(11)
-    for j in rng.choice(len(reqs), 24, replace=False):
-        i, k0, cnt, o = reqs[int(j)]
-        kk = int(rng.integers(cnt))
-        inst = insts[i]
-        c, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0 + kk, 1)
-        ok &= (int(oc[o + kk].item()) & ((1 << 64) - 1)) == int(c[0])
-        ok &= float(orr[o + kk].item()) == float(r[0])
     res = {"workload": "10000 instances, e from {3,5,7,17,257,65537}, lengths log-uniform in "
                        "[2^8, 2^22], k0 < 2^40, %d outputs u64+f64" % total,
            "batched_gnumbers_per_s": batched, "batched_ms": ms,
            "plain_per_request_gnumbers_per_s": total / plain_s / 1e9 if plain_s else None,
            "batched_vs_plain": (total / (ms / 1e3)) / (total / plain_s) if plain_s else None,
-           "config": best.as_dict(), "verified_samples": bool(ok)}
+           "config": best.as_dict(), "outputs_by_exponent": {str(k): v for k, v in by_e.items()},
+           "verified": ver,
+           "roofline": roofline_of(by_e, ms / 1e3, False, tile_kernel_name(best),
+                                   "one graph replay (chain setup, prefix pass over the "
+                                   "lead-in, tile kernel)")}
     log("batched uneven: %.1f Gnum/s graph" % batched +
         (" vs %.1f plain" % res["plain_per_request_gnumbers_per_s"] if plain_s else ""))
     del b, oc, orr
@@ -306,6 +495,51 @@ def tune_served(R, torch, stream, pool, inst, k0, cnt, chunk):
     del oc, orr
     torch.cuda.empty_cache()
     return best, ms
+
+
+def verify_served(srv, insts, inst, k0, cnt, threads=None):
+    """Untimed: submit the requests (inst, k0, cnt) together, wait for all of
+    them, and compare every output of each (read back from the server's arena)
+    bit for bit with the oracle, on the host's threads; then release them."""
+    import concurrent.futures as cf
+
+    import numpy as np
+
+    import oracle
+    threads = threads or min(16, os.cpu_count() or 1)
+    base = 1 << 40
+    n = len(inst)
+    for j in range(n):
+        rc = srv.submit(int(inst[j]), int(k0[j]), int(cnt[j]), base + j)
+        if rc != 0:
+            raise RuntimeError("rsaprng_server_submit returned %d" % rc)
+    done = set()
+    t0 = time.perf_counter()
+    while len(done) < n:
+        for c in srv.poll():
+            done.add(c.tag - base)
+        if time.perf_counter() - t0 > 120:
+            raise RuntimeError("served verification: requests did not complete")
+        time.sleep(0.0005)
+
+    def one(j):
+        c = int(cnt[j])
+        cg = np.empty(c, dtype=np.uint64)
+        rg = np.empty(c, dtype=np.float64)
+        srv.read(base + j, cg, rg)
+        inst_ = insts[int(inst[j])]
+        cref, rref = oracle.generate(inst_.p, inst_.q, inst_.e, inst_.m0, inst_.s0, int(k0[j]), c)
+        return bool(np.array_equal(cg, cref) and
+                    np.array_equal(rg.view(np.uint64), rref.view(np.uint64))), c
+
+    with cf.ThreadPoolExecutor(threads) as ex:
+        res = list(ex.map(one, range(n)))
+    for j in range(n):
+        srv.release(base + j)
+    return {"all_equal": all(r[0] for r in res), "requests_compared": n,
+            "outputs_compared": sum(r[1] for r in res), "seconds": time.perf_counter() - t0,
+            "what": "%d requests of a fresh trace submitted together, every output read back "
+                    "from the arena" % n}
 
 
 def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
@@ -343,6 +577,13 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
     t_adm, t_done = srv.replay(inst, k0, cnt, np.zeros(len(inst)))
     cap = float(cnt.sum()) / float(t_done.max()) / 1e9
     res["saturated_gnumbers_per_s"] = cap
+    by_e = {}
+    for i, c in zip(inst, cnt):
+        by_e[insts[int(i)].e] = by_e.get(insts[int(i)].e, 0) + int(c)
+    res["roofline"] = roofline_of(by_e, float(t_done.max()), False,
+                                  tile_kernel_name(cfg) + " per iteration",
+                                  "the whole saturated trace (40000 requests submitted at once), "
+                                  "wall clock")
     log("served saturated: %.1f Gnum/s over %d requests" % (cap, len(inst)))
     # the same requests as plain per-request launches on one stream
     n_plain = 4000
@@ -383,6 +624,10 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
 
     res["headline"] = poisson(rho_main, 2.0, 10.0)
     res["sweep"] = [poisson(r, 1.0, 4.0) for r in sweep]
+    res["verified"] = verify_served(srv, insts, *trace(256))
+    log("served verified: %d requests, %d outputs, equal: %s" % (
+        res["verified"]["requests_compared"], res["verified"]["outputs_compared"],
+        res["verified"]["all_equal"]))
     st = srv.stats()
     res["iterations"] = st["iterations"]
     srv.close()
@@ -626,6 +871,11 @@ def main():
                     help="only copy BYTES device-to-device five times (counter calibration)")
     ap.add_argument("--issue-probe", action="store_true",
                     help="only the throughput probes (VALU issue rates, store bandwidth)")
+    ap.add_argument("--consume-only", type=int, default=0, metavar="E",
+                    help="only the exponent sweep's consume workload at exponent E (with "
+                         "--config: that configuration, no autotuning)")
+    ap.add_argument("--verify-cap", type=float, default=120.0, metavar="SECONDS",
+                    help="time cap of the batched workload's comparison with the oracle")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched uneven workload, without the plain per-request "
                          "launches (with --config: that configuration, no autotuning)")
@@ -670,7 +920,13 @@ def main():
         print(json.dumps(run_issue_probe(R, torch, stream)), flush=True)
         return
     if args.batched_only:
-        res = run_batched_uneven(R, torch, stream, args.steps, cfg=fixed, plain=False)
+        res = run_batched_uneven(R, torch, stream, args.steps, cfg=fixed, plain=False,
+                                 verify_cap_s=args.verify_cap)
+        print(json.dumps(res))
+        return
+    if args.consume_only:
+        res = run_consume_sweep(R, torch, stream, args.steps, exponents=[args.consume_only],
+                                cfg=fixed)
         print(json.dumps(res))
         return
 
@@ -727,7 +983,8 @@ def main():
         torch.cuda.empty_cache()
         extras["single_instance"] = run_single(R, torch, stream, args.steps)
         extras["exponent_sweep_consume"] = run_consume_sweep(R, torch, stream, args.steps)
-        extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps)
+        extras["batched_uneven"] = run_batched_uneven(R, torch, stream, args.steps,
+                                                      verify_cap_s=args.verify_cap)
         extras["served"] = run_served(R, torch, stream)
         extras["parameter_generation"] = run_param_gen(R, torch, stream)
         extras["battery"] = run_battery(R, torch, stream, args.steps)
@@ -736,6 +993,12 @@ def main():
     cpu = None if args.no_cpu else cpu_baseline(insts, 1024 * B)
     if cpu:
         log("cpu oracle: %.3f Gnum/s on %d threads" % (cpu["value"], cpu["cores"]))
+        cpu["host"] = cpu_host_info()
+        if not args.no_extras:
+            extras["cpu_baselines"] = cpu_baselines()
+            log("cpu oracle on the other workloads:", json.dumps(
+                {k: v["value"] for k, v in extras["cpu_baselines"].items()
+                 if isinstance(v, dict) and "value" in v}))
 
     out = {
         "metric": "Gnumbers/s (u64+FP64) and % of INT-VALU/HBM roofline; batched & served vs plain",
@@ -744,7 +1007,9 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "u64+f64", "data": "synthetic",
         "config": {"workload": "multi-instance: 1024 seeded prime pairs, e=3, 256 substreams of "
                                "2^12 per instance (k0 = j*2^12), 2^30 outputs as uint64 c_k and "
-                               "binary64 r_k, one graph-captured batch",
+                               "binary64 r_k; one prepared batch per step, launched eagerly with "
+                               "HIP events between its kernels (graph replays of the same batch "
+                               "reported beside)",
                    "instances": 1024, "outputs_per_step": N, "exponent": 3,
                    "kernel_config": best.as_dict(), "parallelism": "single GPU"},
         "roofline": roofline, "cpu_baseline": cpu, "verified": bool(verified),

@@ -178,7 +178,10 @@ typedef struct {
   uint64_t lt_half;     /* number of r_k < 0.5 */
   uint64_t count;       /* number of outputs reduced */
   double sum;           /* the exact sum rounded once to binary64 */
-  uint64_t acc32[6];    /* internal: sum * 2^128 = sum_i acc32[i] 2^(32 i) */
+  uint64_t acc32[6];    /* not a result: the kernels' exact accumulator (work-groups add
+                           32-bit digit sums here with device atomics; the finalisation
+                           normalises them into sum_fx and sum), kept in the record so a
+                           consume launch needs no scratch of its own */
   uint64_t hist[1024];
 } rsaprng_stats;
 int rsaprng_consume(rsaprng_t h, uint64_t k0, uint64_t count, rsaprng_stats* out_dev,
@@ -270,8 +273,15 @@ void rsaprng_batch_destroy(rsaprng_batch_t b);
 /* Autotuner: times every kernel configuration in its search space on this
  * request set, checks that all of them produce byte-identical outputs, and
  * writes the fastest to *best (and its time per launch in ms to *best_ms).
+ * Generate mode overwrites out_u64 / out_f64 over [0, max(out_off + count)):
+ * before each configuration's run both are filled with a sentinel, so an
+ * output a configuration failed to write would change the comparison; on
+ * return the requested elements hold the outputs and any element between them
+ * the sentinel 0xA5A5A5A5A5A5A5A5.  Consume mode overwrites the records.
  * If cache_path is non-NULL the result is stored there (JSON lines keyed by a
- * workload signature) and reused on the next call with the same signature. */
+ * signature of the library build, the device and the workload: exponent mix,
+ * request count and total outputs) and reused on the next call with the same
+ * signature. */
 int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
                      uint64_t* out_u64, double* out_f64, rsaprng_stats* stats_dev,
                      const char* cache_path, void* stream, rsaprng_config* best, double* best_ms);

@@ -26,9 +26,23 @@ SOURCES = ["k_mont_gen.hip", "k_crt_gen.hip", "k_mont_con.hip", "k_crt_con.hip",
            "k_misc.hip", "k_primes.hip", "k_probe.hip", "host.cpp", "server.cpp"]
 
 
+def source_hash() -> str:
+    """Hash of every source the library is built from (the autotuner's cache key
+    carries it, so a rebuilt library never reuses another build's choice)."""
+    import hashlib
+    h = hashlib.sha256()
+    for d in (CSRC, INCLUDE):
+        for f in sorted(os.listdir(d)):
+            if f.endswith((".h", ".hip", ".cpp")):
+                with open(os.path.join(d, f), "rb") as fh:
+                    h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, src + ".o")
-    cmd = [HIPCC, *COMMON, *DEVICE, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *COMMON, *DEVICE, '-DRSAPRNG_SOURCE_HASH="%s"' % source_hash(), "-c",
+           os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("compile failed: %s\n%s%s" % (" ".join(cmd), r.stdout, r.stderr))

@@ -162,6 +162,8 @@ int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t*
                          double* r, uint64_t count, void* stream);
 int kernel_max_grid(const KernelShape& shape, int* wg_per_cu);
 int launch_checksum(const uint64_t* p, uint64_t n, uint64_t* out_dev, void* stream);
+// p[i] = v for i < n.
+int launch_fill(uint64_t* p, uint64_t n, uint64_t v, void* stream);
 // Throughput probes (k_probe.hip).
 int probe_grid(int ncu);
 uint64_t probe_threads(int ncu);

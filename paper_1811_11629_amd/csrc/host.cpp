@@ -21,6 +21,11 @@
 
 #include "common.h"
 #include "host_internal.h"
+#include "plan_core.h"
+
+#ifndef RSAPRNG_SOURCE_HASH
+#define RSAPRNG_SOURCE_HASH "unversioned"
+#endif
 
 namespace rsaprng {
 
@@ -231,7 +236,11 @@ static std::vector<uint64_t> power_table(u64h step, size_t count) {
 }
 
 static std::mutex g_mu;
-static std::map<int, Device*> g_devices;
+// Device contexts and per-stream scratch live until the process ends: the
+// tables are held by heap objects that are never destroyed, so no static
+// destructor frees them while another thread (a server loop, an exit handler)
+// may still launch.
+static std::map<int, Device*>& g_devices = *new std::map<int, Device*>;
 
 int device_get(Device** out) {
   int dev = 0;
@@ -371,7 +380,8 @@ int Scratch::mark(int slot, void* stream) {
                                                                             : RSAPRNG_E_HIP;
 }
 
-static std::map<std::pair<int, void*>, Scratch*> g_scratch;
+static std::map<std::pair<int, void*>, Scratch*>& g_scratch =
+    *new std::map<std::pair<int, void*>, Scratch*>;
 
 int scratch_for_stream(void* stream, Scratch** out) {
   int dev = 0;
@@ -449,24 +459,14 @@ static u64h e_cost(uint32_t e) {
 int plan_requests(const PlanIn* in_raw, size_t nreq_raw, const rsaprng_config& c, int mode,
                   std::vector<Req>& out, u64h* ntiles_out) {
   const u64h T = tile_size(c);
-  // Requests of one instance that continue each other -- next k0 = previous end,
-  // and (generate) next output offset = previous end, or (consume) the same
-  // statistics record -- are one contiguous range: they share one scan chain.
   std::vector<PlanIn> merged;
   merged.reserve(nreq_raw);
   for (size_t i = 0; i < nreq_raw; ++i) {
-    const PlanIn& r = in_raw[i];
-    if (!merged.empty()) {
-      PlanIn& m = merged.back();
-      const bool plain = !(m.flags | r.flags);
-      const bool adj_k = m.count && r.k0 == m.k0 + m.count && r.k0 > m.k0;
-      const bool adj_o = mode != kModeGenerate ? r.slot == m.slot : r.out_off == m.out_off + m.count;
-      if (plain && r.inst == m.inst && adj_k && adj_o && r.count) {
-        m.count += r.count;
-        continue;
-      }
+    if (!merged.empty() && plan_merges(merged.back(), in_raw[i], mode)) {
+      merged.back().count += in_raw[i].count;
+      continue;
     }
-    merged.push_back(r);
+    merged.push_back(in_raw[i]);
   }
   const PlanIn* in = merged.data();
   const size_t nreq = merged.size();
@@ -485,25 +485,10 @@ int plan_requests(const PlanIn* in_raw, size_t nreq_raw, const rsaprng_config& c
   for (size_t oi = 0; oi < nreq; ++oi) {
     const PlanIn& r = in[order[oi]];
     if (r.count == 0) continue;
-    if (r.count - 1 > ~0ull - r.k0) return RSAPRNG_E_RANGE;
     Req q;
-    std::memset(&q, 0, sizeof(q));
-    q.k0 = r.k0;
-    q.count = r.count;
-    q.out_off = r.out_off;
-    q.inst = r.inst;
-    q.slot = r.slot;
-    q.flags = r.flags;
-    if (r.flags & kReqContinue) {
-      if (r.S % T || r.S > r.k0) return RSAPRNG_E_ARG;
-      q.S = r.S;
-    } else {
-      q.S = r.k0 & ~(kBlock - 1);
-    }
-    const u64h last = r.k0 + (r.count - 1);
-    const u64h nt = (last - q.S) / T + 1;
-    if (tiles + nt > 0xffffffffull) return RSAPRNG_E_RANGE;
-    q.tile_begin = (uint32_t)tiles;
+    u64h nt = 0;
+    const int rc = plan_one(r, T, tiles, q, &nt);
+    if (rc) return rc;
     tiles += nt;
     out.push_back(q);
   }
@@ -522,32 +507,7 @@ int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode
   const u64h T = tile_size(c);
   chains.clear();
   chains.reserve(reqs.size());
-  for (const Req& r : reqs) {
-    const u64h last = r.k0 + (r.count - 1);
-    u64h x = r.S;
-    u64h first = r.tile_begin;
-    for (;;) {
-      const u64h be = (x & ~(kBlock - 1)) + (kBlock - 1);
-      const u64h chain_last = std::min(last, be);
-      const u64h nt = (chain_last - x) / T + 1;
-      Chain ch;
-      std::memset(&ch, 0, sizeof(ch));
-      ch.S = x;
-      ch.k0 = r.k0;
-      ch.last = last;
-      ch.out_off = r.out_off;
-      ch.inst = r.inst;
-      ch.first = (uint32_t)first;
-      ch.ntiles = (uint32_t)nt;
-      ch.slot = r.slot;
-      ch.flags = ((r.flags & kReqContinue) && x == r.S ? kChainFromState : 0u) |
-                 ((r.flags & kReqWriteEnd) && last <= be ? kChainWriteEnd : 0u);
-      chains.push_back(ch);
-      first += nt;
-      if (last <= be) break;
-      x = be + 1;
-    }
-  }
+  for (const Req& r : reqs) plan_emit_chains(r, T, [&](const Chain& ch) { chains.push_back(ch); });
   *ntiles_out = ntiles;
   return RSAPRNG_OK;
 }
@@ -577,6 +537,28 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks,
                    rsaprng_battery* battery, uint32_t shared_e) {
+  if (ntiles) {
+    const u64h chunks_per_tile = tile_size(c) / (64ull * c.per_lane);
+    const int rc = sc->ensure_tiles(ntiles, ntiles * chunks_per_tile, nchain, stream);
+    if (rc) return rc;
+  }
+  ScratchView v;
+  v.ctl = sc->ctl;
+  v.lb = sc->lb;
+  v.tiles = sc->tiles;
+  v.cstart = sc->cstart;
+  v.tiles_cap = sc->tiles_cap;
+  v.chunks_cap = sc->chunks_cap;
+  v.chains_cap = sc->chains_cap;
+  return enqueue_launch_in(d, v, c, mode, inst, chains, nchain, ntiles, out_c, out_r, stats,
+                           nstats, state, stream, marks, battery, shared_e);
+}
+
+int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c, int mode,
+                      const rsaprng_params* inst, const Chain* chains, uint32_t nchain,
+                      u64h ntiles, uint64_t* out_c, double* out_r, rsaprng_stats* stats,
+                      size_t nstats, ChainState* state, void* stream, hipEvent_t* marks,
+                      rsaprng_battery* battery, uint32_t shared_e) {
   int rc;
   auto mark = [&](int i) {
     return !marks || hipEventRecord(marks[i], (hipStream_t)stream) == hipSuccess ? RSAPRNG_OK
@@ -592,8 +574,9 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
     return RSAPRNG_OK;
   }
   const u64h T = tile_size(c);
-  const u64h chunks_per_tile = T / (64ull * c.per_lane);
-  if ((rc = sc->ensure_tiles(ntiles, ntiles * chunks_per_tile, nchain, stream))) return rc;
+  if (ntiles > sc.tiles_cap || ntiles * (T / (64ull * c.per_lane)) > sc.chunks_cap ||
+      nchain > sc.chains_cap)
+    return RSAPRNG_E_ARG;
   KernelShape shape;
   shape.variant = c.variant;
   shape.wg = c.lanes_per_tile;
@@ -612,20 +595,20 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   a.tile_log2 = (uint32_t)__builtin_ctzll(T);
   a.chunk_log2 = (uint32_t)__builtin_ctzll(64ull * c.per_lane);
   a.spin_limit = (uint32_t)env_int("RSAPRNG_SPIN_LIMIT", 1 << 22);
-  const u64h cap = sc->tiles_cap, ccap = sc->chunks_cap;
+  const u64h cap = sc.tiles_cap, ccap = sc.chunks_cap;
   const u64h half = (cap + 1) / 2;
-  a.tile_chain = reinterpret_cast<uint32_t*>(sc->tiles);
-  a.s_tile = sc->tiles + half;
-  a.agg = sc->tiles + half + cap;
-  a.excl = sc->tiles + half + cap + ccap;
-  a.cstart = sc->cstart;
-  a.lb = sc->lb;
+  a.tile_chain = reinterpret_cast<uint32_t*>(sc.tiles);
+  a.s_tile = sc.tiles + half;
+  a.agg = sc.tiles + half + cap;
+  a.excl = sc.tiles + half + cap + ccap;
+  a.cstart = sc.cstart;
+  a.lb = sc.lb;
   a.out_c = out_c;
   a.out_r = out_r;
   a.stats = stats;
   a.battery = battery;
   a.state = state;
-  a.ctl = sc->ctl;
+  a.ctl = sc.ctl;
   a.pow2 = d->pow2;
   const int ti = T == 2048 ? 0 : (T == 4096 ? 1 : 2);
   if (T != (2048ull << ti)) return RSAPRNG_E_ARG;
@@ -638,7 +621,8 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
     if ((rc = launch_sums(a, stream))) return rc;
     if ((rc = launch_scan(a, stream))) return rc;
   } else if (c.prefix == kPrefixLookback) {
-    if ((rc = launch_begin(sc->ctl, stream))) return rc;
+    if (!sc.ctl || !sc.lb) return RSAPRNG_E_ARG;
+    if ((rc = launch_begin(sc.ctl, stream))) return rc;
   }
   if ((rc = mark(2))) return rc;
   if ((rc = launch_tiles(shape, a, stream)) || (rc = mark(3))) return rc;
@@ -1477,6 +1461,16 @@ static std::string signature(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, 
     total += reqs[i].count;
   }
   std::ostringstream os;
+  // the library build (hash of its sources) and the device: a result measured
+  // on other kernels or another chip is not reused
+  int dev = 0;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    std::memset(&prop, 0, sizeof(prop));
+  }
+  prop.gcnArchName[sizeof(prop.gcnArchName) - 1] = 0;
+  os << "src=" << RSAPRNG_SOURCE_HASH << ";dev=" << prop.gcnArchName << "/"
+     << prop.multiProcessorCount << ";";
   os << "mode=" << mode << ";nreq=" << nreq << ";total=" << total;
   for (auto& kv : by_e) os << ";e" << kv.first << "=" << kv.second;
   return os.str();
@@ -1526,6 +1520,8 @@ std::vector<rsaprng_config> tune_space() {
 
 extern "C" {
 
+static constexpr uint64_t kTuneSentinel = 0xA5A5A5A5A5A5A5A5ull;
+
 int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
                      uint64_t* out_u64, double* out_f64, rsaprng_stats* stats_dev,
                      const char* cache_path, void* stream, rsaprng_config* best, double* best_ms) {
@@ -1563,6 +1559,15 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
   bool have_ref = false;
   int rc = RSAPRNG_OK;
   for (const rsaprng_config& c : tune_space()) {
+    // Every trial writes into buffers that hold a sentinel first, so that a
+    // configuration that left an output unwritten could not inherit it from
+    // an earlier trial (consume records are cleared by each launch itself).
+    if (mode == kModeGenerate) {
+      if (out_u64) rc = launch_fill(out_u64, total_out, kTuneSentinel, stream);
+      if (!rc && out_f64)
+        rc = launch_fill(reinterpret_cast<uint64_t*>(out_f64), total_out, kTuneSentinel, stream);
+      if (rc) break;
+    }
     rsaprng_batch_t b = nullptr;
     rc = rsaprng_batch_create(pool, reqs, nreq, mode, out_u64, out_f64, stats_dev, &c, stream, &b);
     if (rc) break;
@@ -1594,7 +1599,7 @@ int rsaprng_autotune(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t n
       for (int i = 0; i < reps && !rc; ++i) rc = rsaprng_batch_run(b, stream);
       (void)hipEventRecord(e1, (hipStream_t)stream);
       if (hipEventSynchronize(e1) != hipSuccess) rc = RSAPRNG_E_HIP;
-      (void)hipEventElapsedTime(&ms_tot, e0, e1);
+      if (!rc && hipEventElapsedTime(&ms_tot, e0, e1) != hipSuccess) rc = RSAPRNG_E_HIP;
     }
     rsaprng_batch_destroy(b);
     if (rc) break;
@@ -1682,7 +1687,7 @@ int rsaprng_probe(int kind, uint64_t n, uint64_t* out_u64, double* out_f64, doub
   if (kind >= RSAPRNG_PROBE_FMA_F64 && kind <= RSAPRNG_PROBE_MUL_U32_U24) {
     if (n == 0 || n > (1ull << 32)) return RSAPRNG_E_ARG;
     // one sink word per lane, per device, kept for the life of the process
-    static std::map<int, uint64_t*> sinks;
+    static std::map<int, uint64_t*>& sinks = *new std::map<int, uint64_t*>;
     uint64_t* sink = nullptr;
     {
       std::lock_guard<std::mutex> lk(g_mu);

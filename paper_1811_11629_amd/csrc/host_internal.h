@@ -52,6 +52,18 @@ struct Scratch {
 };
 int scratch_for_stream(void* stream, Scratch** out);
 
+// The scratch one launch uses: the control block, the look-back words (only
+// the one-pass form needs ctl and lb), the tile arrays laid out as tile_words()
+// describes for tiles_cap tiles and chunks_cap chunks, and the chain starts
+// (one per chain).
+struct ScratchView {
+  DevCtl* ctl = nullptr;
+  uint64_t* lb = nullptr;
+  uint64_t* tiles = nullptr;
+  ChainStart* cstart = nullptr;
+  u64h tiles_cap = 0, chunks_cap = 0, chains_cap = 0;
+};
+
 rsaprng_config resolve_config(const rsaprng_config* cfg);
 u64h tile_size(const rsaprng_config& c);
 int plan_requests(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode,
@@ -65,6 +77,14 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks = nullptr,
                    rsaprng_battery* battery = nullptr, uint32_t shared_e = 0);
+// The same on scratch the caller provides, sized for the launch (the tile
+// arrays for ntiles tiles and their chunks, cstart for nchain chains);
+// RSAPRNG_E_ARG if the view is too small.
+int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c, int mode,
+                      const rsaprng_params* inst, const Chain* chains, uint32_t nchain,
+                      u64h ntiles, uint64_t* out_c, double* out_r, rsaprng_stats* stats,
+                      size_t nstats, ChainState* state, void* stream, hipEvent_t* marks = nullptr,
+                      rsaprng_battery* battery = nullptr, uint32_t shared_e = 0);
 // The exponent shared by every request (0 if they differ; dual-exponent
 // instances have e = 0): lets a launch take kernels specialised to it.
 uint32_t shared_exponent(const PlanIn* in, size_t n);

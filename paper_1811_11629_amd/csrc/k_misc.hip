@@ -221,6 +221,16 @@ int launch_checksum(const uint64_t* p, uint64_t n, uint64_t* out_dev, void* stre
   return hip_rc(hipGetLastError());
 }
 
+__global__ void k_fill(u64* p, u64 n, u64 v) {
+  for (u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x; i < n; i += (u64)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+int launch_fill(uint64_t* p, uint64_t n, uint64_t v, void* stream) {
+  if (n) hipLaunchKernelGGL(k_fill, dim3(2048), dim3(256), 0, (hipStream_t)stream, p, n, v);
+  return hip_rc(hipGetLastError());
+}
+
 template <int VAR>
 __global__ void k_debug_encrypt(rsaprng_params P, const u64* m, u64* c, double* r, u64 count) {
   u64 i = blockIdx.x * (u64)blockDim.x + threadIdx.x;
