@@ -63,7 +63,9 @@ enum rsaprng_status {
   RSAPRNG_E_BUSY = -11,          /* server: arena full or queue full */
   RSAPRNG_E_ARG = -12,           /* other invalid argument */
   RSAPRNG_E_DEVICE = -13,        /* a kernel reported an error (bounded wait expired) */
-  RSAPRNG_E_NO_DEVICE = -14      /* no usable gfx950 device */
+  RSAPRNG_E_NO_DEVICE = -14,     /* no usable gfx950 device */
+  RSAPRNG_E_TOO_LARGE = -15      /* rsaprng_pool_generate_noalloc: the launch does not fit
+                                    its fixed scratch */
 };
 
 /* ---------------------------------------------------------------------------
@@ -247,6 +249,35 @@ int rsaprng_pool_generate(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, siz
                           void* stream);
 int rsaprng_pool_consume(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
                          rsaprng_stats* stats_dev, const rsaprng_config* cfg, void* stream);
+
+/* rsaprng_pool_generate without any allocation, for callers that cannot
+ * allocate device memory: code that runs under stream capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, outputs and status
+ * codes as rsaprng_pool_generate (the outputs are identical), except:
+ *  - all launch scratch lives in one fixed array of RSAPRNG_NOALLOC_SCRATCH_BYTES
+ *    of device memory per GPU, taken once per device by the library and held
+ *    until the process ends; the chain plan is staged in fixed host arrays.
+ *    Nothing is allocated on the device or the host by the call;
+ *  - a launch must fit that scratch: at most RSAPRNG_NOALLOC_MAX_CHAINS chains
+ *    (one per request and 2^20 block it touches, after merging requests that
+ *    continue each other), and its tile arrays (12 bytes per tile plus 16 per
+ *    wave chunk of 64 * per_lane indices) within the rest; otherwise
+ *    RSAPRNG_E_TOO_LARGE and nothing is enqueued.  With the default tile of
+ *    2048 indices that is about 2^29 outputs per call;
+ *  - the one-pass form (prefix 1) is replaced by two passes (prefix 0);
+ *  - the pool must belong to the current device (RSAPRNG_E_ARG otherwise), and
+ *    devices 0..7 only (RSAPRNG_E_NO_DEVICE).
+ * Every call on a GPU shares that GPU's scratch, which keeps the last call's
+ * contents: calls on one stream are ordered, but calls that overlap on one GPU
+ * (on different streams without an ordering between them) race and may
+ * corrupt each other's outputs.  Returns before the launch completes, like
+ * rsaprng_pool_generate; a later call on a different stream first waits for
+ * the launch that last used the same upload slot. */
+#define RSAPRNG_NOALLOC_SCRATCH_BYTES (32u << 20)
+#define RSAPRNG_NOALLOC_MAX_CHAINS 16384
+int rsaprng_pool_generate_noalloc(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
+                                  uint64_t* out_u64, double* out_f64, const rsaprng_config* cfg,
+                                  void* stream);
 
 /* Prepared batches: the request table and tile plan are uploaded once and the
  * launch (queue reset + persistent kernel) is captured in a hipGraph on the

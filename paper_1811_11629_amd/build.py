@@ -23,7 +23,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I" + INCLUDE
 DEVICE = ["-ffp-contract=off", "-fno-fast-math", "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
 SOURCES = ["k_mont_gen.hip", "k_crt_gen.hip", "k_mont_con.hip", "k_crt_con.hip", "k_crt_bat.hip", "k_vector.hip",
-           "k_misc.hip", "k_primes.hip", "k_probe.hip", "host.cpp", "server.cpp"]
+           "k_misc.hip", "k_primes.hip", "k_probe.hip", "noalloc.hip", "host.cpp", "server.cpp"]
 
 
 def source_hash() -> str:

@@ -681,6 +681,7 @@ const char* rsaprng_strerror(int code) {
     case RSAPRNG_E_ARG: return "invalid argument";
     case RSAPRNG_E_DEVICE: return "kernel-reported error";
     case RSAPRNG_E_NO_DEVICE: return "no gfx950 device";
+    case RSAPRNG_E_TOO_LARGE: return "launch does not fit the fixed scratch of the no-allocation entry point";
     default: return "unknown status";
   }
 }

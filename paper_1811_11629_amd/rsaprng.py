@@ -31,6 +31,7 @@ STATUS = {
     -6: "RSAPRNG_E_RANGE", -7: "RSAPRNG_E_NULL", -8: "RSAPRNG_E_ALIGN", -9: "RSAPRNG_E_OOM",
     -10: "RSAPRNG_E_HIP", -11: "RSAPRNG_E_BUSY", -12: "RSAPRNG_E_ARG", -13: "RSAPRNG_E_DEVICE",
     -14: "RSAPRNG_E_NO_DEVICE",
+    -15: "RSAPRNG_E_TOO_LARGE",
 }
 globals().update({name[len("RSAPRNG_"):]: code for code, name in STATUS.items() if code})
 VARIANT_AUTO, VARIANT_MONT, VARIANT_CRT = 0, 1, 2
@@ -126,6 +127,8 @@ _SIGS = {
     "rsaprng_pool_size": (_sz, [_vp]),
     "rsaprng_pool_generate": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp, _vp,
                                      C.POINTER(rsaprng_config), _vp]),
+    "rsaprng_pool_generate_noalloc": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp, _vp,
+                                             C.POINTER(rsaprng_config), _vp]),
     "rsaprng_pool_consume": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _vp,
                                     C.POINTER(rsaprng_config), _vp]),
     "rsaprng_batch_create": (_i32, [_vp, C.POINTER(rsaprng_pool_req), _sz, _i32, _vp, _vp, _vp,
@@ -372,6 +375,16 @@ def rsaprng_pool_generate(pool: Pool, reqs, out_u64=None, out_f64=None, cfg=None
            "rsaprng_pool_generate")
 
 
+def rsaprng_pool_generate_noalloc(pool: Pool, reqs, out_u64=None, out_f64=None, cfg=None,
+                                  stream=None):
+    arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
+    _check(lib().rsaprng_pool_generate_noalloc(pool.h, arr, len(arr), _ptr(out_u64),
+                                               _ptr(out_f64),
+                                               C.byref(cfg) if cfg is not None else None,
+                                               _stream(stream)),
+           "rsaprng_pool_generate_noalloc")
+
+
 def rsaprng_pool_consume(pool: Pool, reqs, stats, cfg=None, stream=None):
     arr = reqs if isinstance(reqs, C.Array) else pool_reqs(reqs)
     _check(lib().rsaprng_pool_consume(pool.h, arr, len(arr), _ptr(stats),
@@ -540,6 +553,10 @@ def rsaprng_next_primes(x, out, safe: bool = False, exps=(), stream=None) -> Non
     _check(lib().rsaprng_next_primes(_ptr(x), n, 1 if safe else 0, arr, len(exps), _ptr(out),
                                      _stream(stream)), "rsaprng_next_primes")
 
+
+# Limits of rsaprng_pool_generate_noalloc (its fixed scratch).
+NOALLOC_SCRATCH_BYTES = 32 << 20
+NOALLOC_MAX_CHAINS = 16384
 
 PROBES = {"v_fma_f64": 0, "v_mul_f64": 1, "v_add_f64": 2, "v_rndne_f64": 3,
           "v_mad_u64_u32": 4, "v_mul_lo_u32": 5, "v_mul_hi_u32": 6, "v_add_u32": 7,
