@@ -1,7 +1,8 @@
 """Host code under AddressSanitizer and UndefinedBehaviorSanitizer (gcc/g++,
 host only): the served form's scheduler driven by random request streams with
-its invariants checked, and the CPU oracle on generation, the battery and prime
-counts, its digests equal to the regular build's."""
+its invariants checked; the whole host library over a checking stand-in of the
+HIP runtime; and the CPU oracle on generation, the battery and prime counts,
+its digests equal to the regular build's."""
 import os
 import shutil
 import subprocess
@@ -34,6 +35,25 @@ def test_scheduler_invariants_under_sanitizers(tmp_path):
     for seed in (1, 2, 3):
         r = subprocess.run([exe, str(seed)], capture_output=True, text=True, timeout=300, env=_env())
         assert r.returncode == 0 and r.stdout.startswith("ok"), (seed, r.stdout[-2000:], r.stderr[-4000:])
+
+
+def test_host_library_under_sanitizers(tmp_path):
+    """host.cpp, server.cpp and noalloc.hip built for the host against a checking
+    stand-in of the HIP runtime (tests/native/fakehip.cpp): every entry point over
+    uneven batched, consume and served request sets, with every simulated output
+    checked for its own (instance, index) and no device object left behind."""
+    csrc = os.path.join(ROOT, "paper_1811_11629_amd", "csrc")
+    native = os.path.join(ROOT, "tests", "native")
+    exe = str(tmp_path / "host_harness")
+    subprocess.check_call(["g++", "-std=c++17", *SAN, "-I" + os.path.join(native, "fakehip"),
+                           "-I" + csrc, "-I" + os.path.join(ROOT, "include"), "-o", exe,
+                           os.path.join(native, "host_harness.cpp"),
+                           os.path.join(native, "fakehip.cpp"), os.path.join(csrc, "host.cpp"),
+                           os.path.join(csrc, "server.cpp"), "-x", "c++",
+                           os.path.join(csrc, "noalloc.hip"), "-lpthread"])
+    r = subprocess.run([exe, str(tmp_path / "tune.jsonl")], capture_output=True, text=True,
+                       timeout=900, env=_env())
+    assert r.returncode == 0 and r.stdout.startswith("ok"), (r.stdout[-3000:], r.stderr[-6000:])
 
 
 def _fnv(h, data):
