@@ -542,7 +542,8 @@ def verify_served(srv, insts, inst, k0, cnt, threads=None):
                     "from the arena" % n}
 
 
-def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
+def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=27, chunk_log2=24,
+               verify=True):
     """Served workload: 100,000 device-resident instances, requests (instance
     uniform, k0 < 2^40, length log-uniform in [2^10, 2^24)) arriving as a Poisson
     stream; continuous batching with a 64 GiB output arena.  Offered load is a
@@ -563,15 +564,18 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
                 np.array([r.k0 for r in reqs], dtype=np.uint64),
                 np.array([r.count for r in reqs], dtype=np.uint64))
 
-    chunk = 1 << 22
+    chunk = 1 << chunk_log2
     cfg, tune_ms = tune_served(R, torch, stream, pool, *trace(64), chunk)
-    log("served config", cfg.as_dict())
-    srv = R.Server(pool, arena_bytes=64 << 30, chunk_outputs=chunk, cfg=cfg)
+    log("served config", cfg.as_dict(), "iteration 2^%d outputs, chunk 2^%d" % (iter_log2,
+                                                                              chunk_log2))
+    srv = R.Server(pool, arena_bytes=64 << 30, iter_outputs=1 << iter_log2, chunk_outputs=chunk,
+                   cfg=cfg)
 
     res = {"workload": "100000 instances (e from {3,5,7,17,257,65537}), requests: instance "
                        "uniform, k0 < 2^40, count = floor(2^(10+14u)); Poisson arrivals; "
                        "64 GiB output arena; u64+f64 outputs",
-           "config": cfg.as_dict()}
+           "config": cfg.as_dict(), "iteration_outputs": 1 << iter_log2,
+           "chunk_outputs": chunk}
     # saturated capacity: a trace submitted at once
     inst, k0, cnt = trace(40000)
     t_adm, t_done = srv.replay(inst, k0, cnt, np.zeros(len(inst)))
@@ -624,10 +628,11 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9)):
 
     res["headline"] = poisson(rho_main, 2.0, 10.0)
     res["sweep"] = [poisson(r, 1.0, 4.0) for r in sweep]
-    res["verified"] = verify_served(srv, insts, *trace(256))
-    log("served verified: %d requests, %d outputs, equal: %s" % (
-        res["verified"]["requests_compared"], res["verified"]["outputs_compared"],
-        res["verified"]["all_equal"]))
+    if verify:
+        res["verified"] = verify_served(srv, insts, *trace(256))
+        log("served verified: %d requests, %d outputs, equal: %s" % (
+            res["verified"]["requests_compared"], res["verified"]["outputs_compared"],
+            res["verified"]["all_equal"]))
     st = srv.stats()
     res["iterations"] = st["iterations"]
     srv.close()
@@ -876,6 +881,9 @@ def main():
                          "--config: that configuration, no autotuning)")
     ap.add_argument("--verify-cap", type=float, default=120.0, metavar="SECONDS",
                     help="time cap of the batched workload's comparison with the oracle")
+    ap.add_argument("--served-only", default="", metavar="ITER,CHUNK",
+                    help="only the served workload, with iterations of 2^ITER outputs and "
+                         "per-request chunks of 2^CHUNK (no comparison with the oracle)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched uneven workload, without the plain per-request "
                          "launches (with --config: that configuration, no autotuning)")
@@ -922,6 +930,11 @@ def main():
     if args.batched_only:
         res = run_batched_uneven(R, torch, stream, args.steps, cfg=fixed, plain=False,
                                  verify_cap_s=args.verify_cap)
+        print(json.dumps(res))
+        return
+    if args.served_only:
+        it, ch = (int(x) for x in args.served_only.split(","))
+        res = run_served(R, torch, stream, iter_log2=it, chunk_log2=ch, verify=False)
         print(json.dumps(res))
         return
     if args.consume_only:

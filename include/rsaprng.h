@@ -260,7 +260,9 @@ int rsaprng_pool_consume(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
  *    Nothing is allocated on the device or the host by the call;
  *  - a launch must fit that scratch: at most RSAPRNG_NOALLOC_MAX_CHAINS chains
  *    (one per request and 2^20 block it touches, after merging requests that
- *    continue each other), and its tile arrays (12 bytes per tile plus 16 per
+ *    continue each other, plus for the chain-serial form one per request that
+ *    starts beyond the first tile of its block), and its tile arrays (12 bytes
+ *    per tile plus 16 per
  *    wave chunk of 64 * per_lane indices) within the rest; otherwise
  *    RSAPRNG_E_TOO_LARGE and nothing is enqueued.  With the default tile of
  *    2048 indices that is about 2^29 outputs per call;

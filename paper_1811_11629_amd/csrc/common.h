@@ -59,6 +59,18 @@ static_assert(sizeof(Chain) == 64, "Chain layout");
 enum ChainFlags : uint32_t {
   kChainFromState = 1u,  // skip and message before S come from state[slot]
   kChainWriteEnd = 2u,   // the tile holding `last` writes state[slot]
+  kChainStartGiven = 4u, // the chain's start (skip at S, message before S) is written by
+                         // the lead-in pass (k_leadin_state); k_chain_setup leaves it
+};
+
+// A chain-serial generate launch whose chains begin with whole tiles before
+// their request's first index: those lead-in tiles are walked by the two-pass
+// prefix kernels over `nlead` lead-in chains (stored after the `nout` output
+// chains, with tiles [0, lead_tiles)), which then hand each output chain its
+// start at its first tile with outputs.  nlead = 0: no lead-in pass.
+struct LeadIn {
+  uint32_t nout = 0, nlead = 0;
+  uint64_t lead_tiles = 0;
 };
 
 // Computed on the device per chain: the skip at S and the message before S.
@@ -157,6 +169,10 @@ int launch_tiles(const KernelShape& shape, const LaunchArgs& args, void* stream)
 int launch_battery_zero(rsaprng_battery* rec, uint64_t outputs, void* stream);
 int launch_battery_values(const LaunchArgs& args, const double* r, uint64_t count, void* stream);
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream);
+// For each lead-in chain l of `lead` (its prefix arrays filled by k_sums and
+// k_scan): out[slot of l] = the skip at the first index after its tiles and
+// the message before it.
+int launch_leadin_state(const LaunchArgs& lead, ChainStart* out, void* stream);
 int launch_stats_finalize(rsaprng_stats* st, size_t nrec, void* stream);
 int launch_debug_encrypt(const rsaprng_params& prm, int variant, const uint64_t* m, uint64_t* c,
                          double* r, uint64_t count, void* stream);

@@ -512,6 +512,18 @@ int plan_chains(const PlanIn* in, size_t nreq, const rsaprng_config& c, int mode
   return RSAPRNG_OK;
 }
 
+int split_leadin(std::vector<Chain>& chains, const rsaprng_config& c, int mode, LeadIn* li) {
+  li->nout = (uint32_t)chains.size();
+  li->nlead = 0;
+  li->lead_tiles = 0;
+  if (c.prefix != kPrefixSerial || mode != kModeGenerate || chains.empty()) return RSAPRNG_OK;
+  const size_t n = chains.size();
+  chains.resize(2 * n);
+  const int rc = plan_split_leadin(chains.data(), n, 2 * n, tile_size(c), li);
+  chains.resize(n + li->nlead);
+  return rc;
+}
+
 static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c, u64h ntiles) {
   // The dispatch packet counts work-items in 32 bits; work-groups loop over the
   // tile queue (chains, for the chain-serial form), so any grid covers all work.
@@ -536,7 +548,7 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks,
-                   rsaprng_battery* battery, uint32_t shared_e) {
+                   rsaprng_battery* battery, uint32_t shared_e, const LeadIn* li) {
   if (ntiles) {
     const u64h chunks_per_tile = tile_size(c) / (64ull * c.per_lane);
     const int rc = sc->ensure_tiles(ntiles, ntiles * chunks_per_tile, nchain, stream);
@@ -551,15 +563,22 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   v.chunks_cap = sc->chunks_cap;
   v.chains_cap = sc->chains_cap;
   return enqueue_launch_in(d, v, c, mode, inst, chains, nchain, ntiles, out_c, out_r, stats,
-                           nstats, state, stream, marks, battery, shared_e);
+                           nstats, state, stream, marks, battery, shared_e, li);
 }
 
 int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c, int mode,
                       const rsaprng_params* inst, const Chain* chains, uint32_t nchain,
                       u64h ntiles, uint64_t* out_c, double* out_r, rsaprng_stats* stats,
                       size_t nstats, ChainState* state, void* stream, hipEvent_t* marks,
-                      rsaprng_battery* battery, uint32_t shared_e) {
+                      rsaprng_battery* battery, uint32_t shared_e, const LeadIn* li) {
   int rc;
+  // chain-serial generate launches may walk their lead-in tiles in a pass of
+  // their own (plan_split_leadin)
+  const bool lead = li && li->nlead;
+  if (lead && (c.prefix != kPrefixSerial || mode != kModeGenerate || li->nout + (u64h)li->nlead != nchain ||
+               li->lead_tiles >= ntiles))
+    return RSAPRNG_E_ARG;
+  const uint32_t nrun = lead ? li->nout : nchain;
   auto mark = [&](int i) {
     return !marks || hipEventRecord(marks[i], (hipStream_t)stream) == hipSuccess ? RSAPRNG_OK
                                                                                 : RSAPRNG_E_HIP;
@@ -585,12 +604,12 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
   shape.prefix = c.prefix;
   shape.r = c.chunks_per_wave;
   shape.e = shared_e;
-  shape.grid = grid_for(d, shape, c, c.prefix == kPrefixSerial ? (u64h)nchain : ntiles);
+  shape.grid = grid_for(d, shape, c, c.prefix == kPrefixSerial ? (u64h)nrun : ntiles);
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
   a.inst = inst;
   a.chain = chains;
-  a.nchain = nchain;
+  a.nchain = nrun;
   a.ntiles = (uint32_t)ntiles;
   a.tile_log2 = (uint32_t)__builtin_ctzll(T);
   a.chunk_log2 = (uint32_t)__builtin_ctzll(64ull * c.per_lane);
@@ -617,6 +636,18 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
   a.powv = c.per_lane == 8 ? d->powv8 : d->powv16;
   a.gc = d->gc;
   if ((rc = launch_chain_setup(a, stream)) || (rc = mark(1))) return rc;
+  if (lead) {
+    // the lead-in chains: chain setup, the two prefix passes over their tiles,
+    // then the start of each output chain after its lead-in
+    LaunchArgs al = a;
+    al.chain = chains + li->nout;
+    al.nchain = li->nlead;
+    al.ntiles = (uint32_t)li->lead_tiles;
+    al.cstart = sc.cstart + li->nout;
+    if ((rc = launch_chain_setup(al, stream)) || (rc = launch_sums(al, stream)) ||
+        (rc = launch_scan(al, stream)) || (rc = launch_leadin_state(al, sc.cstart, stream)))
+      return rc;
+  }
   if (c.prefix == kPrefixTwoPass) {
     if ((rc = launch_sums(a, stream))) return rc;
     if ((rc = launch_scan(a, stream))) return rc;
@@ -754,13 +785,15 @@ int rsaprng_generate(rsaprng_t h, uint64_t k0, uint64_t count, uint64_t* out_u64
   std::vector<Chain> chains;
   u64h ntiles;
   if ((rc = plan_chains(&in, 1, c, kModeGenerate, chains, &ntiles))) return rc;
+  LeadIn li;
+  if ((rc = split_leadin(chains, c, kModeGenerate, &li))) return rc;
   void* dch;
   int slot;
   if ((rc = sc->upload(chains.data(), chains.size() * sizeof(Chain), stream, &dch, &slot)))
     return rc;
   rc = enqueue_launch(d, sc, c, kModeGenerate, h->dev, (const Chain*)dch, (uint32_t)chains.size(),
                       ntiles, out_u64, out_f64, nullptr, 0, nullptr, stream, nullptr, nullptr,
-                      shared_exponent(&in, 1));
+                      shared_exponent(&in, 1), &li);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -893,6 +926,8 @@ int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u
   u64h ntiles;
   if ((rc = plan_chains(in.data(), nreq, c, kModeGenerate, plan, &ntiles))) return rc;
   if (plan.empty()) return RSAPRNG_OK;
+  LeadIn li;
+  if ((rc = split_leadin(plan, c, kModeGenerate, &li))) return rc;
   const size_t ib = insts.size() * sizeof(rsaprng_params), rb = plan.size() * sizeof(Chain);
   std::vector<char> buf(ib + rb);
   std::memcpy(buf.data(), insts.data(), ib);
@@ -903,7 +938,7 @@ int rsaprng_generate_batch(const rsaprng_req* reqs, size_t nreq, uint64_t* out_u
   rc = enqueue_launch(d, sc, c, kModeGenerate, (const rsaprng_params*)dbuf,
                       (const Chain*)((char*)dbuf + ib), (uint32_t)plan.size(), ntiles, out_u64,
                       out_f64, nullptr, 0, nullptr, stream, nullptr, nullptr,
-                      shared_exponent(in.data(), nreq));
+                      shared_exponent(in.data(), nreq), &li);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -1025,7 +1060,7 @@ rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg) {
 
 int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
               const rsaprng_config& c, std::vector<Chain>& plan, u64h* ntiles,
-              uint32_t* shared_e = nullptr) {
+              uint32_t* shared_e, LeadIn* li) {
   std::vector<PlanIn> in(nreq);
   const size_t np = pool->host.size();
   for (size_t i = 0; i < nreq; ++i) {
@@ -1036,7 +1071,8 @@ int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, in
     if (mode == kModeConsume && reqs[i].out_off > 0xffffffffull) return RSAPRNG_E_ARG;
   }
   if (shared_e) *shared_e = shared_exponent(in.data(), nreq);
-  return plan_chains(in.data(), nreq, c, mode, plan, ntiles);
+  const int rc = plan_chains(in.data(), nreq, c, mode, plan, ntiles);
+  return rc ? rc : split_leadin(plan, c, mode, li);
 }
 
 static size_t stats_records(const rsaprng_pool_req* reqs, size_t nreq) {
@@ -1073,7 +1109,8 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   std::vector<Chain> plan;
   u64h ntiles;
   uint32_t se = 0;
-  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles, &se))) return rc;
+  LeadIn li;
+  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles, &se, &li))) return rc;
   const size_t nst = mode == kModeConsume ? stats_records(reqs, nreq) : 0;
   if (mode == kModeBattery) {
     u64h total = 0;
@@ -1087,7 +1124,7 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
   int slot;
   if ((rc = sc->upload(plan.data(), plan.size() * sizeof(Chain), stream, &dreq, &slot))) return rc;
   rc = enqueue_launch(d, sc, c, mode, pool->dev, (const Chain*)dreq, (uint32_t)plan.size(), ntiles,
-                      out_u64, out_f64, stats, nst, nullptr, stream, nullptr, battery, se);
+                      out_u64, out_f64, stats, nst, nullptr, stream, nullptr, battery, se, &li);
   int rc2 = sc->mark(slot, stream);
   return rc ? rc : rc2;
 }
@@ -1313,6 +1350,7 @@ struct rsaprng_batch_s {
   rsaprng_stats* stats = nullptr;
   size_t nst = 0;
   uint32_t shared_e = 0;                      // exponent of every request, or 0
+  rsaprng::LeadIn li;                         // lead-in split of a chain-serial launch
   std::vector<std::array<hipEvent_t, 5>> ev;  // per timed run
   size_t ev_used = 0;
   ~rsaprng_batch_s() {
@@ -1342,10 +1380,12 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   std::vector<Chain> plan;
   u64h ntiles;
   uint32_t se = 0;
-  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles, &se))) return rc;
+  LeadIn li;
+  if ((rc = pool_plan(pool, reqs, nreq, mode, c, plan, &ntiles, &se, &li))) return rc;
   auto b = std::make_unique<rsaprng_batch_s>();
   b->pool = pool;
   b->shared_e = se;
+  b->li = li;
   if ((rc = b->sc.init())) return rc;
   // sized before the capture so that the captured launch allocates nothing
   if ((rc = b->sc.ensure_tiles(ntiles, ntiles * (tile_size(c) / (64ull * c.per_lane)), plan.size(),
@@ -1364,7 +1404,7 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
     return RSAPRNG_E_HIP;
   rc = enqueue_launch(d, &b->sc, c, mode, pool->dev, (const Chain*)b->dreq, (uint32_t)plan.size(),
                       ntiles, out_u64, out_f64, stats_dev, nst, nullptr, b->cap_stream, nullptr,
-                      nullptr, se);
+                      nullptr, se, &b->li);
   hipGraph_t g = nullptr;
   hipError_t e1 = hipStreamEndCapture(b->cap_stream, &g);
   if (rc) {
@@ -1409,7 +1449,8 @@ int rsaprng_batch_run_timed(rsaprng_batch_t b, void* stream) {
   hipEvent_t* marks = b->ev[b->ev_used].data();
   const int rc = enqueue_launch(b->dev, &b->sc, b->cfg, b->mode, b->pool->dev,
                                 (const Chain*)b->dreq, b->nchain, b->ntiles, b->out_c, b->out_r,
-                                b->stats, b->nst, nullptr, stream, marks, nullptr, b->shared_e);
+                                b->stats, b->nst, nullptr, stream, marks, nullptr, b->shared_e,
+                                &b->li);
   if (!rc) ++b->ev_used;
   return rc;
 }

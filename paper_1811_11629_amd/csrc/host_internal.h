@@ -76,7 +76,8 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
                    const rsaprng_params* inst, const Chain* chains, uint32_t nchain, u64h ntiles,
                    uint64_t* out_c, double* out_r, rsaprng_stats* stats, size_t nstats,
                    ChainState* state, void* stream, hipEvent_t* marks = nullptr,
-                   rsaprng_battery* battery = nullptr, uint32_t shared_e = 0);
+                   rsaprng_battery* battery = nullptr, uint32_t shared_e = 0,
+                   const LeadIn* li = nullptr);
 // The same on scratch the caller provides, sized for the launch (the tile
 // arrays for ntiles tiles and their chunks, cstart for nchain chains);
 // RSAPRNG_E_ARG if the view is too small.
@@ -84,7 +85,12 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
                       const rsaprng_params* inst, const Chain* chains, uint32_t nchain,
                       u64h ntiles, uint64_t* out_c, double* out_r, rsaprng_stats* stats,
                       size_t nstats, ChainState* state, void* stream, hipEvent_t* marks = nullptr,
-                      rsaprng_battery* battery = nullptr, uint32_t shared_e = 0);
+                      rsaprng_battery* battery = nullptr, uint32_t shared_e = 0,
+                      const LeadIn* li = nullptr);
+// Chain-serial generate launches: the lead-in split of plan_split_leadin on a
+// planned chain vector (which grows by the lead-in chains); other launches
+// are left as planned (li->nlead = 0).
+int split_leadin(std::vector<Chain>& chains, const rsaprng_config& c, int mode, LeadIn* li);
 // The exponent shared by every request (0 if they differ; dual-exponent
 // instances have e = 0): lets a launch take kernels specialised to it.
 uint32_t shared_exponent(const PlanIn* in, size_t n);

@@ -16,6 +16,8 @@ __global__ __launch_bounds__(256) void k_chain_setup(LaunchArgs a) {
   const u32 c = blockIdx.x * 4 + (threadIdx.x >> 6);
   if (c >= a.nchain) return;
   const Chain C = a.chain[c];
+  for (u32 i = lane; i < C.ntiles; i += 64) a.tile_chain[C.first + i] = c;
+  if (C.flags & kChainStartGiven) return;  // written by k_leadin_state
   const rsaprng_params P = a.inst[C.inst];
   const u64 n = P.n;
   u64 s_S, m_base;
@@ -41,7 +43,24 @@ __global__ __launch_bounds__(256) void k_chain_setup(LaunchArgs a) {
     cs.m_base = m_base;
     a.cstart[c] = cs;
   }
-  for (u32 i = lane; i < C.ntiles; i += 64) a.tile_chain[C.first + i] = c;
+}
+
+// One thread per lead-in chain (its tiles' chunk sums and prefixes already in
+// agg and excl): the message at its last index is the prefix of its last chunk
+// plus that chunk's sum, and the skip after it is the skip at its start times
+// a^(T ntiles) (a lead-in chain lies inside one 2^20 block, so ntiles < 2^20 / T
+// and the power is a table entry).  They become the start of the output chain
+// named by its slot.
+__global__ __launch_bounds__(256) void k_leadin_state(LaunchArgs a, ChainStart* out) {
+  const u32 l = blockIdx.x * 256 + threadIdx.x;
+  if (l >= a.nchain) return;
+  const Chain L = a.chain[l];
+  const u64 n = a.inst[L.inst].n;
+  const u64 q = ((u64)(L.first + L.ntiles) << (a.tile_log2 - a.chunk_log2)) - 1;
+  ChainStart cs;
+  cs.m_base = addmod(a.excl[q], a.agg[q], n);
+  cs.s_S = mulmod_q(a.cstart[l].s_S, a.at[L.ntiles]);
+  out[L.slot] = cs;
 }
 
 // One wave per tile: T/64 consecutive skips per lane; the sums of the tile's
@@ -253,6 +272,13 @@ int launch_begin(DevCtl* ctl, void* stream) {
 int launch_chain_setup(const LaunchArgs& a, void* stream) {
   if (!a.nchain) return RSAPRNG_OK;
   hipLaunchKernelGGL(k_chain_setup, dim3((a.nchain + 3) / 4), dim3(256), 0, (hipStream_t)stream, a);
+  return hip_rc(hipGetLastError());
+}
+
+int launch_leadin_state(const LaunchArgs& a, ChainStart* out, void* stream) {
+  if (!a.nchain) return RSAPRNG_OK;
+  hipLaunchKernelGGL(k_leadin_state, dim3((a.nchain + 255) / 256), dim3(256), 0,
+                     (hipStream_t)stream, a, out);
   return hip_rc(hipGetLastError());
 }
 

@@ -140,6 +140,14 @@ extern "C" int rsaprng_pool_generate_noalloc(rsaprng_pool_t pool, const rsaprng_
     have = true;
   }
   if (have && (rc = flush(cur))) return rc;
+  // chain-serial: the lead-in tiles in a pass of their own, the lead-in chains
+  // after the output chains in the same table
+  LeadIn li;
+  li.nout = (uint32_t)nchain;
+  if (c.prefix == kPrefixSerial) {
+    if ((rc = plan_split_leadin(stage, nchain, kMaxChains, T, &li))) return rc;
+    nchain += li.nlead;
+  }
 
   ScratchView v;
   v.ctl = reinterpret_cast<DevCtl*>(pd.ptr);
@@ -158,7 +166,7 @@ extern "C" int rsaprng_pool_generate_noalloc(rsaprng_pool_t pool, const rsaprng_
     return RSAPRNG_E_HIP;
   rc = enqueue_launch_in(d, v, c, kModeGenerate, pool_dev(pool), nchain ? dchains : nullptr,
                          (uint32_t)nchain, ntiles, out_u64, out_f64, nullptr, 0, nullptr, stream,
-                         nullptr, nullptr, se);
+                         nullptr, nullptr, se, &li);
   // the slot's table is read by the launch just enqueued (or by the copy
   // already queued if the launch failed): its next writer waits for this event
   if (hipEventRecord(pd.ev[slot], (hipStream_t)stream) != hipSuccess) return rc ? rc : RSAPRNG_E_HIP;

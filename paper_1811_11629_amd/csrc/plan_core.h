@@ -75,4 +75,60 @@ inline void plan_emit_chains(const Req& r, u64h T, Emit&& emit) {
   }
 }
 
+// Splits the whole tiles before each request's first index off the chains of
+// a chain-serial generate launch (the chain-serial kernel would walk them one
+// step at a time inside one work-group; the two-pass prefix kernels walk them
+// with a wave per tile).  chains[0, n) are the planned chains over `ntiles`
+// tiles of T indices; on return chains[0, n) are the output chains (the split
+// ones start at their first tile with outputs, flagged kChainStartGiven) and
+// chains[n, n + nlead) the lead-in chains, whose slot is the index of their
+// output chain.  Lead-in tiles are numbered [0, lead_tiles), the output chains'
+// tiles [lead_tiles, ntiles).  Returns RSAPRNG_E_TOO_LARGE if n + nlead
+// exceeds cap (nothing is changed then).
+inline int plan_split_leadin(Chain* chains, size_t n, size_t cap, u64h T, LeadIn* li) {
+  size_t nlead = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const Chain& C = chains[i];
+    if (!(C.flags & kChainFromState) && C.k0 > C.S && (C.k0 - C.S) / T > 0) ++nlead;
+  }
+  li->nout = (uint32_t)n;
+  li->nlead = 0;
+  li->lead_tiles = 0;
+  if (nlead == 0) return RSAPRNG_OK;
+  if (n + nlead > cap || n + nlead > 0xffffffffull) return RSAPRNG_E_TOO_LARGE;
+  u64h lead_first = 0;
+  for (size_t i = 0; i < n; ++i) {
+    const Chain& C = chains[i];
+    if (!(C.flags & kChainFromState) && C.k0 > C.S && (C.k0 - C.S) / T > 0)
+      lead_first += (C.k0 - C.S) / T;
+  }
+  const u64h lead_tiles = lead_first;
+  u64h lt = 0, ot = lead_tiles;
+  size_t l = n;
+  for (size_t i = 0; i < n; ++i) {
+    Chain& C = chains[i];
+    const u64h L = (!(C.flags & kChainFromState) && C.k0 > C.S) ? (C.k0 - C.S) / T : 0;
+    if (L > 0) {
+      Chain& D = chains[l++];
+      memset(&D, 0, sizeof(D));
+      D.S = C.S;
+      D.k0 = C.S;
+      D.last = C.S + L * T - 1;
+      D.inst = C.inst;
+      D.first = (uint32_t)lt;
+      D.ntiles = (uint32_t)L;
+      D.slot = (uint32_t)i;
+      lt += L;
+      C.S += L * T;
+      C.ntiles -= (uint32_t)L;
+      C.flags |= kChainStartGiven;
+    }
+    C.first = (uint32_t)ot;
+    ot += C.ntiles;
+  }
+  li->nlead = (uint32_t)nlead;
+  li->lead_tiles = lead_tiles;
+  return RSAPRNG_OK;
+}
+
 }  // namespace rsaprng

@@ -130,13 +130,15 @@ int rsaprng_server_s::launch_next() {
   if (!sched->plan(plan, finishing, &total)) return 0;
   u64h ntiles = 0;
   int rc = plan_chains(plan.data(), plan.size(), cfg, kModeGenerate, chains, &ntiles);
+  LeadIn li;
+  if (!rc) rc = split_leadin(chains, cfg, kModeGenerate, &li);
   void* dch = nullptr;
   int slot = 0;
   if (!rc) rc = sc.upload(chains.data(), chains.size() * sizeof(Chain), stream, &dch, &slot);
   if (!rc)
     rc = enqueue_launch(dev, &sc, cfg, kModeGenerate, pool_dev(pool), (const Chain*)dch,
                         (uint32_t)chains.size(), ntiles, arena_c, arena_r, nullptr, 0, states,
-                        stream);
+                        stream, nullptr, nullptr, 0, &li);
   if (!rc) rc = sc.mark(slot, stream);
   Inflight f;
   if (!rc && hipEventCreateWithFlags(&f.ev, hipEventDisableTiming) != hipSuccess)

@@ -797,13 +797,13 @@ __device__ __forceinline__ double wave_scan_f64(double x, int) {
 // sequence (the register budget of those kernels is tight), and other chunks
 // take the EK ladder with predicated stores.  The general kernels' fast path
 // takes any 8-byte-aligned output (store_chunk tests the alignment).
-template <int WG, int V, int VAR, int MODE, int EK = 0, class Msg>
+template <int WG, int V, int VAR, int MODE, int EK = 0, int AL = 1, class Msg>
 __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, bool fast, u64 laneStart) {
   if constexpr (EK != 0) {
     if (fast)
-      tile_outputs<WG, V, VAR, MODE, EK, true, 1>(a, sh, C, P, msg, laneStart);
+      tile_outputs<WG, V, VAR, MODE, EK, true, AL>(a, sh, C, P, msg, laneStart);
     else
       tile_outputs<WG, V, VAR, MODE, EK, false>(a, sh, C, P, msg, laneStart);
   } else if (!fast) {
@@ -825,9 +825,10 @@ __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG
 // Outputs of one wave chunk (64 V indices starting at chunkStart).  The fast
 // path needs every index of the chunk requested; in the general kernels with
 // V = 8 its stores take any 8-byte-aligned output (store_chunk), the pair
-// stores of other V and the kernels specialised to one exponent need 16-byte
-// alignment.
-template <int WG, int V, int VAR, int MODE, int EK = 0, class Msg>
+// stores of other V need 16-byte alignment, and so do the paths specialised
+// to one exponent with AL = 1 (the kernels for launches of one exponent);
+// with AL = -1 (the per-chain dispatch over exponents) they test it.
+template <int WG, int V, int VAR, int MODE, int EK = 0, int AL = 1, class Msg>
 __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
                                               const Msg& msg, u64 chunkStart, u64 laneStart) {
@@ -840,7 +841,8 @@ __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG
   };
   const bool full = chunkStart >= C.k0 && chunkStart + (CHUNK - 1) <= C.last;
   if constexpr (EK != 0)
-    outputs_for_e<WG, V, VAR, MODE, EK>(a, sh, C, P, msg, full && a16(), laneStart);
+    outputs_for_e<WG, V, VAR, MODE, EK, AL>(a, sh, C, P, msg, full && (AL == -1 || a16()),
+                                            laneStart);
   else
     outputs_for_e<WG, V, VAR, MODE, EK>(a, sh, C, P, msg,
                                         full && (MODE != kModeGenerate || V == 8 || a16()),
@@ -1067,18 +1069,175 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
 // for the Montgomery variant.  The waves exchange their totals through LDS
 // once per step (double-buffered by step parity: one barrier per step).  The
 // output pass walks each chunk again from its first skip instead of keeping
-// R V skips across the barrier, except in the kernels specialised to one
-// exponent (EK != 0, generate mode): with a single ladder in the kernel the
+// R V skips across the barrier, except on the paths specialised to one
+// exponent (EK != 0, generate mode): with a single ladder in the loop the
 // skips fit the register budget of four waves per SIMD (which the transpose
 // buffers' LDS caps residency at anyway), so they are kept.  Steps before the
 // chain's first requested index only walk.  No prefix pass is needed.
+//
+// chain3 runs one chain; k_gen3 loops over the chains.  EK > 0: every chain
+// of the launch has exponent EK (outputs 16-byte aligned for the fast path,
+// AL = 1).  EK = kEKPerChain: each chain dispatches on its exponent to the
+// path specialised to it (the common exponents; any other, and the
+// dual-exponent instances, take the general path), with the fast path taking
+// any 8-byte-aligned output (AL = -1).  Each path is its own loop nest, so the
+// kernel's register budget is the largest one's, not their sum.
+constexpr int kEKPerChain = -1;
+
+template <int WG, int V, int R, int VAR, int MODE, int EK, int AL>
+__device__ __forceinline__ void chain3(const LaunchArgs& a, TileShared<WG, MODE>& sh,
+                                       double2 (&xch)[2][WG / 64], u32 c, const u64 (&pv)[R],
+                                       u64 aT, int lane, u32 wave) {
+  constexpr int NW = WG / 64;
+  constexpr u64 T = (u64)WG * V * R;
+  constexpr u64 CHUNK = 64ull * V;
+  const Chain C = load_cst(a.chain + c);
+  const rsaprng_params P = load_cst(a.inst + C.inst);
+  const ChainStart cs0 = load_cst(a.cstart + c);
+  const u64 n = P.n;
+  // the chain ends at the request's last index or at the end of its 2^20 block
+  const u64 clast = C.last < (C.S | (kBlock - 1)) ? C.last : (C.S | (kBlock - 1));
+  u64 s_step = cs0.s_S;       // skip at the step's first index
+  double cp = 0.0, cq = 0.0;  // CRT carry: residues of the message before the step
+  u64 cm = 0;                 // Montgomery carry: the message before the step
+  if constexpr (VAR == kVariantCrt) {
+    cp = res_p(cs0.m_base, P);
+    cq = res_q(cs0.m_base, P);
+  } else {
+    cm = cs0.m_base;
+  }
+  for (u32 step = 0;; ++step) {
+    const u64 base = C.S + (u64)step * T;
+    const bool step_out = base + (T - 1) >= C.k0;  // uniform over the work-group
+    const int par = step & 1;
+    u64 sf[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) sf[r] = mulmod_q(s_step, pv[r]);
+    if constexpr (VAR == kVariantCrt) {
+      // per chunk: lane totals as residues, exclusive lane prefix plus the
+      // totals of the wave's earlier chunks
+      double ep[R], eq[R];
+      double wp = 0.0, wq = 0.0;
+      constexpr bool kKeep = EK != 0;
+      u64 S[R][kKeep ? V : 1];  // the kept skips of each chunk
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double Ht, Lt;
+        walk_sum<V, kKeep>(sf[r], S[r], Ht, Lt);
+        const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
+        const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
+        const double ip = wave_scan_f64(tp, lane);
+        const double iq = wave_scan_f64(tq, lane);
+        ep[r] = wp + (ip - tp);
+        eq[r] = wq + (iq - tq);
+        wp += lane_value_f64(ip, 63);
+        wq += lane_value_f64(iq, 63);
+      }
+      if (lane == 63) xch[par][wave] = make_double2(wp, wq);
+      __syncthreads();
+      double op = 0.0, oq = 0.0, Tp = 0.0, Tq = 0.0;
+      // the wave index re-read each step: otherwise the NW factors below are
+      // hoisted out of the chain loop and held in scalar registers
+      u32 wv = wave;
+      asm volatile("" : "+s"(wv));
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const double2 v = xch[par][w];
+        // a wave-uniform 1 for the waves before this one: one fma instead of
+        // a select and an add (integers below 2^53, every step exact)
+        const double f = w < (int)wv ? 1.0 : 0.0;
+        op = __fma_rn(f, v.x, op);
+        oq = __fma_rn(f, v.y, oq);
+        Tp += v.x;
+        Tq += v.y;
+      }
+      if (step_out) {
+        if constexpr (kKeep) {
+          // unrolled by instantiation: the kept skips are indexed statically
+          static_for<0, R>([&](auto rc) {
+            constexpr int r = decltype(rc)::value;
+            const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+            const u64 laneStart = chunkStart + (u64)lane * V;
+            const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
+            const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
+            if (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast) {
+              const MsgRes<V> msg{S[r], bp, bq};
+              chunk_outputs<WG, V, VAR, MODE, EK, AL>(a, sh, C, P, msg, chunkStart, laneStart);
+            }
+            chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
+          });
+        } else {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+            const u64 laneStart = chunkStart + (u64)lane * V;
+            const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
+            const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
+            const bool chunk_out = MODE == kModeConsume ||
+                                   (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
+            const MsgResWalk<V> msg{sf[r], bp, bq};
+            if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+            chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
+          }
+        }
+      }
+      cp = reduce_res(cp + Tp, P.pd, P.pinv);
+      cq = reduce_res(cq + Tq, P.qd, P.qinv);
+    } else {
+      u64 ex[R];
+      u64 wt = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        u64 X[V];
+        const u64 x = walk<V>(sf[r], n, X);
+        const u64 incl = wave_scan_mod(x, n);
+        ex[r] = addmod(wt, submod(incl, x, n), n);
+        wt = addmod(wt, lane_value(incl, 63), n);
+      }
+      if (lane == 63) xch[par][wave].x = __longlong_as_double((long long)wt);
+      __syncthreads();
+      u64 off = 0, tot = 0;
+#pragma unroll
+      for (int w = 0; w < NW; ++w) {
+        const u64 v = (u64)__double_as_longlong(xch[par][w].x);
+        if (w < (int)wave) off = addmod(off, v, n);
+        tot = addmod(tot, v, n);
+      }
+      if (step_out) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
+          const u64 laneStart = chunkStart + (u64)lane * V;
+          const u64 pre = addmod(addmod(cm, off, n), ex[r], n);
+          const MsgExactWalk<V> msg{pre, n, sf[r]};
+          const bool chunk_out = MODE == kModeConsume ||
+                                 (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
+          if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+          chain_end_walk<V>(a, C, n, pre, sf[r], laneStart);
+        }
+      }
+      cm = addmod(cm, tot, n);
+    }
+    if constexpr (MODE == kModeBattery) {
+      // a step that ends a collision trial whose indices were all requested
+      // (T divides 2^14, so steps never straddle a trial)
+      const u64 end = base + T;
+      if ((end & ((1ull << kTrialLog2) - 1)) == 0 && end - (1ull << kTrialLog2) >= C.k0 &&
+          end - 1 <= C.last)
+        trial_flush<WG>(a, sh);
+    }
+    if (clast - base < T) break;
+    s_step = mulmod_q(s_step, aT);
+  }
+  if constexpr (MODE == kModeConsume) consume_flush<WG>(a, sh, C.slot);
+  if constexpr (MODE == kModeBattery) battery_flush<WG>(a, sh);
+}
+
 template <int WG, int V, int R, int VAR, int MODE, int EK = 0>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(EK != 0 ? 4 : 1)))
 void k_gen3(LaunchArgs a) {
   static_assert(EK == 0 || (MODE == kModeGenerate && VAR == kVariantCrt), "specialised generate");
   constexpr int NW = WG / 64;
-  constexpr u64 T = (u64)WG * V * R;
-  constexpr u64 CHUNK = 64ull * V;
   __shared__ TileShared<WG, MODE> sh;
   __shared__ double2 xch[2][NW];  // wave totals: residues (CRT) or the u64 bits in .x
   const int lane = threadIdx.x & 63;
@@ -1098,146 +1257,22 @@ void k_gen3(LaunchArgs a) {
     __syncthreads();
   }
   for (u32 c = blockIdx.x; c < a.nchain; c += gridDim.x) {
-    const Chain C = load_cst(a.chain + c);
-    const rsaprng_params P = load_cst(a.inst + C.inst);
-    const ChainStart cs0 = load_cst(a.cstart + c);
-    const u64 n = P.n;
-    // the chain ends at the request's last index or at the end of its 2^20 block
-    const u64 clast = C.last < (C.S | (kBlock - 1)) ? C.last : (C.S | (kBlock - 1));
-    u64 s_step = cs0.s_S;       // skip at the step's first index
-    double cp = 0.0, cq = 0.0;  // CRT carry: residues of the message before the step
-    u64 cm = 0;                 // Montgomery carry: the message before the step
-    if constexpr (VAR == kVariantCrt) {
-      cp = res_p(cs0.m_base, P);
-      cq = res_q(cs0.m_base, P);
+    if constexpr (EK == kEKPerChain) {
+      const u32 inst = cst(&a.chain[c].inst)[0];
+      switch (cst(&a.inst[inst].e)[0]) {
+        case 3: chain3<WG, V, R, VAR, MODE, 3, -1>(a, sh, xch, c, pv, aT, lane, wave); break;
+        case 5: chain3<WG, V, R, VAR, MODE, 5, -1>(a, sh, xch, c, pv, aT, lane, wave); break;
+        case 7: chain3<WG, V, R, VAR, MODE, 7, -1>(a, sh, xch, c, pv, aT, lane, wave); break;
+        case 17: chain3<WG, V, R, VAR, MODE, 17, -1>(a, sh, xch, c, pv, aT, lane, wave); break;
+        case 257: chain3<WG, V, R, VAR, MODE, 257, -1>(a, sh, xch, c, pv, aT, lane, wave); break;
+        case 65537:
+          chain3<WG, V, R, VAR, MODE, 65537, -1>(a, sh, xch, c, pv, aT, lane, wave);
+          break;
+        default: chain3<WG, V, R, VAR, MODE, 0, 1>(a, sh, xch, c, pv, aT, lane, wave); break;
+      }
     } else {
-      cm = cs0.m_base;
+      chain3<WG, V, R, VAR, MODE, EK, 1>(a, sh, xch, c, pv, aT, lane, wave);
     }
-    for (u32 step = 0;; ++step) {
-      const u64 base = C.S + (u64)step * T;
-      const bool step_out = base + (T - 1) >= C.k0;  // uniform over the work-group
-      const int par = step & 1;
-      u64 sf[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) sf[r] = mulmod_q(s_step, pv[r]);
-      if constexpr (VAR == kVariantCrt) {
-        // per chunk: lane totals as residues, exclusive lane prefix plus the
-        // totals of the wave's earlier chunks
-        double ep[R], eq[R];
-        double wp = 0.0, wq = 0.0;
-        constexpr bool kKeep = EK != 0;
-        u64 S[R][kKeep ? V : 1];  // the kept skips of each chunk
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          double Ht, Lt;
-          walk_sum<V, kKeep>(sf[r], S[r], Ht, Lt);
-          const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
-          const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
-          const double ip = wave_scan_f64(tp, lane);
-          const double iq = wave_scan_f64(tq, lane);
-          ep[r] = wp + (ip - tp);
-          eq[r] = wq + (iq - tq);
-          wp += lane_value_f64(ip, 63);
-          wq += lane_value_f64(iq, 63);
-        }
-        if (lane == 63) xch[par][wave] = make_double2(wp, wq);
-        __syncthreads();
-        double op = 0.0, oq = 0.0, Tp = 0.0, Tq = 0.0;
-        // the wave index re-read each step: otherwise the NW factors below are
-        // hoisted out of the chain loop and held in scalar registers
-        u32 wv = wave;
-        asm volatile("" : "+s"(wv));
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const double2 v = xch[par][w];
-          // a wave-uniform 1 for the waves before this one: one fma instead of
-          // a select and an add (integers below 2^53, every step exact)
-          const double f = w < (int)wv ? 1.0 : 0.0;
-          op = __fma_rn(f, v.x, op);
-          oq = __fma_rn(f, v.y, oq);
-          Tp += v.x;
-          Tq += v.y;
-        }
-        if (step_out) {
-          if constexpr (kKeep) {
-            // unrolled by instantiation: the kept skips are indexed statically
-            static_for<0, R>([&](auto rc) {
-              constexpr int r = decltype(rc)::value;
-              const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
-              const u64 laneStart = chunkStart + (u64)lane * V;
-              const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
-              const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
-              if (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast) {
-                const MsgRes<V> msg{S[r], bp, bq};
-                chunk_outputs<WG, V, VAR, MODE, EK>(a, sh, C, P, msg, chunkStart, laneStart);
-              }
-              chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
-            });
-          } else {
-#pragma unroll
-            for (int r = 0; r < R; ++r) {
-              const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
-              const u64 laneStart = chunkStart + (u64)lane * V;
-              const double bp = reduce_res(cp + op + ep[r], P.pd, P.pinv);
-              const double bq = reduce_res(cq + oq + eq[r], P.qd, P.qinv);
-              const bool chunk_out = MODE == kModeConsume ||
-                                     (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
-              const MsgResWalk<V> msg{sf[r], bp, bq};
-              if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-              chain_end_res<V>(a, C, P, sf[r], bp, bq, laneStart);
-            }
-          }
-        }
-        cp = reduce_res(cp + Tp, P.pd, P.pinv);
-        cq = reduce_res(cq + Tq, P.qd, P.qinv);
-      } else {
-        u64 ex[R];
-        u64 wt = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          u64 X[V];
-          const u64 x = walk<V>(sf[r], n, X);
-          const u64 incl = wave_scan_mod(x, n);
-          ex[r] = addmod(wt, submod(incl, x, n), n);
-          wt = addmod(wt, lane_value(incl, 63), n);
-        }
-        if (lane == 63) xch[par][wave].x = __longlong_as_double((long long)wt);
-        __syncthreads();
-        u64 off = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) {
-          const u64 v = (u64)__double_as_longlong(xch[par][w].x);
-          if (w < (int)wave) off = addmod(off, v, n);
-          tot = addmod(tot, v, n);
-        }
-        if (step_out) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const u64 chunkStart = base + ((u64)wave * R + r) * CHUNK;
-            const u64 laneStart = chunkStart + (u64)lane * V;
-            const u64 pre = addmod(addmod(cm, off, n), ex[r], n);
-            const MsgExactWalk<V> msg{pre, n, sf[r]};
-            const bool chunk_out = MODE == kModeConsume ||
-                                   (chunkStart + (CHUNK - 1) >= C.k0 && chunkStart <= clast);
-            if (chunk_out) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-            chain_end_walk<V>(a, C, n, pre, sf[r], laneStart);
-          }
-        }
-        cm = addmod(cm, tot, n);
-      }
-      if constexpr (MODE == kModeBattery) {
-        // a step that ends a collision trial whose indices were all requested
-        // (T divides 2^14, so steps never straddle a trial)
-        const u64 end = base + T;
-        if ((end & ((1ull << kTrialLog2) - 1)) == 0 && end - (1ull << kTrialLog2) >= C.k0 &&
-            end - 1 <= C.last)
-          trial_flush<WG>(a, sh);
-      }
-      if (clast - base < T) break;
-      s_step = mulmod_q(s_step, aT);
-    }
-    if constexpr (MODE == kModeConsume) consume_flush<WG>(a, sh, C.slot);
-    if constexpr (MODE == kModeBattery) battery_flush<WG>(a, sh);
   }
 }
 
@@ -1305,11 +1340,14 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
     if (s.prefix == kPrefixSerial) {
       if constexpr (MODE == kModeGenerate && VAR == kVariantCrt) {
         // every instance of the launch has e = 3: the kernels specialised to
-        // it (not for four chunks per wave, whose kept skips would spill)
+        // it; otherwise each chain takes the path specialised to its own
+        // exponent (not for four chunks per wave, whose kept skips would spill)
         if (s.e == 3) {
           if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
           if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
         }
+        if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);
+        if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);
       }
       if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
       if (s.wg == 256 && s.v == 8 && s.r == 4) return launch3<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);

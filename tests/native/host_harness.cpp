@@ -107,7 +107,12 @@ int launch_chain_setup(const LaunchArgs& a, void* stream) {
               "chain %u continues from a state that is not the one before index %" PRIu64, c, C.S);
       }
       for (uint32_t i = 0; i < C.ntiles; ++i) wr(a.tile_chain + C.first + i, c, "tile_chain");
-      wr(a.cstart + c, ChainStart{marker(c), marker(c)}, "cstart");
+      if (C.flags & kChainStartGiven) {
+        // the lead-in pass writes it; mark it unset until then
+        wr(a.cstart + c, ChainStart{0, 0}, "cstart (given later)");
+      } else {
+        wr(a.cstart + c, ChainStart{marker(c), marker(c)}, "cstart");
+      }
     }
   });
 }
@@ -137,6 +142,25 @@ int launch_scan(const LaunchArgs& a, void* stream) {
               q, c);
         wr(a.excl + q, marker(c), "excl");
       }
+    }
+  });
+}
+
+int launch_leadin_state(const LaunchArgs& a, ChainStart* out, void* stream) {
+  if (!a.nchain) return RSAPRNG_OK;
+  return enq(stream, "k_leadin_state", [a, out] {
+    const uint64_t ch = 1ull << (a.tile_log2 - a.chunk_log2);
+    const uint64_t T = 1ull << a.tile_log2;
+    for (uint32_t l = 0; l < a.nchain; ++l) {
+      const Chain L = chain_at(a, l, "k_leadin_state chain");
+      const uint64_t q = ((uint64_t)L.first + L.ntiles) * ch - 1;
+      CHECK(L.k0 == L.S && L.last == L.S + L.ntiles * T - 1 && L.ntiles > 0,
+            "lead-in chain %u malformed", l);
+      CHECK(rd(a.excl + q, "lead excl") == marker(l) && rd(a.agg + q, "lead agg") == marker(l),
+            "lead-in chain %u: prefix of its last chunk unset", l);
+      (void)rd(a.cstart + l, "lead cstart");
+      (void)rd(a.at + L.ntiles, "a^(T ntiles)");
+      wr(out + L.slot, ChainStart{marker(L.slot), marker(L.slot)}, "output chain start");
     }
   });
 }
