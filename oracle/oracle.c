@@ -217,36 +217,57 @@ int oracle_messages(uint64_t p, uint64_t q, uint64_t m0, uint64_t s0, uint64_t k
   return walk(p, q, m0, s0, k0, count, emit_msg, &g);
 }
 
-/* ---- algorithm (1): the paper's own CRT formulation ---- */
+/* ---- algorithm (1): the paper's own CRT formulation ----
+ *
+ * An independent route to the same outputs inside block 0, used as a pin of
+ * the definition above: the message is never formed as one 64-bit number.
+ * Its residues modulo p and q are carried instead (Number Theory section,
+ * eqs. CRTimplementation), the skip comes from Schrage's decomposition of
+ * a s mod Q (Implementation section), each residue is raised to e modulo its
+ * own prime, and the ciphertext is the unique value mod n = p q with those
+ * residues (Chinese remainder theorem, by Garner's form). */
 
-/* Exponentiation modulo a 32-bit prime with native 64-bit products. */
-static uint64_t powmod32(uint64_t x, uint64_t e, uint64_t m) {
-  uint64_t result = 1 % m, base = x % m;
-  while (e) {
-    if (e & 1) result = result * base % m;
-    base = base * base % m;
-    e >>= 1;
+struct crt_ctx {
+  uint64_t p, q;
+  uint64_t q_inv_p; /* q^-1 mod p */
+};
+
+/* x^e mod m for m < 2^32 (products fit 64 bits). */
+static uint64_t pow_small(uint64_t x, uint64_t e, uint64_t m) {
+  uint64_t acc = 1 % m;
+  for (int b = 63; b >= 0; --b) {
+    acc = acc * acc % m;
+    if ((e >> b) & 1) acc = acc * (x % m) % m;
   }
-  return result;
+  return acc;
+}
+
+/* The value x in [0, p q) with x = a (mod p) and x = b (mod q): x = b + q t
+ * where t = (a - b) q^-1 mod p. */
+static uint64_t crt_value(const struct crt_ctx* k, uint64_t a, uint64_t b) {
+  uint64_t d = (a % k->p + k->p - b % k->p) % k->p;
+  uint64_t t = d * k->q_inv_p % k->p;
+  return b + t * k->q;
 }
 
 int oracle_paper_algorithm1(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0,
                             uint64_t count, uint64_t* c_out, double* r_out) {
   int rc = instance_ok(p, q, e, m0, s0);
   if (rc) return rc;
-  uint64_t n = p * q;
-  uint64_t qinv = oracle_inverse(q % p, p); /* precomputed q^-1 mod p */
-  uint64_t s = s0, mp = m0 % p, mq = m0 % q;
+  const struct crt_ctx k = {p, q, oracle_inverse(q % p, p)};
+  uint64_t res[2] = {m0 % p, m0 % q}; /* the message's residues */
+  const uint64_t mod[2] = {p, q};
+  uint64_t skip = s0;
   for (uint64_t i = 0; i < count; ++i) {
-    s = oracle_lcg_next_schrage(s);         /* skip step, 64-bit only */
-    mp = (mp + s) % p;                      /* CRT residues of the message */
-    mq = (mq + s) % q;
-    uint64_t cp = powmod32(mp, e, p);
-    uint64_t cq = powmod32(mq, e, q);
-    uint64_t diff = (cp + p - cq % p) % p;  /* (c_p - c_q) mod p, kept non-negative */
-    uint64_t c = (diff * qinv % p) * q + cq; /* Garner */
+    skip = oracle_lcg_next_schrage(skip);
+    uint64_t enc[2];
+    for (int j = 0; j < 2; ++j) {
+      res[j] = (res[j] + skip % mod[j]) % mod[j];
+      enc[j] = pow_small(res[j], e, mod[j]);
+    }
+    const uint64_t c = crt_value(&k, enc[0], enc[1]);
     if (c_out) c_out[i] = c;
-    if (r_out) r_out[i] = oracle_ratio(c, n);
+    if (r_out) r_out[i] = oracle_ratio(c, p * q);
   }
   return 0;
 }
