@@ -228,21 +228,30 @@ __device__ __forceinline__ u64 encrypt(u64 m, const rsaprng_params& P, double& c
   }
 }
 
-// r * 2^128 as a 128-bit integer (r = 0 or 2^-64 <= r < 1: the shift is in [12, 75]).
-__device__ __forceinline__ void fixed128(double r, u64& lo, u64& hi) {
-  u64 bits = (u64)__double_as_longlong(r);
-  int ex = (int)(bits >> 52);
-  u64 mant = (bits & 0xfffffffffffffull) | (1ull << 52);
-  int sh = ex - 947;
-  if (ex == 0) {
-    lo = 0;
-    hi = 0;
-  } else if (sh < 64) {
-    lo = mant << sh;
-    hi = mant >> (64 - sh);
-  } else {
-    lo = 0;
-    hi = mant << (sh - 64);
+// Adds r 2^128 (r = 0 or 2^-64 <= r < 1, so r 2^128 = mant 2^(ex - 947) is an
+// integer with the shift in [12, 75]) to the 128-bit sum lo + 2^64 hi, counting
+// the carries out of hi in hc.  For r >= 2^-12 (all but about one output in
+// 4096) the low word is zero and r 2^64 = mant 2^(ex - 1011) < 2^64 is added to
+// hi alone; the rest take the full shift.
+__device__ __forceinline__ void add_fixed128(double r, u64& lo, u64& hi, u32& hc) {
+  const u64 bits = (u64)__double_as_longlong(r);
+  const u32 ex = (u32)(bits >> 52);
+  const u64 mant = (bits & 0xfffffffffffffull) | (1ull << 52);
+  if (ex >= 1011) {
+    const u64 v = mant << (ex - 1011);
+    const u64 t = hi + v;
+    hc += t < v;
+    hi = t;
+  } else if (ex != 0) {
+    const u32 sh = ex - 947;                  // in [12, 64)
+    const u64 vl = mant << sh;
+    const u64 vh = mant >> (64 - sh);         // < 2^53
+    const u64 t = lo + vl;
+    const u64 h2 = vh + (t < vl);             // < 2^53 + 1: no wrap
+    lo = t;
+    const u64 t2 = hi + h2;
+    hc += t2 < h2;
+    hi = t2;
   }
 }
 
@@ -500,11 +509,12 @@ struct TileShared {
   u32 tile;
   u64 pre;
   u64 wave_tot[WG / 64];
-  u64 red[MODE == kModeConsume ? (WG / 64) * 6 : 1];
+  u64 red[MODE == kModeConsume ? (WG / 64) * 7 : 1];
   u32 hist[MODE == kModeConsume ? 1024 : 1];
-  // consume: per-thread running sums (digit sums c0..c3, r < 0.5, count),
-  // acc[j WG + thread], flushed to the record by consume_flush
-  u64 acc[MODE == kModeConsume ? 6 * WG : 1];
+  // consume: per-thread running sums (the 32-bit digit sums d0..d4 of the
+  // fixed-point sum, r < 0.5, count), acc[j WG + thread], flushed to the
+  // record by consume_flush
+  u64 acc[MODE == kModeConsume ? 7 * WG : 1];
   // generate: per wave, two 64 x 8 blocks (c, then r) for the coalescing transpose
   u64 xbuf[MODE == kModeGenerate ? 2 * (WG / 64) * 64 * kXRow : 1];
   // battery: the current collision trial's urns, and the small tables
@@ -575,7 +585,10 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
   } else if constexpr (MODE == kModeBattery) {
     battery_outputs<WG, V, VAR, E>(a, sh, C, P, msg, laneStart);
   } else {
-    u64 c0 = 0, c1 = 0, c2 = 0, c3 = 0, lt = 0, cnt = 0;
+    // the lane's exact sum of r 2^128 over its V indices as lo + 2^64 hi +
+    // 2^128 hc, then added to the thread's running digit sums
+    u64 lo = 0, hi = 0;
+    u32 hc = 0, lt = 0, cnt = 0;
 #pragma unroll
     for (int i = 0; i < V; ++i) {
       const u64 k = laneStart + i;
@@ -583,24 +596,21 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       (void)msg.template enc<VAR, E>(i, P, cd);
       const double r = ratio_of(cd, P);
       if (full || (k >= C.k0 && k <= C.last)) {
-        u64 lo, hi;
-        fixed128(r, lo, hi);
-        c0 += lo32(lo);
-        c1 += hi32(lo);
-        c2 += lo32(hi);
-        c3 += hi32(hi);
+        add_fixed128(r, lo, hi, hc);
         lt += r < 0.5;
-        cnt += 1;
+        if (!full) cnt += 1;
         atomicAdd(&sh.hist[(int)(r * 1024.0)], 1u);
       }
     }
+    if (full) cnt = V;
     u64* const acc = sh.acc + threadIdx.x;
-    acc[0] += c0;
-    acc[WG] += c1;
-    acc[2 * WG] += c2;
-    acc[3 * WG] += c3;
-    acc[4 * WG] += lt;
-    acc[5 * WG] += cnt;
+    acc[0] += lo32(lo);
+    acc[WG] += hi32(lo);
+    acc[2 * WG] += lo32(hi);
+    acc[3 * WG] += hi32(hi);
+    acc[4 * WG] += hc;
+    acc[5 * WG] += lt;
+    acc[6 * WG] += cnt;
   }
 }
 
@@ -613,40 +623,39 @@ template <int WG>
 __device__ __forceinline__ void consume_flush(const LaunchArgs& a, TileShared<WG, kModeConsume>& sh,
                                               u32 slot) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  u64 v[6];
+  u64 v[7];
 #pragma unroll
-  for (int j = 0; j < 6; ++j) {
+  for (int j = 0; j < 7; ++j) {
     v[j] = sh.acc[j * WG + threadIdx.x];
     sh.acc[j * WG + threadIdx.x] = 0;
   }
 #pragma unroll
   for (int m = 1; m < 64; m <<= 1) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) v[j] += __shfl_xor(v[j], m, 64);
+    for (int j = 0; j < 7; ++j) v[j] += __shfl_xor(v[j], m, 64);
   }
   if (lane == 0) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) sh.red[wave * 6 + j] = v[j];
+    for (int j = 0; j < 7; ++j) sh.red[wave * 7 + j] = v[j];
   }
   __syncthreads();
   rsaprng_stats* st = a.stats + slot;
   if (threadIdx.x == 0) {
-    u64 s[4] = {0, 0, 0, 0}, tl = 0, tc = 0;
+    u64 s[5] = {0, 0, 0, 0, 0}, tl = 0, tc = 0;
     for (int w = 0; w < WG / 64; ++w) {
-      for (int j = 0; j < 4; ++j) s[j] += sh.red[w * 6 + j];
-      tl += sh.red[w * 6 + 4];
-      tc += sh.red[w * 6 + 5];
+      for (int j = 0; j < 5; ++j) s[j] += sh.red[w * 7 + j];
+      tl += sh.red[w * 7 + 5];
+      tc += sh.red[w * 7 + 6];
     }
     // carry-normalise into 32-bit digits so each atomic adds < 2^32
     u64 carry = 0;
     u32 dig[6];
-    for (int j = 0; j < 4; ++j) {
+    for (int j = 0; j < 5; ++j) {
       u64 v = s[j] + carry;
       dig[j] = lo32(v);
       carry = v >> 32;
     }
-    dig[4] = lo32(carry);
-    dig[5] = hi32(carry);
+    dig[5] = lo32(carry);
     for (int j = 0; j < 6; ++j)
       if (dig[j]) atomicAdd((unsigned long long*)&st->acc32[j], (unsigned long long)dig[j]);
     if (tl) atomicAdd((unsigned long long*)&st->lt_half, (unsigned long long)tl);
@@ -938,7 +947,7 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
   for (int r = 0; r < R; ++r) pv[r] = a.powv[((u64)wave * R + r) * 64 + lane];
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
-    for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
+    for (int j = 0; j < 7; ++j) sh.acc[j * WG + threadIdx.x] = 0;
     __syncthreads();
   }
   for (u32 t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
@@ -1003,7 +1012,7 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
   const u64 my_powv = a.powv[threadIdx.x];
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
-    for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
+    for (int j = 0; j < 7; ++j) sh.acc[j * WG + threadIdx.x] = 0;
   }
   const u32 tag = a.ctl->epoch;
   for (;;) {
@@ -1248,7 +1257,7 @@ void k_gen3(LaunchArgs a) {
   const u64 aT = load_cst(a.at + 1);  // a^T mod Q
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
-    for (int j = 0; j < 6; ++j) sh.acc[j * WG + threadIdx.x] = 0;
+    for (int j = 0; j < 7; ++j) sh.acc[j * WG + threadIdx.x] = 0;
     __syncthreads();
   }
   if constexpr (MODE == kModeBattery) {
