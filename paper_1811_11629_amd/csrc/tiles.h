@@ -1245,7 +1245,8 @@ __device__ __forceinline__ void chain3(const LaunchArgs& a, TileShared<WG, MODE>
 template <int WG, int V, int R, int VAR, int MODE, int EK = 0>
 __global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(EK != 0 ? 4 : 1)))
 void k_gen3(LaunchArgs a) {
-  static_assert(EK == 0 || (MODE == kModeGenerate && VAR == kVariantCrt), "specialised generate");
+  static_assert(EK == 0 || ((MODE == kModeGenerate || MODE == kModeConsume) && VAR == kVariantCrt),
+                "specialised paths: CRT generate and consume");
   constexpr int NW = WG / 64;
   __shared__ TileShared<WG, MODE> sh;
   __shared__ double2 xch[2][NW];  // wave totals: residues (CRT) or the u64 bits in .x
@@ -1347,6 +1348,9 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
       return RSAPRNG_E_ARG;
     }
     if (s.prefix == kPrefixSerial) {
+      if constexpr (MODE == kModeConsume && VAR == kVariantCrt) {
+        if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);
+      }
       if constexpr (MODE == kModeGenerate && VAR == kVariantCrt) {
         // every instance of the launch has e = 3: the kernels specialised to
         // it; otherwise each chain takes the path specialised to its own

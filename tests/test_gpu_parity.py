@@ -229,7 +229,8 @@ def test_consume_matches_oracle(R):
     for (var, name), (shape, prefix) in [(v, sp) for v in _variants(R)
                                          for sp in (((256, 8, 4), 0), ((256, 8, 1), 1),
                                                     ((512, 8, 2), 0), ((256, 16, 1), 1),
-                                                    ((256, 8, 4), 2), ((512, 8, 2), 2))]:
+                                                    ((256, 8, 4), 2), ((512, 8, 2), 2),
+                                                    ((256, 8, 2), 2))]:
         log("consume", name, shape, prefix)
         st = R.stats_tensor(len(ranges))
         R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx) for idx, (j, k0, cnt) in enumerate(ranges)],
