@@ -32,17 +32,46 @@ __device__ __forceinline__ u64 reduce_q_small(u64 r) {
   return (r2 >> 63) ? (r2 & kMask63) : r;
 }
 
-// One skip step s -> a s mod Q (eq. congruentialgenerator1).  a < 2^32 and
-// s < 2^63, so a s < 2^95 = t1 2^32 + lo32(t0); splitting it as H 2^63 + L gives
-// a s = 25 H + L (mod Q) with H < 2^32.  Three full-rate v_mad_u64_u32.  H is
-// taken with an explicit funnel shift (bits 31..62 of t1): written as a shift
-// and a truncation, the compiler widened it and added a zero term.
-__device__ __forceinline__ u64 lcg_next(u64 s) {
+// One skip step s -> a s mod Q (eq. congruentialgenerator1) without the final
+// reduction.  a < 2^32 and s < 2^63 + 2^37, so a s = t1 2^32 + lo32(t0) with
+// t1 < 2^63 (hi32(s) <= 2^31 + 2^5, a < 2^31.11); splitting a s as H 2^63 + L
+// gives a s = 25 H + L (mod Q) with H < 2^32, and r = 25 H + L < 2^63 + 2^37 is
+// a valid input again.  Three full-rate v_mad_u64_u32.  H is taken with an
+// explicit funnel shift (bits 31..62 of t1): written as a shift and a
+// truncation, the compiler widened it and added a zero term.
+// r >= Q needs hi32(r) >= kHiUnreduced, so a run of such steps whose largest
+// hi32 stays below it consists of reduced skips only (about one step in 2^31
+// fails the test; the callers then redo the run with lcg_next).
+constexpr u32 kHiUnreduced = 0x7fffffffu;  // hi32(Q)
+__device__ __forceinline__ u64 lcg_lazy(u64 s) {
   u64 t0 = (u64)(u32)kA * lo32(s);
-  u64 t1 = mad32((u32)kA, hi32(s), hi32(t0));  // < 2^63: hi32(s) < 2^31
+  u64 t1 = mad32((u32)kA, hi32(s), hi32(t0));
   const u32 H = __builtin_amdgcn_alignbit(hi32(t1), lo32(t1), 31);
   u64 L = ((t1 & 0x7fffffffull) << 32) | lo32(t0);
-  return reduce_q_small(mad32(H, 25u, L));     // < 2^63 + 2^37
+  return mad32(H, 25u, L);
+}
+
+// One skip step, reduced: a s mod Q in [0, Q).
+__device__ __forceinline__ u64 lcg_next(u64 s) { return reduce_q_small(lcg_lazy(s)); }
+
+// True when some lane of the wave has top >= kHiUnreduced: its run of lazy
+// steps may hold a value >= Q (a wave-uniform test, so that the exact redo is
+// a branch the wave takes together).
+__device__ __forceinline__ bool wave_any_unreduced(u32 top) {
+  return __builtin_expect(__builtin_amdgcn_ballot_w64(top >= kHiUnreduced) != 0, 0);
+}
+
+// One skip step of a lane's walk: lazy (lcg_lazy, the largest hi32 kept in
+// top) or reduced.
+template <bool LAZY>
+__device__ __forceinline__ u64 walk_step(u64 s, u32& top) {
+  if constexpr (LAZY) {
+    const u64 r = lcg_lazy(s);
+    top = max(top, hi32(r));
+    return r;
+  } else {
+    return lcg_next(s);
+  }
 }
 
 // Full 64x64 -> 128 product.

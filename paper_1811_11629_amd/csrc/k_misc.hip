@@ -63,6 +63,25 @@ __global__ __launch_bounds__(256) void k_leadin_state(LaunchArgs a, ChainStart* 
   out[L.slot] = cs;
 }
 
+// The sum of per (even) consecutive skips from s as lo + 2^64 hi.  Two
+// reduced skips (each below 2^63) add without overflow, so the carry is taken
+// once per pair; with LAZY the steps are lcg_lazy's and top their largest hi32
+// (the sum is exact when it stays below kHiUnreduced).
+template <bool LAZY>
+__device__ __forceinline__ void lane_skip_sum(u64 s, int per, u64& lo, u64& hi, u32& top) {
+  lo = 0;
+  hi = 0;
+  for (int i = 0; i < per; i += 2) {
+    if (i) s = walk_step<LAZY>(s, top);
+    const u64 s1 = walk_step<LAZY>(s, top);
+    const u64 pair = s + s1;
+    const u64 t2 = lo + pair;
+    hi += t2 < pair;
+    lo = t2;
+    s = s1;
+  }
+}
+
 // One wave per tile: T/64 consecutive skips per lane; the sums of the tile's
 // wave chunks (64 V indices each, 64/NW consecutive lanes here) mod n.
 __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
@@ -76,20 +95,15 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   const u64 n = cst(&a.inst[inst].n)[0];
   const u32 j = t - first;
   const u64 s_tile = mulmod_q(cst(&a.cstart[c].s_S)[0], cst(a.at)[j]);
-  u64 s = mulmod_q(s_tile, a.pl[lane]);
+  const u64 s0 = mulmod_q(s_tile, a.pl[lane]);
   const int per = 1 << (a.tile_log2 - 6);  // even: T >= 2048
   // exact integer sum of the lane's skips: lo + 2^64 hi, hi < per / 2 (skips <
-  // 2^63); two skips add without overflow, so the carry is taken once per pair
-  u64 lo = 0, hi = 0;
-  for (int i = 0; i < per; i += 2) {
-    if (i) s = lcg_next(s);
-    const u64 s1 = lcg_next(s);
-    const u64 pair = s + s1;
-    const u64 t2 = lo + pair;
-    hi += t2 < pair;
-    lo = t2;
-    s = s1;
-  }
+  // 2^63); lazy steps first, the walk redone with reduced steps in a wave where
+  // one of them may be unreduced
+  u64 lo, hi;
+  u32 top = 0;
+  lane_skip_sum<true>(s0, per, lo, hi, top);
+  if (wave_any_unreduced(top)) lane_skip_sum<false>(s0, per, lo, hi, top);
   // reduce mod n: lo mod n (lo < 2^64 <= 4n), plus hi (2^64 mod n) by doubling
   u64 x = lo;
   x = x >= n ? x - n : x;

@@ -734,14 +734,15 @@ __device__ __forceinline__ u64 walk(u64 s_first, u64 n, u64 (&X)[V]) {
 // 32-bit halves (below 2^35 and 2^36 for V <= 16) as exact doubles.  The sums
 // are formed in integers so that the per-index conversions of the output pass
 // are not shared with this one (sharing would keep 2 V doubles live).
-template <int V>
-__device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H, double& L) {
+template <int V, bool LAZY>
+__device__ __forceinline__ void walk_halves_run(u64 s_first, u64 (&S)[V], double& H, double& L,
+                                                u32& top) {
   static_assert(V <= 16, "half sums must stay exact and below the residue bounds");
   u64 s = s_first;
   u64 h = 0, l = 0;
 #pragma unroll
   for (int i = 0; i < V; ++i) {
-    if (i) s = lcg_next(s);
+    if (i) s = walk_step<LAZY>(s, top);
     S[i] = s;
     h += hi32(s);
     l += lo32(s);
@@ -750,21 +751,33 @@ __device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H,
   L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
 }
 
+// Lazy steps first; a wave where one of them may be unreduced walks again with
+// reduced steps (the two walks give the same skips whenever the first is
+// accepted).
+template <int V>
+__device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H, double& L) {
+  u32 top = 0;
+  walk_halves_run<V, true>(s_first, S, H, L, top);
+  if (wave_any_unreduced(top)) walk_halves_run<V, false>(s_first, S, H, L, top);
+}
+
 // The lane total of V skips as H 2^32 + L, the skips kept in S[0..V) when
 // KEEP.  Two skips (each below 2^63) add without overflow; the pair sums go
 // into a 64-bit accumulator with a carry count, so the total S = carry 2^64 +
 // acc (below V 2^63) gives H = carry 2^32 + hi32(acc) < 2^35 and L = lo32(acc)
-// exactly.
-template <int V, bool KEEP>
-__device__ __forceinline__ void walk_sum(u64 s_first, u64* S, double& H, double& L) {
+// exactly.  (A lazy walk whose values may exceed 2^63 is redone, so the bound
+// holds for every accepted walk.)
+template <int V, bool KEEP, bool LAZY>
+__device__ __forceinline__ void walk_sum_run(u64 s_first, u64* S, double& H, double& L,
+                                             u32& top) {
   static_assert(V % 2 == 0 && V <= 16, "pairs of skips; H below 2^35");
   u64 s = s_first;
   u64 acc = 0;
   u32 carry = 0;
 #pragma unroll
   for (int i = 0; i < V; i += 2) {
-    if (i) s = lcg_next(s);
-    const u64 s1 = lcg_next(s);
+    if (i) s = walk_step<LAZY>(s, top);
+    const u64 s1 = walk_step<LAZY>(s, top);
     if constexpr (KEEP) {
       S[i] = s;
       S[i + 1] = s1;
@@ -777,6 +790,13 @@ __device__ __forceinline__ void walk_sum(u64 s_first, u64* S, double& H, double&
   }
   H = __fma_rn((double)carry, 4294967296.0, (double)hi32(acc));
   L = (double)lo32(acc);
+}
+
+template <int V, bool KEEP>
+__device__ __forceinline__ void walk_sum(u64 s_first, u64* S, double& H, double& L) {
+  u32 top = 0;
+  walk_sum_run<V, KEEP, true>(s_first, S, H, L, top);
+  if (wave_any_unreduced(top)) walk_sum_run<V, KEEP, false>(s_first, S, H, L, top);
 }
 
 // Inclusive scan over the wave of integer-valued doubles whose partial sums
@@ -970,12 +990,14 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
       if (!outs && !(C.flags & kChainWriteEnd)) continue;
       const u64 s_first = mulmod_q(s_tile, pv[r]);
       if constexpr (VAR == kVariantCrt) {
-        // lane totals as residues, scanned in exact binary64 arithmetic
+        // lane totals as residues up to multiples of p and q, scanned in exact
+        // binary64 arithmetic: |tp| < 2^37 (Ht, Lt < 2^36), so the partial sums
+        // stay below 2^43 and the sum formed below for reduce_res below 2^44
         u64 S[V];
         double Ht, Lt;
         walk_halves<V>(s_first, S, Ht, Lt);
-        const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
-        const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
+        const double tp = fold_p(Ht, P) + Lt;
+        const double tq = fold_q(Ht, P) + Lt;
         const double ip = wave_scan_f64(tp, lane);
         const double iq = wave_scan_f64(tq, lane);
         const double bp =
@@ -1133,8 +1155,10 @@ __device__ __forceinline__ void chain3(const LaunchArgs& a, TileShared<WG, MODE>
       for (int r = 0; r < R; ++r) {
         double Ht, Lt;
         walk_sum<V, kKeep>(sf[r], S[r], Ht, Lt);
-        const double tp = reduce_res(fold_p(Ht, P) + Lt, P.pd, P.pinv);
-        const double tq = reduce_res(fold_q(Ht, P) + Lt, P.qd, P.qinv);
+        // unreduced: |tp| < 2^33, so the lane prefixes stay below 2^39, the
+        // wave totals below 2^41 and their sums over the work-group below 2^45
+        const double tp = fold_p(Ht, P) + Lt;
+        const double tq = fold_q(Ht, P) + Lt;
         const double ip = wave_scan_f64(tp, lane);
         const double iq = wave_scan_f64(tq, lane);
         ep[r] = wp + (ip - tp);

@@ -216,6 +216,50 @@ def test_exponent_specialised_chain_serial(R):
             _check_ranges(mixed, ranges, c, r, "mixed %s %d" % (shape, pers))
 
 
+def test_unreduced_lazy_skips_every_shape(R):
+    # Skip values the kernels' lazy steps leave unreduced (v + Q for a small v),
+    # or reduced with the upper word of Q, inside requested ranges and inside
+    # the lead-in before them, at several positions of a lane's run: the exact
+    # redo of those walks must give the oracle's bytes, in every shape of both
+    # variants, on a pool of e = 3 (the specialised chain-serial kernels) and on
+    # one of mixed exponents (the per-chain paths and the general kernels).
+    from tests import lazy_skip_cases as LC
+    pools = [("e=3", LC.instances((3,))), ("mixed", LC.instances((3, 5, 17, 257, 65537)))]
+    for what, (insts, cases) in pools:
+        ranges = LC.ranges_for(cases)
+        refs = [oracle_gen(insts[i], k0, cnt) for i, k0, cnt in ranges]
+        cref = np.concatenate([x[0] for x in refs])
+        rref = np.concatenate([x[1] for x in refs])
+        for var, name in _variants(R):
+            for shape in SHAPES:
+                for pers in (0, 1):
+                    log("unreduced skips", what, name, shape, pers)
+                    cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                                   chunks_per_wave=shape[2], prefix=shape[3], persistent=pers,
+                                   order=pers)
+                    c, r, _ = _gen_pool(R, insts, ranges, cfg)
+                    assert_same(c, r, cref, rref,
+                                "unreduced skips %s %s %s %d" % (what, name, shape, pers))
+        st_refs = [oracle_stats(insts[i], k0, cnt) for i, k0, cnt in ranges]
+        pool = R.Pool.from_instances(insts)
+        for var, name in _variants(R):
+            for shape in SHAPES:
+                log("unreduced skips consume", what, name, shape)
+                st = R.stats_tensor(len(ranges))
+                cfg = R.config(variant=var, lanes_per_tile=shape[0], per_lane=shape[1],
+                               chunks_per_wave=shape[2], prefix=shape[3])
+                R.rsaprng_pool_consume(pool, [(i, k0, cnt, idx)
+                                              for idx, (i, k0, cnt) in enumerate(ranges)],
+                                       st, cfg=cfg)
+                R.rsaprng_check_device_error()
+                got = R.stats_decode(st)
+                for idx, ref in enumerate(st_refs):
+                    g = got[idx]
+                    assert g["sum_fx"] == ref["sum_fx"], (what, name, shape, idx)
+                    assert g["lt_half"] == ref["lt_half"], (what, name, shape, idx)
+                    assert np.array_equal(g["hist"], ref["hist"]), (what, name, shape, idx)
+
+
 def test_consume_matches_oracle(R):
     import torch
     insts = inputs.config3(3)
