@@ -102,12 +102,14 @@ struct LaunchArgs {
   uint32_t tile_log2;      // T = 2^tile_log2 indices per tile
   uint32_t chunk_log2;     // a wave's share of a tile: 64 V = 2^chunk_log2 indices
   uint32_t spin_limit;
-  uint32_t pad0;
+  uint32_t excl_res;       // two passes, CRT: k_scan leaves the residues of each
+                           // chunk's message, mod p in agg and mod q in excl
+                           // (binary64 bits), instead of the message in excl
   uint32_t* tile_chain;    // per tile: owning chain (k_chain_setup)
   ChainStart* cstart;      // per chain (k_chain_setup)
   uint64_t* s_tile;        // per tile: skip at the tile start (k_sums)
   uint64_t* agg;           // per wave chunk: sum of its skips mod n (k_sums)
-  uint64_t* excl;          // per wave chunk: message before the chunk (k_scan)
+  uint64_t* excl;          // per wave chunk: message before the chunk (k_scan; see excl_res)
   uint64_t* lb;            // single pass: 4 tagged words per tile
   uint64_t* out_c;
   double* out_r;

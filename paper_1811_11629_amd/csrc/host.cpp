@@ -649,6 +649,8 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
       return rc;
   }
   if (c.prefix == kPrefixTwoPass) {
+    // the CRT tile kernel takes each chunk's message as its two residues
+    a.excl_res = c.variant == kVariantCrt ? 1u : 0u;
     if ((rc = launch_sums(a, stream))) return rc;
     if ((rc = launch_scan(a, stream))) return rc;
   } else if (c.prefix == kPrefixLookback) {

@@ -147,6 +147,7 @@ __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
   const int nw_log2 = a.tile_log2 - a.chunk_log2;
   const u64 q_first = (u64)first << nw_log2;         // first chunk of the chain
   const u64 nq = (u64)ntiles << nw_log2;             // chunks of the chain
+  const u32 inst = cst(&a.chain[c].inst)[0];
   u64 E = cst(&a.cstart[c].m_base)[0];
   for (u64 base = 0; base < nq; base += 64 * kScanPer) {
     const u64 left = nq - base;
@@ -161,10 +162,24 @@ __global__ __launch_bounds__(256) void k_scan(LaunchArgs a) {
     for (u32 j = 0; j < kScanPer; ++j) tot = addmod(tot, v[j], n);
     const u64 incl = wave_scan_mod(tot, n);
     u64 x = addmod(E, submod(incl, tot, n), n);      // message before the run
+    if (a.excl_res) {
+      // the residues of each message mod p and mod q (its run's sums are
+      // already in registers, so the residue mod p can take their place)
+      const rsaprng_params P = load_cst(a.inst + inst);
 #pragma unroll
-    for (u32 j = 0; j < kScanPer; ++j) {
-      if (q0 + j < q1) a.excl[q_first + q0 + j] = x;
-      x = addmod(x, v[j], n);
+      for (u32 j = 0; j < kScanPer; ++j) {
+        if (q0 + j < q1) {
+          a.agg[q_first + q0 + j] = (u64)__double_as_longlong(res_p(x, P));
+          a.excl[q_first + q0 + j] = (u64)__double_as_longlong(res_q(x, P));
+        }
+        x = addmod(x, v[j], n);
+      }
+    } else {
+#pragma unroll
+      for (u32 j = 0; j < kScanPer; ++j) {
+        if (q0 + j < q1) a.excl[q_first + q0 + j] = x;
+        x = addmod(x, v[j], n);
+      }
     }
     E = addmod(E, lane_value(incl, 63), n);
   }

@@ -730,37 +730,6 @@ __device__ __forceinline__ u64 walk(u64 s_first, u64 n, u64 (&X)[V]) {
   return x;
 }
 
-// Walk of one lane keeping the skips, and the sums of their upper and lower
-// 32-bit halves (below 2^35 and 2^36 for V <= 16) as exact doubles.  The sums
-// are formed in integers so that the per-index conversions of the output pass
-// are not shared with this one (sharing would keep 2 V doubles live).
-template <int V, bool LAZY>
-__device__ __forceinline__ void walk_halves_run(u64 s_first, u64 (&S)[V], double& H, double& L,
-                                                u32& top) {
-  static_assert(V <= 16, "half sums must stay exact and below the residue bounds");
-  u64 s = s_first;
-  u64 h = 0, l = 0;
-#pragma unroll
-  for (int i = 0; i < V; ++i) {
-    if (i) s = walk_step<LAZY>(s, top);
-    S[i] = s;
-    h += hi32(s);
-    l += lo32(s);
-  }
-  H = __fma_rn((double)hi32(h), 4294967296.0, (double)lo32(h));
-  L = __fma_rn((double)hi32(l), 4294967296.0, (double)lo32(l));
-}
-
-// Lazy steps first; a wave where one of them may be unreduced walks again with
-// reduced steps (the two walks give the same skips whenever the first is
-// accepted).
-template <int V>
-__device__ __forceinline__ void walk_halves(u64 s_first, u64 (&S)[V], double& H, double& L) {
-  u32 top = 0;
-  walk_halves_run<V, true>(s_first, S, H, L, top);
-  if (wave_any_unreduced(top)) walk_halves_run<V, false>(s_first, S, H, L, top);
-}
-
 // The lane total of V skips as H 2^32 + L, the skips kept in S[0..V) when
 // KEEP.  Two skips (each below 2^63) add without overflow; the pair sums go
 // into a 64-bit accumulator with a carry count, so the total S = carry 2^64 +
@@ -949,9 +918,9 @@ __device__ __forceinline__ void chain_end(const LaunchArgs& a, const Chain& C, u
 
 // Two passes: each wave owns R consecutive chunks of 64 V indices of the tile
 // (T = WG V R) and processes them one after the other; the message before a
-// chunk comes from k_scan and its start skip from the tile's skip and a^(64 V q
-// + V lane), so waves never wait on each other.  The next chunk's prefix and
-// offset power are loaded while the current chunk computes.
+// chunk comes from k_scan (for CRT as its two residues) and its start skip
+// from the tile's skip, a^(64 V q) for the chunk (wave-uniform) and a^(V lane),
+// so waves never wait on each other.
 template <int WG, int V, int R, int VAR, int MODE>
 __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
   constexpr int NW = WG / 64;
@@ -961,10 +930,7 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
   __shared__ TileShared<WG, MODE> sh;
   const int lane = threadIdx.x & 63;
   const u32 wave = uniform(threadIdx.x >> 6);
-  // per-lane offset powers of the wave's chunks, loaded before any store
-  u64 pv[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) pv[r] = a.powv[((u64)wave * R + r) * 64 + lane];
+  const u64 pl = a.powv[lane];  // a^(V lane)
   if constexpr (MODE == kModeConsume) {
     for (int b = threadIdx.x; b < 1024; b += WG) sh.hist[b] = 0;
     for (int j = 0; j < 7; ++j) sh.acc[j * WG + threadIdx.x] = 0;
@@ -977,33 +943,38 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
     const u64 n = P.n;
     const u64 tileStart = C.S + (u64)(t - C.first) * T;
     const u64 s_tile = cst(a.s_tile)[t];
-    const u64 q0 = (u64)wave * R;  // first chunk of this wave
-    u64 E[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) E[r] = cst(a.excl)[(u64)t * CH + q0 + r];
+    const u32 q0 = wave * R;  // first chunk of this wave
     const bool any_out = tileStart + (T - 1) >= C.k0;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const u64 chunkStart = tileStart + (q0 + r) * CHUNK;
+      const u64 chunkStart = tileStart + (u64)(q0 + r) * CHUNK;
       const u64 laneStart = chunkStart + (u64)lane * V;
       const bool outs = MODE == kModeConsume ? any_out : chunkStart + (CHUNK - 1) >= C.k0;
       if (!outs && !(C.flags & kChainWriteEnd)) continue;
-      const u64 s_first = mulmod_q(s_tile, pv[r]);
+      // the message before the chunk (CRT: its residues mod p and q), used
+      // after the walk and the scans
+      const u64 q = (u64)t * CH + q0 + r;
+      const u64 E1 = cst(a.excl)[q];
+      const u64 E2 = VAR == kVariantCrt ? cst(a.agg)[q] : 0;
+      // the chunk's first skip (wave-uniform, scalar arithmetic), then each lane's
+      const u64 s_chunk = mulmod_q(s_tile, cst(a.powv)[(u64)(q0 + r) * 64]);
+      const u64 s_first = mulmod_q(s_chunk, pl);
       if constexpr (VAR == kVariantCrt) {
         // lane totals as residues up to multiples of p and q, scanned in exact
-        // binary64 arithmetic: |tp| < 2^37 (Ht, Lt < 2^36), so the partial sums
-        // stay below 2^43 and the sum formed below for reduce_res below 2^44
+        // binary64 arithmetic: |tp| < 2^33 (Ht < 2^35, Lt < 2^32), so the
+        // partial sums stay below 2^39 and the sums formed for reduce_res
+        // below 2^40
         u64 S[V];
         double Ht, Lt;
-        walk_halves<V>(s_first, S, Ht, Lt);
+        walk_sum<V, true>(s_first, S, Ht, Lt);
         const double tp = fold_p(Ht, P) + Lt;
         const double tq = fold_q(Ht, P) + Lt;
         const double ip = wave_scan_f64(tp, lane);
         const double iq = wave_scan_f64(tq, lane);
-        const double bp =
-            reduce_res(res_p(E[r], P) + (ip - tp), P.pd, P.pinv);
-        const double bq =
-            reduce_res(res_q(E[r], P) + (iq - tq), P.qd, P.qinv);
+        const double Ep = __longlong_as_double((long long)E2);
+        const double Eq = __longlong_as_double((long long)E1);
+        const double bp = reduce_res(Ep + (ip - tp), P.pd, P.pinv);
+        const double bq = reduce_res(Eq + (iq - tq), P.qd, P.qinv);
         const MsgRes<V> msg{S, bp, bq};
         if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
         chain_end_res<V>(a, C, P, s_first, bp, bq, laneStart);
@@ -1011,7 +982,7 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
         u64 X[V];
         const u64 x = walk<V>(s_first, n, X);
         const u64 incl = wave_scan_mod(x, n);
-        const u64 pre = addmod(E[r], submod(incl, x, n), n);
+        const u64 pre = addmod(E1, submod(incl, x, n), n);
         const MsgExact<V> msg{pre, n, X};
         if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
         chain_end<V>(a, C, n, pre, X, s_first, laneStart);
