@@ -220,7 +220,8 @@ BATTERY_FIELDS = [("outputs", 1, np.uint64), ("reserved", 1, np.uint64),
                   ("serial3", 1000000, np.uint32), ("serial4", 1 << 20, np.uint32),
                   ("serial5", 1 << 20, np.uint32), ("serial6", 1000000, np.uint32),
                   ("poker", 8, np.uint32), ("maxt", 1024, np.uint32),
-                  ("coll", 256, np.uint32), ("runs", 128, np.uint32)]
+                  ("coll", 256, np.uint32), ("runs", 128, np.uint32),
+                  ("coll_msb", 256, np.uint32)]
 BATTERY_BYTES = sum(n * np.dtype(t).itemsize for _, n, t in BATTERY_FIELDS)
 
 

@@ -490,5 +490,31 @@ int oracle_battery_values(const double* r, uint64_t k0, uint64_t count, oracle_b
     }
     free(urn);
   }
+  /* leading bits of 20 successive values: trials j = 0, 1, 2 of each block of
+   * 2^20 indices, 2^14 balls of 20 indices each from the block's start */
+  const uint64_t BALL = 20, TRIAL = BALL << 14, BLOCK = 1ULL << 20;
+  uint32_t* urn2 = NULL;
+  for (uint64_t blk = k0 & ~(BLOCK - 1);; blk += BLOCK) {
+    for (uint64_t j = 0; j < 3; ++j) {
+      const uint64_t ts = blk + j * TRIAL;
+      if (ts < k0 || ts > last || last - ts < TRIAL - 1) continue;
+      if (!urn2 && !(urn2 = (uint32_t*)calloc(1u << 15, sizeof(uint32_t)))) return -9;
+      uint32_t distinct = 0;
+      for (uint64_t g = 0; g < (1u << 14); ++g) {
+        uint32_t u = 0;
+        for (uint64_t i = 0; i < BALL; ++i)
+          u |= (uint32_t)(r[ts - k0 + g * BALL + i] * 2.0) << i;
+        if (!(urn2[u >> 5] & (1u << (u & 31)))) {
+          urn2[u >> 5] |= 1u << (u & 31);
+          ++distinct;
+        }
+      }
+      const uint32_t c = (1u << 14) - distinct;
+      B->coll_msb[c < 255 ? c : 255]++;
+      memset(urn2, 0, (1u << 15) * sizeof(uint32_t));
+    }
+    if (blk >= (last & ~(BLOCK - 1))) break;
+  }
+  free(urn2);
   return 0;
 }

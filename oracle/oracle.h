@@ -120,6 +120,13 @@ uint64_t oracle_next_prime(uint64_t x, int safe, const uint32_t* exps, int nexp)
  * number of distinct urns, counted in coll[min(C, 255)].  Gaps test (runs of
  * 0s and 1s with b = [r > 1/2]): in each aligned block of 64 indices the run
  * starting at its first index, value b and length L <= 64, in runs[b][L - 1].
+ * Collision test on leading bits: inside each block of 2^20 indices, balls of
+ * 20 consecutive indices from the block's start (20 g .. 20 g + 19 relative
+ * to it), the urn the 20-bit number whose bit j is the leading bit
+ * floor(2 r) of the ball's j-th value; trials of 2^14 consecutive balls, the
+ * first three of the block (its last 65536 indices take no ball); a trial
+ * whose indices all lie in [k0, k0+count) counts 2^14 minus its distinct urns
+ * in coll_msb[min(C, 255)].
  * oracle_battery_add ACCUMULATES into *b. */
 typedef struct {
   uint64_t outputs;
@@ -134,6 +141,7 @@ typedef struct {
   uint32_t maxt[1024];
   uint32_t coll[256];
   uint32_t runs[2][64];
+  uint32_t coll_msb[256];
 } oracle_battery;
 int oracle_battery_add(uint64_t p, uint64_t q, uint64_t e, uint64_t m0, uint64_t s0, uint64_t k0,
                        uint64_t count, oracle_battery* b);

@@ -196,3 +196,57 @@ def test_collision_distribution_and_report(R):
     assert R.battery_report(rec.tobytes())["gaps"]["p"] > 0.99
     view["runs"][0] += 100000
     assert R.battery_report(rec.tobytes())["gaps"]["p"] < 1e-6
+
+
+MSB_BALL, MSB_TRIAL, BLOCK = 20, 20 << 14, 1 << 20
+
+
+def _msb_trial_c(vals):
+    """C for one trial of the leading-bit collision test: 2^14 balls of 20
+    values, the urn the 20 leading bits (value j of the ball -> bit j)."""
+    bits = (np.asarray(vals) >= 0.5).astype(np.int64).reshape(1 << 14, MSB_BALL)
+    urns = bits @ (1 << np.arange(MSB_BALL, dtype=np.int64))
+    return (1 << 14) - np.unique(urns).size
+
+
+def test_oracle_collisions_msb_match_definition():
+    # trials 1 and 2 of block 3 (trial 0 cut by k0), then past the block's tail
+    # into block 4, whose trial 0 is whole
+    inst = inputs.config1()
+    k0 = 3 * BLOCK + MSB_TRIAL - 5
+    count = 4 * BLOCK + MSB_TRIAL + 7 - k0
+    _, r = oracle.generate(inst.p, inst.q, inst.e, inst.m0, inst.s0, k0, count)
+    got = oracle.battery([(inst, k0, count)])
+    want = np.zeros(256, dtype=int)
+    for ts in (3 * BLOCK + MSB_TRIAL, 3 * BLOCK + 2 * MSB_TRIAL, 4 * BLOCK):
+        c = _msb_trial_c(r[ts - k0:ts - k0 + MSB_TRIAL])
+        want[min(c, 255)] += 1
+    assert want.sum() == 3 and np.array_equal(got["coll_msb"], want)
+
+
+def _balls_to_values(urns):
+    # values whose leading bits spell the given urns (0.25 for a 0 bit, 0.75 for a 1)
+    u = np.asarray(urns, dtype=np.int64)
+    bits = (u[:, None] >> np.arange(MSB_BALL)) & 1
+    return np.where(bits.reshape(-1) == 1, 0.75, 0.25)
+
+
+def test_oracle_collisions_msb_closed_forms():
+    g = np.arange(1 << 14)
+    # every ball in urn 0: 2^14 - 1 collisions (class 255)
+    got = oracle.battery_values(np.full(MSB_TRIAL, 0.25), 0)
+    assert got["coll_msb"][255] == 1 and got["coll_msb"].sum() == 1
+    # ball g in urn g: no collision
+    got = oracle.battery_values(_balls_to_values(g), 0)
+    assert got["coll_msb"][0] == 1 and got["coll_msb"].sum() == 1
+    # the last 100 balls repeat urn 7: 100 collisions; the same values placed as
+    # trial 2 of block 5 count too, as trial 3 (the block's tail) they do not
+    urns = np.where(g < (1 << 14) - 100, g, 7)
+    vals = _balls_to_values(urns)
+    for k0, n in ((0, 1), (5 * BLOCK + 2 * MSB_TRIAL, 1), (3 * MSB_TRIAL, 0), (1, 0)):
+        got = oracle.battery_values(vals, k0)
+        assert got["coll_msb"][100] == n and got["coll_msb"].sum() == n, k0
+    # a value of exactly 1/2 has leading bit 1
+    v = _balls_to_values(g)
+    v[v == 0.75] = 0.5
+    assert oracle.battery_values(v, 0)["coll_msb"][0] == 1
