@@ -640,6 +640,12 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=27, c
     return res
 
 
+def p_in_band(rep):
+    """The paper's pass criterion over the tests that counted samples: no
+    p-value below 1e-6 or above 1 - 1e-6."""
+    return all(1e-6 < v["p"] < 1 - 1e-6 for v in rep.values() if v["samples"] > 0)
+
+
 def run_battery(R, torch, stream, steps):
     """The statistical battery as a fused consumer over 2^30 outputs (the
     exponent-sweep instances at e = 3, 2^18 indices each) into one record."""
@@ -667,8 +673,9 @@ def run_battery(R, torch, stream, steps):
     n = len(insts) << 18
     res = {"workload": "4096 instances, e = 3, k in [0, 2^18): 2^30 outputs into one record",
            "gnumbers_per_s": n / t_best / 1e9, "ms": t_best * 1e3, "config": best.as_dict(),
-           "tests": rep,
-           "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep.values())}
+           "tests": rep, "all_p_in_paper_band": p_in_band(rep),
+           # a leading-bit collision trial needs 327680 consecutive indices
+           "tests_without_samples": [k for k, v in rep.items() if v["samples"] == 0]}
     log("battery: %.1f Gnum/s (%.2f ms); p-values %s" % (
         res["gnumbers_per_s"], t_best * 1e3, " ".join("%s=%.3f" % (k, v["p"]) for k, v in rep.items())))
     # the same instances over four 2^20 blocks each: 2^34 outputs across three
@@ -683,7 +690,7 @@ def run_battery(R, torch, stream, steps):
     res["across_reseeding"] = {
         "workload": "the same 4096 instances, k in [0, 2^22) (four blocks each): 2^34 outputs",
         "seconds": dt, "tests": rep4,
-        "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep4.values())}
+        "all_p_in_paper_band": p_in_band(rep4)}
     log("battery over 2^34 outputs (3 re-seedings per instance, %.2f s): p-values %s" % (
         dt, " ".join("%s=%.3f" % (k, v["p"]) for k, v in rep4.items())))
     del rec, pool
@@ -761,7 +768,7 @@ def run_vector(R, torch, stream, steps):
             rep = R.battery_report(rec)
             res["interstream_battery_mv_64"] = {
                 "values": N, "tests": rep,
-                "all_p_in_paper_band": all(1e-6 < v["p"] < 1 - 1e-6 for v in rep.values())}
+                "all_p_in_paper_band": p_in_band(rep)}
             log("battery of the M_v=64 interleaved output: p-values %s" % " ".join(
                 "%s=%.3f" % (k, v["p"]) for k, v in rep.items()))
             del rec

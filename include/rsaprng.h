@@ -402,9 +402,20 @@ void rsaprng_server_destroy(rsaprng_server_t s);
  * (C >= 255 in coll[255]).  Gaps (runs of 0s and 1s, b = [r > 1/2]): in every
  * aligned block of 64 indices, the run that starts at the block's first index
  * has value b and length L (1..64, capped by the block): runs[b][L - 1].
+ * Collisions of leading bits (the Tests section's second collision test, the
+ * most significant bit of twenty successive numbers): inside each block of
+ * 2^20 indices (the re-seeding blocks), balls of 20 consecutive indices from
+ * the block's start; the urn is the 20-bit number whose bit j is the leading
+ * bit floor(2 r) of the ball's j-th value; trials of 2^14 consecutive balls,
+ * the block's first three (its last 65536 indices take no ball); a trial
+ * whose indices are all requested counts C = 2^14 - (distinct urns) in
+ * coll_msb[C] (C >= 255 in coll_msb[255]).
+ * Requests are taken one by one: a block or trial that only the union of two
+ * requests covers is not counted.
  * Counts are unsigned 32-bit (per bin; wraps after 2^32).
  * ------------------------------------------------------------------------ */
-#define RSAPRNG_BAT_TESTS 10  /* frequency, serial D = 2..6, poker, max-of-32, collisions, gaps */
+#define RSAPRNG_BAT_TESTS 11  /* frequency, serial D = 2..6, poker, max-of-32, collisions,
+                                 gaps, collisions of leading bits */
 typedef struct {
   uint64_t outputs;           /* number of r_k consumed: the sum of the requests' counts */
   uint64_t reserved;
@@ -418,12 +429,15 @@ typedef struct {
   uint32_t maxt[1024];        /* bin floor(1024 M^32) */
   uint32_t coll[256];         /* [C] = trials of 2^14 balls with C collisions */
   uint32_t runs[2][64];       /* [b][L - 1] = leading runs of value b and length L */
+  uint32_t coll_msb[256];     /* [C] = trials of the leading-bit urns with C collisions */
 } rsaprng_battery;
 
 /* Zeroes *rec_dev, then accumulates every request into it (reqs[i].out_off is
- * ignored).  Runs the chain-serial CRT kernel whatever cfg asks (its work-group
- * walks each chain in order and holds a trial's 2^20-urn bitmap, 128 KB, in
- * LDS); cfg->lanes_per_tile and cfg->chunks_per_wave select its shape. */
+ * ignored).  Runs the chain-serial CRT kernel, persistent, whatever cfg asks
+ * (its work-group walks each chain in order and holds a trial's 2^20-urn
+ * bitmap, 128 KB, in LDS, and two 2^20-bit bitmaps of the leading-bit trials in
+ * device memory the library keeps per stream, 256 KB per resident work-group);
+ * cfg->lanes_per_tile and cfg->chunks_per_wave select its shape. */
 int rsaprng_pool_battery(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq,
                          rsaprng_battery* rec_dev, const rsaprng_config* cfg, void* stream);
 
@@ -441,8 +455,8 @@ int rsaprng_battery_values(const double* r_dev, uint64_t count, rsaprng_battery*
  * frequency, serial and max tests; for poker the exact probabilities
  * S(5, d) 16 15 ... (16 - d + 1) / 16^5 (S: Stirling numbers of the second
  * kind), with the classes d = 1, 2 merged; for collisions the exact
- * distribution of C for 2^14 balls in 2^20 urns (occupancy recursion); for
- * gaps P(b, L) = 2^-(L+1) for L < 64 and 2^-64 for L = 64.  Collision and gap
+ * distribution of C for 2^14 balls in 2^20 urns (occupancy recursion; both
+ * collision tests); for gaps P(b, L) = 2^-(L+1) for L < 64 and 2^-64 for L = 64.  Collision and gap
  * classes are merged from the tails until each expects at least 5 counts.
  * Host only. */
 typedef struct {

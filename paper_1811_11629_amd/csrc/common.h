@@ -122,7 +122,17 @@ struct LaunchArgs {
   const uint64_t* pl;      // a^((T/64) l) mod Q, l < 64
   const uint64_t* powv;    // a^(V l) mod Q, l < lanes per tile
   uint64_t gc;             // a (a - 1)^-1 mod Q: block seed G_b = s0 gc (a^{bB} - 1)
+  uint32_t* urn2;          // battery: per work-group (blockIdx.x) two 2^20-bit bitmaps
+                           // of the leading-bit collision trials (kUrn2Words words)
 };
+
+// Leading-bit collision trials of the battery (rsaprng.h): balls of 20
+// indices, 2^14 balls per trial, three trials per 2^20 block; a work-group's
+// two bitmaps (by trial parity) in device memory.
+constexpr uint64_t kMsbBall = 20;
+constexpr uint64_t kMsbTrial = kMsbBall << 14;
+constexpr int kMsbTrials = 3;
+constexpr uint32_t kUrn2Words = 2u * ((1u << 20) / 32);
 
 // Vector mode (k_vector.hip): one launch over vector calls [t_lo, t_hi] of one
 // instance.  Lane j stands for substream g = (g_lo + j) mod mv; segment i of
@@ -169,7 +179,9 @@ int launch_sums(const LaunchArgs& args, void* stream);
 int launch_scan(const LaunchArgs& args, void* stream);
 int launch_tiles(const KernelShape& shape, const LaunchArgs& args, void* stream);
 int launch_battery_zero(rsaprng_battery* rec, uint64_t outputs, void* stream);
-int launch_battery_values(const LaunchArgs& args, const double* r, uint64_t count, void* stream);
+// slots: the work-group slots of args.urn2 (the grid is capped to them)
+int launch_battery_values(const LaunchArgs& args, const double* r, uint64_t count, uint32_t slots,
+                          void* stream);
 int launch_stats_zero(rsaprng_stats* st, size_t nrec, void* stream);
 // For each lead-in chain l of `lead` (its prefix arrays filled by k_sums and
 // k_scan): out[slot of l] = the skip at the first index after its tiles and

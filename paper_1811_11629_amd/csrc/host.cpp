@@ -295,6 +295,7 @@ Scratch::~Scratch() {
   if (cstart) (void)hipFree(cstart);
   if (ctl) (void)hipFree(ctl);
   if (vec) (void)hipFree(vec);
+  if (urn2) (void)hipFree(urn2);
 }
 
 int Scratch::init() {
@@ -344,6 +345,19 @@ int Scratch::ensure_vec(u64h words, void* stream) {
   vec_cap = 0;
   if (hipMalloc(&vec, want * 8) != hipSuccess) return RSAPRNG_E_OOM;
   vec_cap = want;
+  return RSAPRNG_OK;
+}
+
+// Battery: the leading-bit trial bitmaps, kUrn2Words words per work-group slot
+// (the kernels clear a bitmap at its trial's first ball, so no initial value).
+int Scratch::ensure_urn2(u64h want, void* stream) {
+  if (want <= urn2_slots) return RSAPRNG_OK;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return RSAPRNG_E_HIP;
+  if (urn2) (void)hipFree(urn2);
+  urn2 = nullptr;
+  urn2_slots = 0;
+  if (hipMalloc(&urn2, want * kUrn2Words * sizeof(uint32_t)) != hipSuccess) return RSAPRNG_E_OOM;
+  urn2_slots = want;
   return RSAPRNG_OK;
 }
 
@@ -554,6 +568,12 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
     const int rc = sc->ensure_tiles(ntiles, ntiles * chunks_per_tile, nchain, stream);
     if (rc) return rc;
   }
+  // the battery's persistent grid: at most one work-group per compute unit
+  // (its 128 KB urn bitmap in LDS), each with its own leading-bit bitmaps
+  if (mode == kModeBattery && ntiles) {
+    const int rc = sc->ensure_urn2((u64h)d->ncu, stream);
+    if (rc) return rc;
+  }
   ScratchView v;
   v.ctl = sc->ctl;
   v.lb = sc->lb;
@@ -562,6 +582,8 @@ int enqueue_launch(Device* d, Scratch* sc, const rsaprng_config& c, int mode,
   v.tiles_cap = sc->tiles_cap;
   v.chunks_cap = sc->chunks_cap;
   v.chains_cap = sc->chains_cap;
+  v.urn2 = sc->urn2;
+  v.urn2_slots = sc->urn2_slots;
   return enqueue_launch_in(d, v, c, mode, inst, chains, nchain, ntiles, out_c, out_r, stats,
                            nstats, state, stream, marks, battery, shared_e, li);
 }
@@ -635,6 +657,10 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
   a.pl = d->pl[ti];
   a.powv = c.per_lane == 8 ? d->powv8 : d->powv16;
   a.gc = d->gc;
+  if (mode == kModeBattery) {
+    if (!c.persistent || !sc.urn2 || (u64h)shape.grid > sc.urn2_slots) return RSAPRNG_E_ARG;
+    a.urn2 = sc.urn2;
+  }
   if ((rc = launch_chain_setup(a, stream)) || (rc = mark(1))) return rc;
   if (lead) {
     // the lead-in chains: chain setup, the two prefix passes over their tiles,
@@ -1102,10 +1128,12 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
     c2.variant = kVariantCrt;
     c = resolve_config(&c2);
   }
-  if (mode == kModeBattery && c.prefix != kPrefixSerial) {
-    // the battery's collision trials need one work-group walking each chain
+  if (mode == kModeBattery && (c.prefix != kPrefixSerial || !c.persistent)) {
+    // the battery's collision trials need one work-group walking each chain,
+    // and a persistent grid (one set of leading-bit bitmaps per work-group)
     rsaprng_config c2 = c;
     c2.prefix = kPrefixSerial;
+    c2.persistent = 1;
     c = resolve_config(&c2);
   }
   std::vector<Chain> plan;
@@ -1157,13 +1185,16 @@ int rsaprng_battery_values(const double* r_dev, uint64_t count, rsaprng_battery*
   if (!rec_dev || (count && !r_dev)) return RSAPRNG_E_NULL;
   if (misaligned(r_dev) || misaligned(rec_dev)) return RSAPRNG_E_ALIGN;
   Device* d;
+  Scratch* sc;
   int rc;
-  if ((rc = device_get(&d))) return rc;
+  if ((rc = device_get(&d)) || (rc = scratch_for_stream(stream, &sc))) return rc;
+  if ((rc = sc->ensure_urn2((u64h)d->ncu, stream))) return rc;
   if ((rc = launch_battery_zero(rec_dev, count, stream))) return rc;
   LaunchArgs a;
   std::memset(&a, 0, sizeof(a));
   a.battery = rec_dev;
-  return launch_battery_values(a, r_dev, count, stream);
+  a.urn2 = sc->urn2;
+  return launch_battery_values(a, r_dev, count, (uint32_t)sc->urn2_slots, stream);
 }
 
 // Upper tail of the chi-squared distribution: the regularised upper incomplete
@@ -1326,6 +1357,15 @@ int rsaprng_battery_report(const rsaprng_battery* r, rsaprng_battery_result* out
     out->chi2[9] = c0 + c1;
     out->dof[9] = d0 + d1 + 1.0;  // one constraint (the total) over both values' classes
     out->p[9] = n > 0 ? rsaprng_chi2_sf(out->chi2[9], out->dof[9]) : 0.0 / 0.0;
+  }
+  {
+    // leading-bit urns: the same 2^14 balls in 2^20 urns
+    const std::vector<double>& P = collision_probs();
+    double o[256], n = 0;
+    for (int c = 0; c < 256; ++c) n += (o[c] = r->coll_msb[c]);
+    out->samples[10] = (uint64_t)n;
+    chi2_merged(o, P.data(), 256, n, out->chi2[10], out->dof[10]);
+    out->p[10] = n > 0 && out->dof[10] > 0 ? rsaprng_chi2_sf(out->chi2[10], out->dof[10]) : 0.0 / 0.0;
   }
   return RSAPRNG_OK;
 }

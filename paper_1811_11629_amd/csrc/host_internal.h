@@ -45,8 +45,11 @@ struct Scratch {
   int init();
   uint64_t* vec = nullptr;       // vector mode: substream and segment tables
   u64h vec_cap = 0;              // in 64-bit words
+  uint32_t* urn2 = nullptr;      // battery: two leading-bit trial bitmaps per work-group slot
+  u64h urn2_slots = 0;
   int ensure_tiles(u64h ntiles, u64h nchunks, u64h nchains, void* stream);
   int ensure_vec(u64h words, void* stream);
+  int ensure_urn2(u64h slots, void* stream);
   int upload(const void* data, size_t bytes, void* stream, void** dev_out, int* slot_out);
   int mark(int slot, void* stream);
 };
@@ -62,6 +65,8 @@ struct ScratchView {
   uint64_t* tiles = nullptr;
   ChainStart* cstart = nullptr;
   u64h tiles_cap = 0, chunks_cap = 0, chains_cap = 0;
+  uint32_t* urn2 = nullptr;      // battery launches only (kUrn2Words per slot)
+  u64h urn2_slots = 0;
 };
 
 rsaprng_config resolve_config(const rsaprng_config* cfg);

@@ -18,7 +18,9 @@ inline bool plan_merges(const PlanIn& m, const PlanIn& r, int mode) {
   const bool plain = !(m.flags | r.flags);
   const bool adj_k = m.count && r.k0 == m.k0 + m.count && r.k0 > m.k0;
   const bool adj_o = mode != kModeGenerate ? r.slot == m.slot : r.out_off == m.out_off + m.count;
-  return plain && r.inst == m.inst && adj_k && adj_o && r.count;
+  // the battery takes requests one by one (a group that only the union of two
+  // requests covers is not counted), so it merges none
+  return mode != kModeBattery && plain && r.inst == m.inst && adj_k && adj_o && r.count;
 }
 
 // The launch record of request r (count > 0) whose tiles, T indices each from

@@ -387,6 +387,9 @@ constexpr int kBatRuns = kBatMax + 1024;     // runs[b][L - 1] [1032, 1160)
 constexpr int kBatLds = kBatRuns + 128;
 constexpr int kTrialLog2 = 14;               // 2^14 balls per collision trial
 constexpr int kUrnWords = (1 << 20) / 32;    // 2^20 urns as a bitmap
+// leading bits of a step (at most 8192 indices), behind the previous step's
+// last 32, and one word of slack for the funnel shift's upper operand
+constexpr int kMsbWords = 8192 / 32 + 2;
 
 __device__ __forceinline__ u32 bin_of(double r, double b, u32 nb) {
   const u32 x = (u32)(r * b);
@@ -487,6 +490,75 @@ __device__ __forceinline__ void battery_count(const LaunchArgs& a, TileShared<WG
   const u64 k64 = laneStart - (u64)(lane & 7) * 8;
   const bool blk64 = k64 >= k0 && k64 <= last && last - k64 >= 63;
   if ((lane & 7) == 0 && blk64) atomicAdd(&sh.bh[kBatRuns + b0 * 64 + (m < 8u ? 8u * m + tm : 64u) - 1], 1u);
+  // the leading bits floor(2 r) of the lane's 8 values: one byte of the step's
+  // bit string (steps of 2^tile_log2 indices, aligned to their size)
+  u32 lead = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) lead |= (r[i] >= 0.5 ? 1u : 0u) << i;
+  const u32 off8 = (u32)((laneStart & ((1ull << a.tile_log2) - 1)) >> 3);
+  reinterpret_cast<unsigned char*>(sh.msb + 1)[off8] = (unsigned char)lead;
+}
+
+// Leading-bit collision trials (rsaprng.h): after a step [base, base + T)
+// whose bytes are in sh.msb[1 ..], behind the previous step's last 32 bits in
+// sh.msb[0], every ball whose last index lies in the step.  A trial counts
+// when all its indices lie in [k0, last]; its bitmap (work-group slot `slot`
+// of a.urn2, by trial parity) is cleared at the step of its first ball, and
+// its distinct urns are read out at the step of its last.  Called by every
+// thread of the work-group, after every byte of the step is written; the next
+// step's bytes may be written as soon as it returns (only sh.msb[0] is written
+// after its last barrier).
+template <int WG>
+__device__ void msb_step(const LaunchArgs& a, TileShared<WG, kModeBattery>& sh, u64 base, u32 T,
+                         u64 k0, u64 last, u32 slot) {
+  const u64 blk = base & ~(kBlock - 1);
+  const u64 rel = base - blk;                     // a multiple of T
+  const u64 g_lo = rel / kMsbBall;                // first ball ending at or after base
+  u64 g_hi = (rel + T) / kMsbBall;                // first ball ending after the step
+  constexpr u64 kBalls = (u64)kMsbTrials << kTrialLog2;
+  if (g_hi > kBalls) g_hi = kBalls;
+  u32* const bm = a.urn2 + (u64)slot * kUrn2Words;
+  const auto counted = [&](u64 j) {
+    const u64 ts = blk + j * kMsbTrial;
+    return ts >= k0 && ts <= last && last - ts >= kMsbTrial - 1;
+  };
+#pragma unroll
+  for (int j = 0; j < kMsbTrials; ++j) {
+    const u64 g0 = (u64)j << kTrialLog2;
+    if (g0 >= g_lo && g0 < g_hi && counted(j)) {
+      u32* b = bm + (j & 1) * kUrnWords;
+      for (int i = threadIdx.x; i < kUrnWords; i += WG) b[i] = 0;
+      if (threadIdx.x == 0) sh.dist2[j & 1] = 0;
+    }
+  }
+  __syncthreads();  // the step's bytes, the cleared bitmaps
+  // the step's last 32 bits, kept for the next step's first balls (written to
+  // sh.msb[0] once every ball below has read it; the next step's bytes may
+  // already be arriving then, so it is read now)
+  const u32 tail = threadIdx.x == 0 ? sh.msb[T / 32] : 0u;
+  for (u64 g = g_lo + threadIdx.x; g < g_hi; g += WG) {
+    const u64 j = g >> kTrialLog2;
+    if (!counted(j)) continue;
+    const u32 o = (u32)(g * kMsbBall + 32 - rel);  // ball's first bit, counted from base - 32
+    const u32 w = o >> 5;
+    const u32 urn = __builtin_amdgcn_alignbit(sh.msb[w + 1], sh.msb[w], o & 31) & 0xfffffu;
+    const u32 bit = 1u << (urn & 31);
+    const u32 old = __hip_atomic_fetch_or(bm + (j & 1) * kUrnWords + (urn >> 5), bit,
+                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!(old & bit)) atomicAdd(&sh.dist2[j & 1], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < kMsbTrials; ++j) {
+      const u64 gl = (((u64)j + 1) << kTrialLog2) - 1;
+      if (gl >= g_lo && gl < g_hi && counted(j)) {
+        const u32 c = (1u << kTrialLog2) - sh.dist2[j & 1];
+        bat_add(&a.battery->coll_msb[c < 255 ? c : 255]);
+      }
+    }
+    sh.msb[0] = tail;
+  }
 }
 
 template <int WG, int V, int VAR, u32 E, class Msg>
@@ -520,6 +592,10 @@ struct TileShared {
   // battery: the current collision trial's urns, and the small tables
   u32 urn[MODE == kModeBattery ? kUrnWords : 1];
   u32 bh[MODE == kModeBattery ? kBatLds : 1];
+  // battery: the step's leading bits and the distinct urns of the two
+  // leading-bit trials in flight (by parity)
+  u32 msb[MODE == kModeBattery ? kMsbWords : 1];
+  u32 dist2[2];
 };
 
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
@@ -1223,6 +1299,7 @@ __device__ __forceinline__ void chain3(const LaunchArgs& a, TileShared<WG, MODE>
       cm = addmod(cm, tot, n);
     }
     if constexpr (MODE == kModeBattery) {
+      if (step_out) msb_step<WG>(a, sh, base, (u32)T, C.k0, C.last, blockIdx.x);
       // a step that ends a collision trial whose indices were all requested
       // (T divides 2^14, so steps never straddle a trial)
       const u64 end = base + T;

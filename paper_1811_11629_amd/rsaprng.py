@@ -95,12 +95,13 @@ _lib = None
 
 _u64, _u32, _i32, _dbl, _sz, _vp = C.c_uint64, C.c_uint32, C.c_int, C.c_double, C.c_size_t, C.c_void_p
 BAT_TESTS = ("frequency", "serial2", "serial3", "serial4", "serial5", "serial6", "poker",
-             "max_of_32", "collisions", "gaps")
-BATTERY_BYTES = 16 + 4 * (4 * (1 << 20) + 2 * 1000000 + 8 + 1024 + 256 + 128)
+             "max_of_32", "collisions", "gaps", "collisions_msb")
+BATTERY_BYTES = 16 + 4 * (4 * (1 << 20) + 2 * 1000000 + 8 + 1024 + 256 + 128 + 256)
 
 
 class rsaprng_battery_result(C.Structure):
-    _fields_ = [("chi2", _dbl * 10), ("dof", _dbl * 10), ("p", _dbl * 10), ("samples", _u64 * 10)]
+    _fields_ = [("chi2", _dbl * len(BAT_TESTS)), ("dof", _dbl * len(BAT_TESTS)),
+                ("p", _dbl * len(BAT_TESTS)), ("samples", _u64 * len(BAT_TESTS))]
 
 
 _SIGS = {

@@ -209,7 +209,11 @@ int launch_tiles(const KernelShape& s, const LaunchArgs& a, void* stream) {
         fakehip::need_device(st, sizeof(*st), "stats record");
         st->count += hi - lo + 1;
       }
-      if (s.mode == kModeBattery) fakehip::need_device(a.battery, sizeof(rsaprng_battery), "battery record");
+      if (s.mode == kModeBattery) {
+        fakehip::need_device(a.battery, sizeof(rsaprng_battery), "battery record");
+        // the leading-bit bitmaps of the work-group slots the grid uses
+        fakehip::need_device(a.urn2, (size_t)s.grid * kUrn2Words * sizeof(uint32_t), "battery bitmaps");
+      }
       if ((C.flags & kChainWriteEnd) && C.last <= be)
         wr(a.state + C.slot, ChainState{tag_state(C.inst, C.last), 0}, "chain-end state");
     }
@@ -224,10 +228,13 @@ int launch_battery_zero(rsaprng_battery* rec, uint64_t outputs, void* stream) {
   });
 }
 
-int launch_battery_values(const LaunchArgs& a, const double* r, uint64_t count, void* stream) {
+int launch_battery_values(const LaunchArgs& a, const double* r, uint64_t count, uint32_t slots,
+                          void* stream) {
+  if (count && (!a.urn2 || slots == 0)) return RSAPRNG_E_ARG;
   return enq(stream, "k_battery_values", [=] {
     fakehip::need_device(r, count * 8, "battery values");
     fakehip::need_device(a.battery, sizeof(rsaprng_battery), "battery record");
+    if (count) fakehip::need_device(a.urn2, (size_t)slots * kUrn2Words * sizeof(uint32_t), "battery bitmaps");
   });
 }
 

@@ -188,6 +188,12 @@ def test_collision_distribution_and_report(R):
     # shifting every count by one class is detected
     view["coll"][:] = np.rint(np.concatenate([[0], expect[:-1]])).astype(np.uint32)
     assert R.battery_report(rec.tobytes())["collisions"]["p"] < 1e-6
+    # the leading-bit collision test takes the same distribution
+    view["coll_msb"][:] = np.rint(expect).astype(np.uint32)
+    out = R.battery_report(rec.tobytes())
+    assert out["collisions_msb"]["samples"] == int(view["coll_msb"].sum())
+    assert out["collisions_msb"]["p"] > 0.99 and out["collisions_msb"]["dof"] > 20
+    view["coll_msb"][:] = 0
     # gaps: counts at their expectations give p near 1; too many short runs do not
     view["coll"][:] = 0
     g = np.array([2.0 ** -(L + 1) if L < 64 else 2.0 ** -64 for L in range(1, 65)]) * (1 << 24)

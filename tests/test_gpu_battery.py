@@ -33,9 +33,15 @@ SHAPES = ((256, 8, 2, 2), (256, 8, 4, 2), (512, 8, 2, 2), (256, 8, 4, 0))
 def test_battery_matches_oracle(R):
     insts = inputs.config3(3)
     cases = [inputs.Instance(i.p, i.q, e, i.m0) for i in insts for e in (3, 17)]
+    T2 = 20 << 14   # a leading-bit collision trial
     ranges = [(0, 5, 70000), (1, B - 4000 + 3, 9000), (2, (1 << 40) + 11, 33333), (3, 0, 4096),
               (4, 7, 1), (5, (1 << 63) + 1, 50000), (0, 3 * B, 5000),
-              (4, 2 * B - 3 * (1 << 14) - 5, 6 * (1 << 14) + 10)]  # trials on both sides of a re-seeding
+              (4, 2 * B - 3 * (1 << 14) - 5, 6 * (1 << 14) + 10),  # trials on both sides of a re-seeding
+              # leading-bit trials: 1 and 2 of a block (0 cut), exactly trial 0, a block's
+              # tail into the next block's trial 0
+              (1, 5 * B + T2 - 3, 2 * T2 + 10), (2, 7 * B, T2), (3, 9 * B + 3 * T2 - 5, B - 3 * T2 + T2 + 9),
+              # adjacent requests are counted one by one: groups across their boundary are not
+              (5, 11 * B + 100, 500), (5, 11 * B + 600, 700), (5, 11 * B + 1300, 64 * 3 + 7)]
     ref = oracle.battery([(cases[j], k0, cnt) for j, k0, cnt in ranges])
     pool = R.Pool.from_instances(cases)
     rec = R.battery_tensor()
@@ -48,6 +54,7 @@ def test_battery_matches_oracle(R):
         got = _decode(rec)
         # the output count is the requests' total; the frequency bins prove each was counted
         assert int(got["freq"].sum(dtype=np.uint64)) == int(got["outputs"][0])
+        assert int(got["coll_msb"].sum()) == 4
         for name in ref:
             if name == "reserved":
                 continue
@@ -96,7 +103,7 @@ def test_battery_of_stored_values(R):
     import torch
     inst = inputs.config3(1)[0]
     # a generated range from index 0: the stored values' battery equals the fused one
-    n = 5 * (1 << 14) + 1234
+    n = B + (20 << 14) + 77    # four leading-bit trials, the last block ragged
     pool = R.Pool.from_instances([inst])
     c = torch.empty(n, dtype=torch.int64, device="cuda")
     r = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -108,6 +115,7 @@ def test_battery_of_stored_values(R):
     R.rsaprng_check_device_error()
     got_v, got_f = _decode(rec_v), _decode(rec_f)
     ref = oracle.battery_values(r.cpu().numpy())
+    assert int(ref["coll_msb"].sum()) == 4
     for name in ref:
         if name == "reserved":
             continue
@@ -115,7 +123,7 @@ def test_battery_of_stored_values(R):
         assert np.array_equal(got_f[name], ref[name]), name
     # the flattened vector-mode output: substreams seen interleaved
     g = R.rsaprng_create_ex(inst.p, inst.q, inst.e, inst.m0, 1)
-    m = 3 * (1 << 14) + 999
+    m = (20 << 14) + 999
     rv = torch.empty(m, dtype=torch.float64, device="cuda")
     R.rsaprng_generate_vector(g, 64, 12345, m, None, rv)
     log("battery of vector-mode values", m)
@@ -127,4 +135,5 @@ def test_battery_of_stored_values(R):
         if name == "reserved":
             continue
         assert np.array_equal(got[name], ref[name]), name
-    assert int(got["coll"].sum()) == 3 and int(got["outputs"][0]) == m
+    assert int(got["coll"].sum()) == 20 and int(got["coll_msb"].sum()) == 1
+    assert int(got["outputs"][0]) == m
