@@ -542,13 +542,17 @@ def verify_served(srv, insts, inst, k0, cnt, threads=None):
                     "from the arena" % n}
 
 
-def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=27, chunk_log2=24,
-               verify=True):
+def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=26, chunk_log2=24,
+               verify=True, policy="sf", compare=True):
     """Served workload: 100,000 device-resident instances, requests (instance
     uniform, k0 < 2^40, length log-uniform in [2^10, 2^24)) arriving as a Poisson
-    stream; continuous batching with a 64 GiB output arena.  Offered load is a
-    fraction rho of the server's own saturated capacity (every request of a
-    trace submitted at once)."""
+    stream; continuous batching with a 64 GiB output arena, iterations of
+    2^iter_log2 outputs, at most 2^chunk_log2 per request and iteration, the
+    requests with the fewest outputs left first (policy "sf") or round robin
+    ("rr").  Offered load is a fraction rho of the server's own saturated
+    capacity (every request of a trace submitted at once).  With compare, a
+    round-robin server with iterations of 2^27 outputs runs the saturated trace
+    and the highest load of the sweep beside it."""
     import numpy as np
 
     import inputs
@@ -566,16 +570,18 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=27, c
 
     chunk = 1 << chunk_log2
     cfg, tune_ms = tune_served(R, torch, stream, pool, *trace(64), chunk)
-    log("served config", cfg.as_dict(), "iteration 2^%d outputs, chunk 2^%d" % (iter_log2,
-                                                                              chunk_log2))
+    pol = {"rr": R.SRV_ROUND_ROBIN, "sf": R.SRV_SHORTEST_FIRST}[policy]
+    log("served config", cfg.as_dict(), "iteration 2^%d outputs, chunk 2^%d, %s" % (
+        iter_log2, chunk_log2, {"rr": "round robin", "sf": "shortest first"}[policy]))
     srv = R.Server(pool, arena_bytes=64 << 30, iter_outputs=1 << iter_log2, chunk_outputs=chunk,
-                   cfg=cfg)
+                   cfg=cfg, policy=pol)
 
     res = {"workload": "100000 instances (e from {3,5,7,17,257,65537}), requests: instance "
                        "uniform, k0 < 2^40, count = floor(2^(10+14u)); Poisson arrivals; "
                        "64 GiB output arena; u64+f64 outputs",
            "config": cfg.as_dict(), "iteration_outputs": 1 << iter_log2,
-           "chunk_outputs": chunk}
+           "chunk_outputs": chunk,
+           "policy": {"rr": "round robin", "sf": "shortest first"}[policy]}
     # saturated capacity: a trace submitted at once
     inst, k0, cnt = trace(40000)
     t_adm, t_done = srv.replay(inst, k0, cnt, np.zeros(len(inst)))
@@ -628,6 +634,18 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=27, c
 
     res["headline"] = poisson(rho_main, 2.0, 10.0)
     res["sweep"] = [poisson(r, 1.0, 4.0) for r in sweep]
+    if compare:
+        main = srv
+        srv = R.Server(pool, arena_bytes=64 << 30, iter_outputs=1 << 27, chunk_outputs=chunk,
+                       cfg=cfg, policy=R.SRV_ROUND_ROBIN)
+        inst, k0, cnt = trace(40000)
+        t_adm, t_done = srv.replay(inst, k0, cnt, np.zeros(len(inst)))
+        cap_main, cap = cap, float(cnt.sum()) / float(t_done.max()) / 1e9
+        log("round robin, iteration 2^27: saturated %.1f Gnum/s" % cap)
+        res["round_robin_2p27"] = {"saturated_gnumbers_per_s": cap,
+                                   "high_load": poisson(max(sweep), 1.0, 4.0)}
+        srv.close()
+        srv, cap = main, cap_main
     if verify:
         res["verified"] = verify_served(srv, insts, *trace(256))
         log("served verified: %d requests, %d outputs, equal: %s" % (
@@ -888,9 +906,10 @@ def main():
                          "--config: that configuration, no autotuning)")
     ap.add_argument("--verify-cap", type=float, default=120.0, metavar="SECONDS",
                     help="time cap of the batched workload's comparison with the oracle")
-    ap.add_argument("--served-only", default="", metavar="ITER,CHUNK",
-                    help="only the served workload, with iterations of 2^ITER outputs and "
-                         "per-request chunks of 2^CHUNK (no comparison with the oracle)")
+    ap.add_argument("--served-only", default="", metavar="ITER,CHUNK[,POLICY]",
+                    help="only the served workload, with iterations of 2^ITER outputs, "
+                         "per-request chunks of 2^CHUNK and POLICY sf (shortest first, the "
+                         "default) or rr (round robin) (no comparison with the oracle)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched uneven workload, without the plain per-request "
                          "launches (with --config: that configuration, no autotuning)")
@@ -940,8 +959,10 @@ def main():
         print(json.dumps(res))
         return
     if args.served_only:
-        it, ch = (int(x) for x in args.served_only.split(","))
-        res = run_served(R, torch, stream, iter_log2=it, chunk_log2=ch, verify=False)
+        parts = args.served_only.split(",")
+        it, ch = int(parts[0]), int(parts[1])
+        res = run_served(R, torch, stream, iter_log2=it, chunk_log2=ch, verify=False,
+                         policy=parts[2] if len(parts) > 2 else "sf", compare=False)
         print(json.dumps(res))
         return
     if args.consume_only:

@@ -335,7 +335,12 @@ typedef struct {
   uint64_t chunk_outputs;     /* max outputs of one request per iteration (0 = default 2^22) */
   size_t max_queue;           /* max waiting requests (0 = 1<<20) */
   rsaprng_config cfg;
+  int policy;                 /* order of the requests' chunks in an iteration:
+                                 RSAPRNG_SRV_ROUND_ROBIN (0) or RSAPRNG_SRV_SHORTEST_FIRST
+                                 (fewest outputs left first) */
 } rsaprng_server_opts;
+#define RSAPRNG_SRV_ROUND_ROBIN 0
+#define RSAPRNG_SRV_SHORTEST_FIRST 1
 typedef struct {
   uint64_t tag;
   const uint64_t* c;          /* device pointers into the arena */
@@ -367,7 +372,8 @@ int rsaprng_server_stats(rsaprng_server_t s, uint64_t* iterations, uint64_t* out
 int rsaprng_server_replay(rsaprng_server_t s, size_t n, const uint32_t* inst, const uint64_t* k0,
                           const uint64_t* count, const double* t_arrival, double* t_admit,
                           double* t_done);
-/* Host-only dry run of the server's scheduler, for tests (no device).  Request i
+/* Host-only dry run of the server's scheduler, for tests (no device), with the
+ * given policy (RSAPRNG_SRV_*).  Request i
  * arrives before iteration arrive_iter[i] (non-decreasing); every iteration
  * completes before the next; a finished request is released hold_iters
  * iterations later.  One record of seven words per planned chunk -- request,
@@ -375,8 +381,8 @@ int rsaprng_server_replay(rsaprng_server_t s, size_t n, const uint32_t* inst, co
  * state, 2 saves state at its end), state slot -- is written to log while
  * fewer than max_log have been written.  Returns the number of chunks or a status. */
 int64_t rsaprng_server_simulate(const rsaprng_config* cfg, uint64_t arena_elems,
-                                uint64_t iter_outputs, uint64_t chunk_outputs, size_t n,
-                                const uint64_t* k0, const uint64_t* count,
+                                uint64_t iter_outputs, uint64_t chunk_outputs, int policy,
+                                size_t n, const uint64_t* k0, const uint64_t* count,
                                 const uint64_t* arrive_iter, uint64_t hold_iters, uint64_t* log,
                                 size_t max_log);
 void rsaprng_server_destroy(rsaprng_server_t s);

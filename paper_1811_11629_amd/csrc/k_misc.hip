@@ -68,9 +68,9 @@ __global__ __launch_bounds__(256) void k_leadin_state(LaunchArgs a, ChainStart* 
 // once per pair; with LAZY the steps are lcg_lazy's and top their largest hi32
 // (the sum is exact when it stays below kHiUnreduced).
 template <bool LAZY>
-__device__ __forceinline__ void lane_skip_sum(u64 s, int per, u64& lo, u64& hi, u32& top) {
+__device__ __forceinline__ void lane_skip_sum(u64 s, int per, u64& lo, u32& hi, u32& top) {
   lo = 0;
-  hi = 0;
+  hi = 0;  // below per / 2: a 32-bit count, one add with the carry per pair
   for (int i = 0; i < per; i += 2) {
     if (i) s = walk_step<LAZY>(s, top);
     const u64 s1 = walk_step<LAZY>(s, top);
@@ -100,7 +100,8 @@ __global__ __launch_bounds__(256) void k_sums(LaunchArgs a) {
   // exact integer sum of the lane's skips: lo + 2^64 hi, hi < per / 2 (skips <
   // 2^63); lazy steps first, the walk redone with reduced steps in a wave where
   // one of them may be unreduced
-  u64 lo, hi;
+  u64 lo;
+  u32 hi;
   u32 top = 0;
   lane_skip_sum<true>(s0, per, lo, hi, top);
   if (wave_any_unreduced(top)) lane_skip_sum<false>(s0, per, lo, hi, top);

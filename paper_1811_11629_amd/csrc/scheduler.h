@@ -59,6 +59,8 @@ class Arena {
 };
 
 enum SrvState { kSrvWaiting = 0, kSrvActive = 1, kSrvDone = 2 };
+// Order in which an iteration takes the admitted requests' next chunks.
+enum SrvPolicy { kSrvRoundRobin = 0, kSrvShortestFirst = 1 };
 
 struct SrvReq {
   uint64_t tag = 0;
@@ -77,8 +79,9 @@ class Scheduler {
   // T: tile size of the kernel configuration (a power of two dividing 2^20).
   // Every chunk but a request's last ends on a multiple of T, so the next chunk
   // can start from the chain state at a tile boundary.
-  Scheduler(u64h arena_elems, uint32_t nslots, u64h T, u64h iter_outputs, u64h chunk_outputs)
-      : arena_(arena_elems), T_(T) {
+  Scheduler(u64h arena_elems, uint32_t nslots, u64h T, u64h iter_outputs, u64h chunk_outputs,
+            int policy = kSrvRoundRobin)
+      : arena_(arena_elems), T_(T), policy_(policy) {
     chunk_ = std::max<u64h>(chunk_outputs, T);
     iter_ = std::max<u64h>(iter_outputs, chunk_);
     free_slots_.resize(nslots);
@@ -104,20 +107,33 @@ class Scheduler {
     }
   }
 
-  // The next iteration: one chunk per admitted request, up to iter outputs in
-  // all, round robin (an iteration starts after the last request the previous
-  // one planned).  Returns false if there is nothing to run.  Requests whose
-  // last chunk is planned go to `finishing`.
+  // The next iteration: at most one chunk per admitted request, up to iter
+  // outputs in all.  Round robin: an iteration starts after the last request
+  // the previous one planned.  Shortest first: the requests with the fewest
+  // outputs left go first (admission order between equals), which keeps most
+  // requests, the short ones, from waiting behind long ones.  Returns false if
+  // there is nothing to run.  Requests whose last chunk is planned go to
+  // `finishing`.
   bool plan(std::vector<PlanIn>& out, std::vector<SrvReq*>& finishing, u64h* total) {
     out.clear();
     finishing.clear();
     u64h budget = iter_, sum = 0;
     const size_t na = active_.size();
     size_t next_rr = rr_;
-    for (size_t i = 0; i < na && budget > 0; ++i) {
-      SrvReq* r = active_[(rr_ + i) % na];
+    const bool sf = policy_ == kSrvShortestFirst;
+    if (sf) {
+      order_.clear();
+      for (size_t i = 0; i < na; ++i)
+        if (!active_[i]->scheduled_all) order_.push_back(active_[i]);
+      std::stable_sort(order_.begin(), order_.end(), [](const SrvReq* a, const SrvReq* b) {
+        return left(a) < left(b);
+      });
+    }
+    const size_t n_try = sf ? order_.size() : na;
+    for (size_t i = 0; i < n_try && budget > 0; ++i) {
+      SrvReq* r = sf ? order_[i] : active_[(rr_ + i) % na];
       if (r->scheduled_all) continue;
-      const u64h remaining = (r->k0 + r->count) - r->pos;  // mod 2^64: k0 + count may be 2^64
+      const u64h remaining = left(r);
       u64h len = std::min(std::min(remaining, chunk_), budget);
       if (len < remaining) {
         const u64h end = (r->pos + len) & ~(T_ - 1);
@@ -145,7 +161,7 @@ class Scheduler {
       }
       if (!last && (next & (kBlock - 1)) != 0) in.flags |= kReqWriteEnd;
       out.push_back(in);
-      next_rr = rr_ + i + 1;
+      if (!sf) next_rr = rr_ + i + 1;
       r->pos = next;
       budget -= len;
       sum += len;
@@ -171,6 +187,9 @@ class Scheduler {
     free_slots_.push_back(r->slot);
   }
 
+  // outputs of r not yet planned; mod 2^64, since k0 + count may be 2^64
+  static u64h left(const SrvReq* r) { return (r->k0 + r->count) - r->pos; }
+
   size_t waiting() const { return waiting_.size(); }
   size_t active() const { return active_.size(); }
   u64h arena_size() const { return arena_.size(); }
@@ -178,6 +197,8 @@ class Scheduler {
  private:
   Arena arena_;
   u64h T_, chunk_, iter_;
+  int policy_;
+  std::vector<SrvReq*> order_;  // shortest first: this iteration's order
   std::vector<uint32_t> free_slots_;
   std::deque<SrvReq*> waiting_;
   std::vector<SrvReq*> active_;

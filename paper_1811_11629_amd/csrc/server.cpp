@@ -109,8 +109,9 @@ int rsaprng_server_s::init() {
   if (!opts.max_queue) opts.max_queue = 1u << 20;
   arena_elems = opts.arena_bytes / 16;
   if (arena_elems == 0) return RSAPRNG_E_ARG;
+  if (opts.policy != kSrvRoundRobin && opts.policy != kSrvShortestFirst) return RSAPRNG_E_ARG;
   sched.reset(new Scheduler(arena_elems, kSlots, tile_size(cfg), opts.iter_outputs,
-                            opts.chunk_outputs));
+                            opts.chunk_outputs, opts.policy));
   device = pool_device(pool);
   DeviceGuard g(device);
   int rc = device_get(&dev);
@@ -347,12 +348,14 @@ int rsaprng_server_replay(rsaprng_server_t s, size_t n, const uint32_t* inst, co
 }
 
 int64_t rsaprng_server_simulate(const rsaprng_config* cfg, uint64_t arena_elems,
-                                uint64_t iter_outputs, uint64_t chunk_outputs, size_t n,
+                                uint64_t iter_outputs, uint64_t chunk_outputs, int policy,
+                                size_t n,
                                 const uint64_t* k0, const uint64_t* count,
                                 const uint64_t* arrive_iter, uint64_t hold_iters, uint64_t* log,
                                 size_t max_log) {
   if (n && (!k0 || !count || !arrive_iter)) return RSAPRNG_E_NULL;
   if (arena_elems == 0) return RSAPRNG_E_ARG;
+  if (policy != kSrvRoundRobin && policy != kSrvShortestFirst) return RSAPRNG_E_ARG;
   for (size_t i = 0; i < n; ++i) {
     if (count[i] == 0 || count[i] > arena_elems) return RSAPRNG_E_RANGE;
     if (count[i] - 1 > ~0ull - k0[i]) return RSAPRNG_E_RANGE;
@@ -360,7 +363,7 @@ int64_t rsaprng_server_simulate(const rsaprng_config* cfg, uint64_t arena_elems,
   }
   const rsaprng_config c = resolve_config(cfg);
   Scheduler sch(arena_elems, kSlots, tile_size(c), iter_outputs ? iter_outputs : 1ull << 26,
-                chunk_outputs ? chunk_outputs : 1ull << 22);
+                chunk_outputs ? chunk_outputs : 1ull << 22, policy);
   std::vector<SrvReq> reqs(n);
   std::deque<std::pair<uint64_t, SrvReq*>> held;  // (release iteration, request)
   std::vector<PlanIn> plan;

@@ -79,7 +79,10 @@ class rsaprng_config(C.Structure):
 class rsaprng_server_opts(C.Structure):
     _fields_ = [("arena_bytes", C.c_size_t), ("iter_outputs", C.c_uint64),
                 ("chunk_outputs", C.c_uint64), ("max_queue", C.c_size_t),
-                ("cfg", rsaprng_config)]
+                ("cfg", rsaprng_config), ("policy", C.c_int)]
+
+
+SRV_ROUND_ROBIN, SRV_SHORTEST_FIRST = 0, 1
 
 
 class rsaprng_completion(C.Structure):
@@ -154,8 +157,8 @@ _SIGS = {
     "rsaprng_server_read": (_i32, [_vp, _u64, _u64, _u64, _vp, _vp, _vp]),
     "rsaprng_server_release": (_i32, [_vp, _u64]),
     "rsaprng_server_replay": (_i32, [_vp, _sz, _vp, _vp, _vp, _vp, _vp, _vp]),
-    "rsaprng_server_simulate": (C.c_int64, [C.POINTER(rsaprng_config), _u64, _u64, _u64, _sz,
-                                            _vp, _vp, _vp, _u64, _vp, _sz]),
+    "rsaprng_server_simulate": (C.c_int64, [C.POINTER(rsaprng_config), _u64, _u64, _u64, _i32,
+                                            _sz, _vp, _vp, _vp, _u64, _vp, _sz]),
     "rsaprng_server_now": (_dbl, [_vp]),
     "rsaprng_server_stats": (_i32, [_vp, C.POINTER(_u64), C.POINTER(_u64), C.POINTER(_u64),
                                     C.POINTER(_u64)]),
@@ -462,7 +465,7 @@ def stats_decode(t) -> List[dict]:
 
 
 def server_simulate(k0, count, arrive_iter, arena_elems, iter_outputs=0, chunk_outputs=0,
-                    hold_iters=0, cfg=None):
+                    hold_iters=0, cfg=None, policy=SRV_ROUND_ROBIN):
     """Host-only dry run of the server's scheduler; returns an (nchunks, 7) uint64
     array: request, iteration, first index, count, arena offset, flags, slot."""
     import numpy as np
@@ -471,14 +474,14 @@ def server_simulate(k0, count, arrive_iter, arena_elems, iter_outputs=0, chunk_o
     arrive_iter = np.ascontiguousarray(arrive_iter, dtype=np.uint64)
     c = cfg if cfg is not None else rsaprng_config()
     n = len(k0)
-    nch = lib().rsaprng_server_simulate(C.byref(c), arena_elems, iter_outputs, chunk_outputs, n,
-                                        k0.ctypes.data, count.ctypes.data,
+    nch = lib().rsaprng_server_simulate(C.byref(c), arena_elems, iter_outputs, chunk_outputs,
+                                        policy, n, k0.ctypes.data, count.ctypes.data,
                                         arrive_iter.ctypes.data, hold_iters, None, 0)
     if nch < 0:
         raise RsaprngError(int(nch), "rsaprng_server_simulate")
     log = np.zeros((max(nch, 1), 7), dtype=np.uint64)
-    nch2 = lib().rsaprng_server_simulate(C.byref(c), arena_elems, iter_outputs, chunk_outputs, n,
-                                         k0.ctypes.data, count.ctypes.data,
+    nch2 = lib().rsaprng_server_simulate(C.byref(c), arena_elems, iter_outputs, chunk_outputs,
+                                         policy, n, k0.ctypes.data, count.ctypes.data,
                                          arrive_iter.ctypes.data, hold_iters, log.ctypes.data,
                                          nch)
     assert nch2 == nch
@@ -578,9 +581,9 @@ class Server:
     """An rsaprng_server_t (continuous batching over a pool)."""
 
     def __init__(self, pool: Pool, arena_bytes: int, iter_outputs=0, chunk_outputs=0, max_queue=0,
-                 cfg=None):
+                 cfg=None, policy=SRV_ROUND_ROBIN):
         opts = rsaprng_server_opts(arena_bytes, iter_outputs, chunk_outputs, max_queue,
-                                   cfg if cfg is not None else rsaprng_config())
+                                   cfg if cfg is not None else rsaprng_config(), policy)
         h = C.c_void_p()
         _check(lib().rsaprng_server_create(pool.h, C.byref(opts), C.byref(h)),
                "rsaprng_server_create")

@@ -30,7 +30,8 @@ int main(int argc, char** argv) {
     const uint32_t nslots = 1 + rng() % 48;
     const u64h T = 1ull << (8 + rng() % 6);
     const u64h iter = T * (1 + rng() % 64), chunk = T * (1 + rng() % 16);
-    Scheduler sc(arena, nslots, T, iter, chunk);
+    // both policies, alternately
+    Scheduler sc(arena, nslots, T, iter, chunk, trial % 2 ? kSrvShortestFirst : kSrvRoundRobin);
     const u64h budget = std::max(iter, std::max(chunk, T));  // the scheduler's own rounding
     const int nreq = 150;
     std::vector<std::unique_ptr<SrvReq>> reqs;

@@ -77,6 +77,7 @@ CFGS = {
     "crt-512": dict(variant=2, lanes_per_tile=512),
     "crt-serial": dict(variant=2, prefix=2),
     "mont-serial-512": dict(variant=1, lanes_per_tile=512, prefix=2),
+    "crt-twopass-shortest-first": dict(variant=2),
 }
 
 
@@ -86,8 +87,9 @@ def test_mix_matches_oracle_and_alone(R, pool_insts, name):
     reqs = make_requests(90, 777 + len(name), len(pool_insts))
     log("server mix", name, "requests", len(reqs), "outputs", sum(r[2] for r in reqs))
     pool = R.Pool.from_instances(pool_insts)
+    policy = R.SRV_SHORTEST_FIRST if "shortest-first" in name else R.SRV_ROUND_ROBIN
     srv = R.Server(pool, arena_bytes=16 * (1 << 21), iter_outputs=24 * T,
-                   chunk_outputs=3 * T + 123, cfg=cfg)
+                   chunk_outputs=3 * T + 123, cfg=cfg, policy=policy)
     try:
         mix = serve(R, srv, reqs)
         st = srv.stats()

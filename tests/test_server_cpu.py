@@ -120,6 +120,41 @@ def test_admission_waits_for_arena(R):
     assert reqs[2][0][1] >= first_done + 1 + hold
 
 
+def test_random_trace_shortest_first(R):
+    # the same invariants under the shortest-first policy
+    rng = inputs.SplitMix64(20240612)
+    n = 300
+    k0 = [rng.next() >> 24 for _ in range(n)]
+    count = [1 + int(2.0 ** (16 * rng.unit53())) for _ in range(n)]
+    arrive = np.cumsum([rng.next() % 3 for _ in range(n)]).tolist()
+    arena, iter_o, chunk_o, hold = 1 << 19, 10 * T, 3 * T + 123, 2
+    log = R.server_simulate(k0, count, arrive, arena, iter_o, chunk_o, hold,
+                            policy=R.SRV_SHORTEST_FIRST)
+    check_schedule(log, k0, count, arrive, arena, iter_o, chunk_o, hold)
+
+
+def test_shortest_first_order(R):
+    # five requests arrive together; an iteration holds four tiles: shortest
+    # first fills it with the fewest-outputs-left requests, so the short ones
+    # finish in the first iterations and the long one last, where round robin
+    # gives every request a chunk per iteration
+    count = [40 * T, 2 * T, T, 3 * T, T // 2]
+    k0 = [i * BLOCK for i in range(5)]
+    arrive = [0] * 5
+    sf = by_request(R.server_simulate(k0, count, arrive, 1 << 24, 4 * T, 2 * T,
+                                      policy=R.SRV_SHORTEST_FIRST), 5)
+    done = [ch[-1][1] for ch in sf]
+    assert done[4] == 0 and done[2] == 0 and done[1] == 0    # T/2 + T + 2T in iteration 0
+    # then 3T takes two iterations of at most one 2T chunk, beside the long one's
+    assert done[3] == 2 and done[0] == max(done)
+    assert all(ch[0][1] == 0 for ch in sf[1:3])
+    assert sf[0][0][1] >= 1                                  # the long one waits
+    rr = by_request(R.server_simulate(k0, count, arrive, 1 << 24, 4 * T, 2 * T), 5)
+    assert rr[0][0][1] == 0                                  # round robin starts it at once
+    with pytest.raises(R.RsaprngError):
+        R.server_simulate(k0, count, arrive, 1 << 24, 4 * T, 2 * T, policy=7)
+
+
 def test_rejects_bad_traces(R):
     with pytest.raises(R.RsaprngError):
         R.server_simulate([0], [10], [0], 5)            # larger than the arena
