@@ -73,10 +73,13 @@ struct LeadIn {
   uint64_t lead_tiles = 0;
 };
 
-// Computed on the device per chain: the skip at S and the message before S.
+// Computed on the device per chain: the skip at S and the message before S,
+// and that message's residues mod p and mod q (in (-p, p) and (-q, q)) for the
+// CRT kernels.
 struct alignas(16) ChainStart {
   uint64_t s_S;
   uint64_t m_base;
+  double rp, rq;
 };
 
 // Per-launch control words owned by the library (one per stream / batch / server).

@@ -41,6 +41,8 @@ __global__ __launch_bounds__(256) void k_chain_setup(LaunchArgs a) {
     ChainStart cs;
     cs.s_S = s_S;
     cs.m_base = m_base;
+    cs.rp = res_p(m_base, P);
+    cs.rq = res_q(m_base, P);
     a.cstart[c] = cs;
   }
 }
@@ -55,11 +57,13 @@ __global__ __launch_bounds__(256) void k_leadin_state(LaunchArgs a, ChainStart* 
   const u32 l = blockIdx.x * 256 + threadIdx.x;
   if (l >= a.nchain) return;
   const Chain L = a.chain[l];
-  const u64 n = a.inst[L.inst].n;
+  const rsaprng_params P = a.inst[L.inst];
   const u64 q = ((u64)(L.first + L.ntiles) << (a.tile_log2 - a.chunk_log2)) - 1;
   ChainStart cs;
-  cs.m_base = addmod(a.excl[q], a.agg[q], n);
+  cs.m_base = addmod(a.excl[q], a.agg[q], P.n);
   cs.s_S = mulmod_q(a.cstart[l].s_S, a.at[L.ntiles]);
+  cs.rp = res_p(cs.m_base, P);
+  cs.rq = res_q(cs.m_base, P);
   out[L.slot] = cs;
 }
 

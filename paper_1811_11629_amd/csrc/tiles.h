@@ -1179,8 +1179,8 @@ __device__ __forceinline__ void chain3(const LaunchArgs& a, TileShared<WG, MODE>
   double cp = 0.0, cq = 0.0;  // CRT carry: residues of the message before the step
   u64 cm = 0;                 // Montgomery carry: the message before the step
   if constexpr (VAR == kVariantCrt) {
-    cp = res_p(cs0.m_base, P);
-    cq = res_q(cs0.m_base, P);
+    cp = cs0.rp;  // residues of m_base, from the chain setup
+    cq = cs0.rq;
   } else {
     cm = cs0.m_base;
   }
