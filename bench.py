@@ -87,13 +87,40 @@ DEVICE_SOURCES = ("k_crt_gen.hip", "k_mont_gen.hip", "common.h", "devmath.h", "t
                   "../../include/rsaprng.h")
 
 
+def code_only(text: str) -> str:
+    """C/C++ source without its comments, whitespace runs collapsed to one
+    space (string and character literals kept as written)."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+            out.append(" ")
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_source_hash() -> str:
-    """Hash of the sources the generate-mode tile kernels are compiled from."""
+    """Hash of the code (comments and layout aside) of the sources the
+    generate-mode tile kernels are compiled from."""
     h = hashlib.sha256()
     d = os.path.join(ROOT, "paper_1811_11629_amd", "csrc")
     for f in DEVICE_SOURCES:
-        with open(os.path.join(d, f), "rb") as fh:
-            h.update(os.path.basename(f).encode() + fh.read())
+        with open(os.path.join(d, f), encoding="utf-8") as fh:
+            h.update(os.path.basename(f).encode() + code_only(fh.read()).encode())
     return h.hexdigest()[:16]
 
 
@@ -155,13 +182,18 @@ def time_graph(batch, stream, steps, warmup, torch):
 def tile_kernel_name(cfg, exponent=0, mode="generate") -> str:
     """The tile kernel of a configuration, as rocprofv3 lists it.  A generate
     launch whose instances all have e = 3 takes the chain-serial CRT kernels
-    specialised to it (two chunks per wave), whose name carries the exponent."""
+    specialised to it (two chunks of 8 or one of 16 indices per lane), whose
+    name carries the exponent; other chain-serial launches with 16 indices per
+    lane take two chunks of 8."""
     form = {0: "k_gen2", 1: "k_gen1", 2: "k_gen3"}[cfg.prefix]
-    r = "" if cfg.prefix == 1 else ", %d" % cfg.chunks_per_wave
-    ek = ", 3" if (mode == "generate" and exponent == 3 and cfg.prefix == 2 and cfg.variant == 2
-                   and cfg.chunks_per_wave == 2) else ""
+    spec = (mode == "generate" and exponent == 3 and cfg.prefix == 2 and cfg.variant == 2)
+    per, chunks = cfg.per_lane, cfg.chunks_per_wave
+    if cfg.prefix == 2 and per == 16 and not spec:
+        per, chunks = 8, 2
+    r = "" if cfg.prefix == 1 else ", %d" % chunks
+    ek = ", 3" if spec and (per, chunks) in ((8, 2), (16, 1)) else ""
     return "%s<%d, %d%s, %d, %d%s> (%s, %s)" % (
-        form, cfg.lanes_per_tile, cfg.per_lane, r, cfg.variant, 0 if mode == "generate" else 1,
+        form, cfg.lanes_per_tile, per, r, cfg.variant, 0 if mode == "generate" else 1,
         ek, "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64", mode)
 
 

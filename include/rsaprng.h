@@ -240,7 +240,10 @@ typedef struct {
                            decoupled look-back over the preceding tiles; 2 chain-serial:
                            one work-group walks each chain (a request's indices inside
                            one 2^20 block) in order, carrying the message prefix */
-  int chunks_per_wave;  /* two passes and chain-serial: 64*per_lane chunks per wave per tile */
+  int chunks_per_wave;  /* two passes and chain-serial: 64*per_lane chunks per wave per tile
+                           (1 for chain-serial with per_lane 16, which runs as such for
+                           CRT generate launches whose instances all have e = 3; other
+                           launches take two chunks of 8 indices per lane, the same tile) */
 } rsaprng_config;
 
 /* One-shot batched launches over a pool (reqs is a host array). */

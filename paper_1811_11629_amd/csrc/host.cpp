@@ -211,7 +211,7 @@ struct Device {
   int ncu = 0;
   uint64_t* pow2 = nullptr;    // a^(2^i) mod Q, i < 64
   uint64_t* powv8 = nullptr;   // a^(8 l) mod Q, l < 1024
-  uint64_t* powv16 = nullptr;  // a^(16 l) mod Q, l < 256
+  uint64_t* powv16 = nullptr;  // a^(16 l) mod Q, l < 512
   uint64_t* at[3] = {};        // a^(T j) mod Q, j < 2^20 / T, for T = 2048, 4096, 8192
   uint64_t* pl[3] = {};        // a^((T/64) l) mod Q, l < 64
   u64h gc = 0;
@@ -267,7 +267,7 @@ int device_get(Device** out) {
   int rc = RSAPRNG_OK;
   if (!rc) rc = upload_table(&d->pow2, t2);
   if (!rc) rc = upload_table(&d->powv8, power_table(8, 1024));
-  if (!rc) rc = upload_table(&d->powv16, power_table(16, 256));
+  if (!rc) rc = upload_table(&d->powv16, power_table(16, 512));
   for (int i = 0; i < 3 && !rc; ++i) {
     const u64h T = 2048ull << i;
     rc = upload_table(&d->at[i], power_table(T, kBlock / T));
@@ -435,10 +435,14 @@ rsaprng_config resolve_config(const rsaprng_config* cfg) {
   if (c.prefix != kPrefixTwoPass && c.prefix != kPrefixLookback && c.prefix != kPrefixSerial)
     c.prefix = env_int("RSAPRNG_PREFIX", kPrefixTwoPass);
   if (c.prefix == kPrefixSerial) {
-    // chain-serial: (256, 8, r) for r = 2, 4 and (512, 8, 2)
-    c.per_lane = 8;
+    // chain-serial: (256, 8, r) for r = 2, 4, (512, 8, 2) and (256 or 512, 16, 1)
     if (c.lanes_per_tile != 512) c.lanes_per_tile = 256;
-    if (c.lanes_per_tile == 512 || c.chunks_per_wave != 4) c.chunks_per_wave = 2;
+    if (c.per_lane == 16) {
+      c.chunks_per_wave = 1;
+    } else {
+      c.per_lane = 8;
+      if (c.lanes_per_tile == 512 || c.chunks_per_wave != 4) c.chunks_per_wave = 2;
+    }
   } else if (c.prefix == kPrefixTwoPass) {
     // shapes built for two passes: (256, 8, r) for r = 1, 2, 4 and (512, 8, 2)
     c.per_lane = 8;
@@ -625,6 +629,14 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
   shape.mode = mode;
   shape.prefix = c.prefix;
   shape.r = c.chunks_per_wave;
+  if (c.prefix == kPrefixSerial && c.per_lane == 16 &&
+      !(c.variant == kVariantCrt && mode == kModeGenerate && shared_e == 3)) {
+    // 16 indices per lane are built for CRT generate launches of e = 3 only
+    // (elsewhere their registers would spill); other launches take two chunks
+    // of 8, the same tile (the plan and the prefix passes do not change)
+    shape.v = 8;
+    shape.r = 2;
+  }
   shape.e = shared_e;
   shape.grid = grid_for(d, shape, c, c.prefix == kPrefixSerial ? (u64h)nrun : ntiles);
   LaunchArgs a;
@@ -655,7 +667,7 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
   if (T != (2048ull << ti)) return RSAPRNG_E_ARG;
   a.at = d->at[ti];
   a.pl = d->pl[ti];
-  a.powv = c.per_lane == 8 ? d->powv8 : d->powv16;
+  a.powv = shape.v == 8 ? d->powv8 : d->powv16;
   a.gc = d->gc;
   if (mode == kModeBattery) {
     if (!c.persistent || !sc.urn2 || (u64h)shape.grid > sc.urn2_slots) return RSAPRNG_E_ARG;
@@ -1128,12 +1140,15 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
     c2.variant = kVariantCrt;
     c = resolve_config(&c2);
   }
-  if (mode == kModeBattery && (c.prefix != kPrefixSerial || !c.persistent)) {
+  if (mode == kModeBattery &&
+      (c.prefix != kPrefixSerial || !c.persistent || c.per_lane != 8)) {
     // the battery's collision trials need one work-group walking each chain,
-    // and a persistent grid (one set of leading-bit bitmaps per work-group)
+    // and a persistent grid (one set of leading-bit bitmaps per work-group);
+    // its tuples are counted from lanes of 8 consecutive indices
     rsaprng_config c2 = c;
     c2.prefix = kPrefixSerial;
     c2.persistent = 1;
+    c2.per_lane = 8;
     c = resolve_config(&c2);
   }
   std::vector<Chain> plan;
@@ -1578,7 +1593,8 @@ std::vector<rsaprng_config> tune_space() {
                                   {kPrefixTwoPass, 256, 8, 4}, {kPrefixTwoPass, 512, 8, 2},
                                   {kPrefixLookback, 256, 8, 1}, {kPrefixLookback, 512, 8, 1},
                                   {kPrefixLookback, 256, 16, 1}, {kPrefixSerial, 256, 8, 2},
-                                  {kPrefixSerial, 256, 8, 4}, {kPrefixSerial, 512, 8, 2}};
+                                  {kPrefixSerial, 256, 8, 4}, {kPrefixSerial, 512, 8, 2},
+                                  {kPrefixSerial, 256, 16, 1}, {kPrefixSerial, 512, 16, 1}};
   std::vector<rsaprng_config> out;
   for (int var : {kVariantCrt, kVariantMont})
     for (const auto& s : shapes)

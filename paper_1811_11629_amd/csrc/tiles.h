@@ -280,15 +280,15 @@ __device__ __forceinline__ double reduce_res(double x, double P, double Pinv) {
 // m_i is congruent to b + s_0 + ... + s_i.  Only m mod p and m mod q enter the
 // encryption, so no 64-bit modular addition is done: each skip s = h 2^32 + l
 // adds fold_p(h) + l to the running residue mp (fold_p(h) in (-p, p)), so after
-// V <= 8 skips |mp| < p + 8 (p + 2^32) < 2^37, a valid input of the ladder's
-// squaring (likewise mod q).
+// V <= 16 skips |mp| < p + 16 (p + 2^32) < 2^38, a valid input of the ladder's
+// opening squaring (below 2^42), and of reduce_res otherwise (likewise mod q).
 template <int V>
 struct MsgRes {
   const u64 (&S)[V];
   double Ap, Aq;  // bp, bq on entry; then the residues of the latest message
   template <int VAR, u32 E>
   __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
-    static_assert(V <= 8, "residue bound");
+    static_assert(V <= 16, "residue bound");
     const double h = (double)hi32(S[i]);
     const double l = (double)lo32(S[i]);
     Ap += fold_p(h, P) + l;
@@ -311,7 +311,7 @@ struct MsgResWalk {
   double Ap, Aq;  // bp, bq on entry; then the residues of the latest message
   template <int VAR, u32 E>
   __device__ __forceinline__ u64 enc(int i, const rsaprng_params& P, double& cd) {
-    static_assert(V <= 8, "residue bound");
+    static_assert(V <= 16, "residue bound");
     if (i) s = lcg_next(s);
     const double h = (double)hi32(s);
     const double l = (double)lo32(s);
@@ -370,6 +370,41 @@ __device__ __forceinline__ void store_chunk(u64* dst, const u64* x, int src, int
 #pragma unroll
     for (int j = 0; j < 8; ++j) dst[(u64)j * 64 + lane] = x[j * 8 * kXRow + src8];
   }
+}
+
+// Row stride of the 64 x 16 block of a lane holding 16 consecutive indices: 16
+// values plus one word of padding.  The block fits in the wave's share of the
+// transpose buffer (2 x 64 x kXRow words), and c and then r pass through it.
+constexpr int kXRow16 = 17;
+static_assert(64 * kXRow16 <= 2 * 64 * kXRow, "one 64 x 16 block per wave");
+
+// Stores a wave's 64 x 16 transposed block x (row = lane, 16 consecutive
+// outputs) to dst[0 .. 1024).  With dst 16-byte aligned, store j writes
+// elements 128 j + 2 lane and the next (row 8 j + lane / 8, columns 2 (lane %
+// 8) and the next): 1 KiB of contiguous output per store instruction, as for
+// the 64 x 8 blocks.  Otherwise store j writes element 64 j + lane (row 4 j +
+// lane / 16, column lane % 16), 512 contiguous bytes per instruction.  A16 as
+// for store_chunk.
+template <int A16>
+__device__ __forceinline__ void store_chunk16(u64* dst, const u64* x, int lane) {
+  if (A16 == 1 || (A16 == -1 && ((uintptr_t)dst & 15) == 0)) {
+    const int src = (lane >> 3) * kXRow16 + 2 * (lane & 7);
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      __builtin_nontemporal_store(
+          u64x2{x[j * 8 * kXRow16 + src], x[j * 8 * kXRow16 + src + 1]},
+          reinterpret_cast<u64x2*>(dst + (u64)j * 128 + 2 * lane));
+  } else {
+    const int src8 = (lane >> 4) * kXRow16 + (lane & 15);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) dst[(u64)j * 64 + lane] = x[j * 4 * kXRow16 + src8];
+  }
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
 // ---------------------------------------------------------------------------
@@ -601,7 +636,8 @@ struct TileShared {
 // Encryption and output of one tile for exponent E (0 = any exponent).  FAST:
 // every index of the tile is requested and both outputs are 16-byte aligned at
 // every lane's first index, so pairs are stored without predicates.
-template <int WG, int V, int VAR, int MODE, u32 E, bool FAST, int A16 = -1, class Msg>
+template <int WG, int V, int VAR, int MODE, u32 E, bool FAST, int A16 = -1, bool XB16 = false,
+          class Msg>
 __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                              const Chain& C, const rsaprng_params& P, Msg msg,
                                              u64 laneStart) {
@@ -633,6 +669,31 @@ __device__ __forceinline__ void tile_outputs(const LaunchArgs& a, TileShared<WG,
       __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else if constexpr (FAST && V == 16 && XB16) {
+      // (the kernels specialised to one exponent) The lane's 16 ciphertexts
+      // go to its row of the wave's 64 x 16 block and are stored from there;
+      // its 16 ratios wait in registers meanwhile and then take the same
+      // block.
+      const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+      u64* x = sh.xbuf + wave * (2 * 64 * kXRow);
+      u64 rv[V];
+#pragma unroll
+      for (int i = 0; i < V; ++i) {
+        double cd;
+        x[lane * kXRow16 + i] = msg.template enc<VAR, E>(i, P, cd);
+        rv[i] = (u64)__double_as_longlong(ratio_of(cd, P));
+      }
+      const u64 chunk0 = C.out_off + (laneStart - (u64)lane * V - C.k0);
+      wave_sync_lds();
+      if (oc) store_chunk16<A16>(oc + chunk0, x, lane);
+      if (orr) {
+        wave_sync_lds();
+#pragma unroll
+        for (int i = 0; i < V; ++i) x[lane * kXRow16 + i] = rv[i];
+        wave_sync_lds();
+        store_chunk16<A16>(reinterpret_cast<u64*>(orr) + chunk0, x, lane);
+      }
+      wave_sync_lds();
     } else if constexpr (FAST) {
       const u64 off0 = C.out_off + (laneStart - C.k0);
 #pragma unroll
@@ -877,7 +938,7 @@ __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG
                                               const Msg& msg, bool fast, u64 laneStart) {
   if constexpr (EK != 0) {
     if (fast)
-      tile_outputs<WG, V, VAR, MODE, EK, true, AL>(a, sh, C, P, msg, laneStart);
+      tile_outputs<WG, V, VAR, MODE, EK, true, AL, true>(a, sh, C, P, msg, laneStart);
     else
       tile_outputs<WG, V, VAR, MODE, EK, false>(a, sh, C, P, msg, laneStart);
   } else if (!fast) {
@@ -900,8 +961,8 @@ __device__ __forceinline__ void outputs_for_e(const LaunchArgs& a, TileShared<WG
 // path needs every index of the chunk requested; in the general kernels with
 // V = 8 its stores take any 8-byte-aligned output (store_chunk), the pair
 // stores of other V need 16-byte alignment, and so do the paths specialised
-// to one exponent with AL = 1 (the kernels for launches of one exponent);
-// with AL = -1 (the per-chain dispatch over exponents) they test it.
+// to one exponent with AL = 1 (the kernels for launches of one exponent, V = 8
+// or 16); with AL = -1 (the per-chain dispatch over exponents) they test it.
 template <int WG, int V, int VAR, int MODE, int EK = 0, int AL = 1, class Msg>
 __device__ __forceinline__ void chunk_outputs(const LaunchArgs& a, TileShared<WG, MODE>& sh,
                                               const Chain& C, const rsaprng_params& P,
@@ -1430,6 +1491,8 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
         if (s.e == 3) {
           if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
           if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
+          if (s.wg == 256 && s.v == 16 && s.r == 1) return launch3<256, 16, 1, VAR, MODE, 3>(a, s.grid, stream, occ);
+          if (s.wg == 512 && s.v == 16 && s.r == 1) return launch3<512, 16, 1, VAR, MODE, 3>(a, s.grid, stream, occ);
         }
         if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);
         if (s.wg == 512 && s.v == 8 && s.r == 2) return launch3<512, 8, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);

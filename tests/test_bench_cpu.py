@@ -34,3 +34,18 @@ def test_traffic_record_is_keyed_by_the_generate_kernel_sources():
     for o in ent.get("other_kernels", []):
         for k in ("kernel", "command", "fetch_size_kib", "write_size_kib", "hbm_bytes_per_launch"):
             assert k in o, k
+
+
+def test_source_hash_ignores_comments_and_layout_only():
+    import bench
+    base = "int f(int x) {\n  return x + 1;  // one\n}\n/* note */\nconst char* s = \"a // b\";\n"
+    same = "int f(int x) { return x + 1; }\n// other words\nconst char* s = \"a // b\"; /* x */\n"
+    assert bench.code_only(base) == bench.code_only(same)
+    # a changed operator, constant or string literal changes the code
+    for changed in (base.replace("x + 1", "x - 1"), base.replace("1;", "2;"),
+                    base.replace("a // b", "a / b")):
+        assert bench.code_only(changed) != bench.code_only(base)
+    # comment markers inside literals are code, and an escaped quote stays inside its literal
+    assert bench.code_only('char c = \'"\'; // x\nint y;') == "char c = '\"'; int y;"
+    assert bench.code_only('const char* t = "q\\"// not a comment";') == \
+        'const char* t = "q\\"// not a comment";'

@@ -32,7 +32,7 @@ def R():
 # prefix 0 two passes, 1 one pass with look-back, 2 chain-serial.
 SHAPES = ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
           (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1), (256, 8, 2, 2), (256, 8, 4, 2),
-          (512, 8, 2, 2))
+          (512, 8, 2, 2), (256, 16, 1, 2), (512, 16, 1, 2))
 
 
 def _variants(R):
@@ -198,13 +198,14 @@ def test_exponent_specialised_chain_serial(R):
     # Launches whose instances all have e = 3 take the chain-serial kernels
     # specialised to that exponent (skips kept for the output pass); ragged
     # ranges put partial chunks and partial steps at both ends of each chain.
-    # A pool that mixes e = 3 and e = 5 takes the general kernels.
+    # A pool that mixes e = 3 and e = 5 takes the per-chain exponent paths (16
+    # indices per lane: two chunks of 8, the same tile).
     insts3 = inputs.config2(6)
     ranges = [(0, 0, B), (1, 17, 5000), (2, B - 777, 4096 + 1000), (3, 3 * B + 8191, 8193),
               (4, 12345, 2 * 8192 + 64 * 8 + 3), (5, (1 << 40) + 5, 70001)]
     # the exponent-sweep instances are valid for e = 5
     mixed = insts3[:3] + [inputs.Instance(i.p, i.q, 5, i.m0) for i in inputs.config3(3)]
-    for shape in ((256, 8, 2), (512, 8, 2)):
+    for shape in ((256, 8, 2), (512, 8, 2), (256, 16, 1), (512, 16, 1)):
         for pers in (0, 1):
             cfg = R.config(variant=R.VARIANT_CRT, lanes_per_tile=shape[0], per_lane=shape[1],
                            chunks_per_wave=shape[2], persistent=pers, order=pers, prefix=2)
