@@ -242,8 +242,10 @@ typedef struct {
                            one 2^20 block) in order, carrying the message prefix */
   int chunks_per_wave;  /* two passes and chain-serial: 64*per_lane chunks per wave per tile
                            (1 for chain-serial with per_lane 16, which runs as such for
-                           CRT generate launches whose instances all have e = 3; other
-                           launches take two chunks of 8 indices per lane, the same tile) */
+                           CRT launches whose instances all share one exponent: e = 3 in
+                           generate mode, 3, 5, 7, 17, 257 or 65537 in consume mode with
+                           256 lanes; other launches take two chunks of 8 indices per
+                           lane, the same tile) */
 } rsaprng_config;
 
 /* One-shot batched launches over a pool (reqs is a host array). */

@@ -555,6 +555,18 @@ static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c
 // Enqueue one launch: chain setup, then either [sums, scan, generate] (two
 // passes) or [queue reset, single-pass generate]; consume mode adds the zero
 // and finalize kernels around it.  `inst` and `chains` are device pointers.
+// The chain-serial kernels with 16 indices per lane: CRT launches whose
+// instances all have one exponent, e = 3 in generate mode (256 or 512 lanes),
+// any of the unrolled ladders in consume mode (256 lanes).
+bool serial16_built(int variant, int mode, uint32_t shared_e, int lanes) {
+  if (variant != kVariantCrt) return false;
+  if (mode == kModeGenerate) return shared_e == 3 && (lanes == 256 || lanes == 512);
+  if (mode == kModeConsume)
+    return lanes == 256 && (shared_e == 3 || shared_e == 5 || shared_e == 7 || shared_e == 17 ||
+                            shared_e == 257 || shared_e == 65537);
+  return false;
+}
+
 uint32_t shared_exponent(const PlanIn* in, size_t n) {
   if (n == 0) return 0;
   for (size_t i = 1; i < n; ++i)
@@ -630,10 +642,11 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
   shape.prefix = c.prefix;
   shape.r = c.chunks_per_wave;
   if (c.prefix == kPrefixSerial && c.per_lane == 16 &&
-      !(c.variant == kVariantCrt && mode == kModeGenerate && shared_e == 3)) {
-    // 16 indices per lane are built for CRT generate launches of e = 3 only
-    // (elsewhere their registers would spill); other launches take two chunks
-    // of 8, the same tile (the plan and the prefix passes do not change)
+      !serial16_built(c.variant, mode, shared_e, c.lanes_per_tile)) {
+    // 16 indices per lane are built for the kernels specialised to one
+    // exponent (elsewhere their registers would spill); other launches take
+    // two chunks of 8, the same tile (the plan and the prefix passes do not
+    // change)
     shape.v = 8;
     shape.r = 2;
   }

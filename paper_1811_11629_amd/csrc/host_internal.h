@@ -99,6 +99,7 @@ int split_leadin(std::vector<Chain>& chains, const rsaprng_config& c, int mode, 
 // The exponent shared by every request (0 if they differ; dual-exponent
 // instances have e = 0): lets a launch take kernels specialised to it.
 uint32_t shared_exponent(const PlanIn* in, size_t n);
+bool serial16_built(int variant, int mode, uint32_t shared_e, int lanes);
 // Parameter generation kernels (k_primes.hip).
 int launch_count_primes(uint64_t lo, uint64_t hi, int safe, unsigned long long* count_dev,
                         void* stream);

@@ -1483,6 +1483,19 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
     if (s.prefix == kPrefixSerial) {
       if constexpr (MODE == kModeConsume && VAR == kVariantCrt) {
         if (s.wg == 256 && s.v == 8 && s.r == 2) return launch3<256, 8, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);
+        // launches of one exponent with 16 indices per lane: kernels specialised
+        // to it (the per-chain dispatch at that shape would spill)
+        if (s.wg == 256 && s.v == 16 && s.r == 1) {
+          switch (s.e) {
+            case 3: return launch3<256, 16, 1, VAR, MODE, 3>(a, s.grid, stream, occ);
+            case 5: return launch3<256, 16, 1, VAR, MODE, 5>(a, s.grid, stream, occ);
+            case 7: return launch3<256, 16, 1, VAR, MODE, 7>(a, s.grid, stream, occ);
+            case 17: return launch3<256, 16, 1, VAR, MODE, 17>(a, s.grid, stream, occ);
+            case 257: return launch3<256, 16, 1, VAR, MODE, 257>(a, s.grid, stream, occ);
+            case 65537: return launch3<256, 16, 1, VAR, MODE, 65537>(a, s.grid, stream, occ);
+            default: return RSAPRNG_E_ARG;
+          }
+        }
       }
       if constexpr (MODE == kModeGenerate && VAR == kVariantCrt) {
         // every instance of the launch has e = 3: the kernels specialised to

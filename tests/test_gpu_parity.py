@@ -295,6 +295,37 @@ def test_consume_matches_oracle(R):
             assert g["sum"] == float(Fraction(ref["sum_fx"], 1 << 128))
 
 
+def test_consume_one_exponent_sixteen_per_lane(R):
+    # Consume launches whose instances share one exponent take chain-serial
+    # kernels specialised to it with 16 indices per lane: each unrolled
+    # exponent, ragged ranges (lead-in, block crossing, partial chunks at both
+    # ends), persistent and not, record by record against the oracle.
+    base = inputs.config3(4)
+    sevens = [i for i in inputs.config4(200)[0] if i.e == 7][:4]
+    pools = [(e, [inputs.Instance(b.p, b.q, e, b.m0) for b in base])
+             for e in (3, 5, 17, 257, 65537)] + [(7, sevens)]
+    for e, insts in pools:
+        ranges = [(j, k0, cnt) for j in range(len(insts))
+                  for k0, cnt in ((0, 1 << 16), (B - 2500, 7000), ((1 << 40) + 3 * j + 1, 5000 + 17 * j))]
+        refs = [oracle_stats(insts[j], k0, cnt) for j, k0, cnt in ranges]
+        pool = R.Pool.from_instances(insts)
+        for pers in (0, 1):
+            log("consume one exponent, 16 per lane", e, pers)
+            st = R.stats_tensor(len(ranges))
+            cfg = R.config(variant=R.VARIANT_CRT, lanes_per_tile=256, per_lane=16, chunks_per_wave=1,
+                           prefix=2, persistent=pers, order=pers)
+            R.rsaprng_pool_consume(pool, [(j, k0, cnt, idx) for idx, (j, k0, cnt) in enumerate(ranges)],
+                                   st, cfg=cfg)
+            R.rsaprng_check_device_error()
+            got = R.stats_decode(st)
+            for idx, ref in enumerate(refs):
+                g = got[idx]
+                assert g["count"] == ranges[idx][2], (e, pers, idx)
+                assert g["sum_fx"] == ref["sum_fx"], (e, pers, idx)
+                assert g["lt_half"] == ref["lt_half"], (e, pers, idx)
+                assert np.array_equal(g["hist"], ref["hist"]), (e, pers, idx)
+
+
 def test_consume_persistent_many_chains(R):
     # one work-group per compute unit walks tiles of many chains in turn: each
     # tile's statistics must land in its own record, in every shape and variant
