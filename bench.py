@@ -180,20 +180,33 @@ def time_graph(batch, stream, steps, warmup, torch):
 
 
 def tile_kernel_name(cfg, exponent=0, mode="generate") -> str:
-    """The tile kernel of a configuration, as rocprofv3 lists it.  A generate
-    launch whose instances all have e = 3 takes the chain-serial CRT kernels
-    specialised to it (two chunks of 8 or one of 16 indices per lane), whose
-    name carries the exponent; other chain-serial launches with 16 indices per
-    lane take two chunks of 8."""
+    """The tile kernel of a configuration, as rocprofv3 lists it, following the
+    launcher's choice for chain-serial CRT launches: the kernels specialised to
+    the launch's one exponent (generate: e = 3 with two chunks of 8 or one of
+    16 indices per lane; consume: 256 lanes, one chunk of 16, any unrolled
+    exponent), else the per-chain exponent dispatch ((256 or 512, 8, 2) in
+    generate mode, (256, 8, 2) in consume mode), with 16 indices per lane
+    taken as two chunks of 8 where no kernel of 16 is built."""
     form = {0: "k_gen2", 1: "k_gen1", 2: "k_gen3"}[cfg.prefix]
-    spec = (mode == "generate" and exponent == 3 and cfg.prefix == 2 and cfg.variant == 2)
-    per, chunks = cfg.per_lane, cfg.chunks_per_wave
-    if cfg.prefix == 2 and per == 16 and not spec:
+    per, chunks, lanes = cfg.per_lane, cfg.chunks_per_wave, cfg.lanes_per_tile
+    ek = ""
+    if cfg.prefix == 2 and cfg.variant == 2 and mode in ("generate", "consume"):
+        if mode == "generate":
+            one = exponent == 3 and (per, chunks) in ((8, 2), (16, 1))
+        else:
+            one = per == 16 and lanes == 256 and exponent in (3, 5, 7, 17, 257, 65537)
+        if one:
+            ek = ", %d" % exponent
+        else:
+            if per == 16:
+                per, chunks = 8, 2
+            if (per, chunks) == (8, 2) and (mode == "generate" or lanes == 256):
+                ek = ", -1"
+    elif cfg.prefix == 2 and per == 16:
         per, chunks = 8, 2
     r = "" if cfg.prefix == 1 else ", %d" % chunks
-    ek = ", 3" if spec and (per, chunks) in ((8, 2), (16, 1)) else ""
     return "%s<%d, %d%s, %d, %d%s> (%s, %s)" % (
-        form, cfg.lanes_per_tile, per, r, cfg.variant, 0 if mode == "generate" else 1,
+        form, lanes, per, r, cfg.variant, {"generate": 0, "consume": 1}.get(mode, 2),
         ek, "CRT binary64 residues" if cfg.variant == 2 else "Montgomery-64", mode)
 
 
@@ -396,7 +409,7 @@ def run_consume_sweep(R, torch, stream, steps, exponents=None, cfg=None):
         out["e%d" % e] = {"gnumbers_per_s": n / (ms / 1e3) / 1e9, "ms_per_launch": ms,
                           "variant": int(best.variant), "config": best.as_dict(),
                           "roofline": roofline_of({e: n}, ms / 1e3, True,
-                                                  tile_kernel_name(best, mode="consume"),
+                                                  tile_kernel_name(best, exponent=e, mode="consume"),
                                                   "one graph replay (statistics zeroing, chain "
                                                   "setup, prefix pass, tile kernel, finalisation)")}
         log("consume e=%d: %.1f Gnum/s (%.3f ms)" % (e, out["e%d" % e]["gnumbers_per_s"], ms))
