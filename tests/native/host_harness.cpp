@@ -16,6 +16,7 @@
 // own violations exit with status 3).
 #include <hip/hip_runtime.h>
 
+#include <array>
 #include <cinttypes>
 #include <cmath>
 #include <cstdio>
@@ -76,6 +77,8 @@ int enq(void* stream, const char* what, std::function<void()> f) {
 // the kernel launchers
 // ---------------------------------------------------------------------------
 namespace rsaprng {
+
+bool serial16_built(int variant, int mode, uint32_t shared_e, int lanes);  // host.cpp
 
 int launch_begin(DevCtl* ctl, void* stream) {
   return enq(stream, "k_begin", [=] {
@@ -172,6 +175,13 @@ int launch_tiles(const KernelShape& s, const LaunchArgs& a, void* stream) {
     const uint64_t ch = 1ull << (a.tile_log2 - a.chunk_log2);
     CHECK(T == (uint64_t)s.wg * s.v * (s.prefix == kPrefixLookback ? 1 : s.r),
           "tile size %" PRIu64 " does not match the kernel shape", T);
+    // chain-serial kernels with 16 indices per lane exist only specialised to
+    // one exponent; the lane-offset table must be the one for 16
+    if (s.prefix == kPrefixSerial && s.v == 16)
+      CHECK(s.r == 1 && serial16_built(s.variant, s.mode, s.e, s.wg),
+            "no chain-serial kernel (%d, 16, %d) for variant %d mode %d e = %u", s.wg, s.r,
+            s.variant, s.mode, s.e);
+    if (s.prefix == kPrefixSerial) CHECK(s.v == 8 || s.v == 16, "indices per lane %d", s.v);
     if (s.prefix == kPrefixLookback) {
       (void)rd(a.ctl, "look-back ctl");
       fakehip::need_device(a.lb, (size_t)a.ntiles * 32, "look-back words");
@@ -433,21 +443,23 @@ struct Outputs {
   }
 };
 
-rsaprng_config cfg_of(int variant, int prefix, int lanes, int r, int persistent) {
+rsaprng_config cfg_of(int variant, int prefix, int lanes, int r, int persistent, int per = 8) {
   rsaprng_config c;
   std::memset(&c, 0, sizeof(c));
   c.variant = variant;
   c.prefix = prefix;
   c.lanes_per_tile = lanes;
-  c.per_lane = 8;
+  c.per_lane = per;
   c.chunks_per_wave = r;
   c.persistent = persistent;
   c.order = persistent;
   return c;
 }
 
-const int kShapes[][3] = {{0, 256, 1}, {0, 256, 2}, {0, 256, 4}, {0, 512, 2}, {1, 256, 1},
-                          {1, 512, 1}, {2, 256, 2}, {2, 256, 4}, {2, 512, 2}};
+// (prefix, lanes, chunks per wave, indices per lane)
+const int kShapes[][4] = {{0, 256, 1, 8}, {0, 256, 2, 8}, {0, 256, 4, 8}, {0, 512, 2, 8},
+                          {1, 256, 1, 8}, {1, 512, 1, 8}, {1, 256, 1, 16}, {2, 256, 2, 8},
+                          {2, 256, 4, 8}, {2, 512, 2, 8}, {2, 256, 1, 16}, {2, 512, 1, 16}};
 
 hipStream_t new_stream() {
   hipStream_t s;
@@ -476,7 +488,7 @@ int main(int argc, char** argv) {
       for (const auto& sh : kShapes)
         for (int pers : {0, 1}) {
           o.clear();
-          rsaprng_config c = cfg_of(var, sh[0], sh[1], sh[2], pers);
+          rsaprng_config c = cfg_of(var, sh[0], sh[1], sh[2], pers, sh[3]);
           CHECK(rsaprng_pool_generate(pool, pr.data(), pr.size(), o.c, o.r, &c, st) == RSAPRNG_OK,
                 "pool_generate");
           o.verify(v, "pool_generate");
@@ -486,10 +498,15 @@ int main(int argc, char** argv) {
     auto v3 = uneven(60, 40, 4, 14, &total);
     auto pr3 = pool_reqs(v3);
     Outputs o3(total);
-    rsaprng_config c = cfg_of(2, 2, 512, 2, 0);
-    CHECK(rsaprng_pool_generate(pool3, pr3.data(), pr3.size(), o3.c, o3.r, &c, st) == RSAPRNG_OK,
-          "pool_generate e = 3");
-    o3.verify(v3, "pool_generate e = 3");
+    for (const auto& sh : {std::array<int, 3>{512, 2, 8}, std::array<int, 3>{256, 1, 16},
+                           std::array<int, 3>{512, 1, 16}}) {
+      o3.clear();
+      rsaprng_config c = cfg_of(2, 2, sh[0], sh[1], 0, sh[2]);
+      CHECK(rsaprng_pool_generate(pool3, pr3.data(), pr3.size(), o3.c, o3.r, &c, st) ==
+                RSAPRNG_OK,
+            "pool_generate e = 3");
+      o3.verify(v3, "pool_generate e = 3");
+    }
     CHECK(rsaprng_check_device_error(st) == RSAPRNG_OK, "device error");
   }
 
@@ -503,7 +520,7 @@ int main(int argc, char** argv) {
     for (const auto& sh : kShapes) {
       o1.clear();
       o2.clear();
-      rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], 0);
+      rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], 0, sh[3]);
       CHECK(rsaprng_pool_generate_noalloc(pool, p1.data(), p1.size(), o1.c, o1.r, &c, st) ==
                 RSAPRNG_OK,
             "noalloc call 1");
@@ -528,10 +545,12 @@ int main(int argc, char** argv) {
     CHECK(rsaprng_pool_generate_noalloc(pool, many.data(), many.size(), small.c, small.r, nullptr,
                                         st) == RSAPRNG_E_TOO_LARGE,
           "too many chains");
-    for (uint64_t cnt : {1ull << 30, 1ull << 31}) {
+    // beyond the scratch for every shape (16 indices per lane halve the chunk
+    // records: about 1.7e9 outputs fit them)
+    for (uint64_t cnt : {1ull << 31, 1ull << 32}) {
       rsaprng_pool_req big{0, 0, 0, cnt, 0};
       for (const auto& sh : kShapes) {
-        rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], 0);
+        rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], 0, sh[3]);
         CHECK(rsaprng_pool_generate_noalloc(pool, &big, 1, small.c, small.r, &c, st) ==
                   RSAPRNG_E_TOO_LARGE,
               "tile arrays beyond the scratch (count %" PRIu64 ")", cnt);
@@ -573,7 +592,7 @@ int main(int argc, char** argv) {
               h[i].count, v[i].count);
     };
     for (const auto& sh : kShapes) {
-      rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], 1);
+      rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], 1, sh[3]);
       CHECK(rsaprng_pool_consume(pool, pr.data(), pr.size(), stats, &c, st) == RSAPRNG_OK,
             "pool_consume");
       check_stats("pool_consume");
@@ -599,7 +618,7 @@ int main(int argc, char** argv) {
                  e0 = fakehip::live_events();
     for (const auto& sh : kShapes)
       for (int pers : {0, 1}) {
-        rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], pers);
+        rsaprng_config c = cfg_of(2, sh[0], sh[1], sh[2], pers, sh[3]);
         rsaprng_batch_t b;
         CHECK(rsaprng_batch_create(pool, pr.data(), pr.size(), 0, o.c, o.r, nullptr, &c, st, &b) ==
                   RSAPRNG_OK,
@@ -758,6 +777,10 @@ int main(int argc, char** argv) {
     auto pb = pool_reqs(vb);
     CHECK(rsaprng_pool_battery(pool, pb.data(), pb.size(), bat, nullptr, st) == RSAPRNG_OK,
           "pool_battery");
+    // 16 indices per lane asked of the battery: it runs on lanes of 8
+    const rsaprng_config c16 = cfg_of(2, 2, 256, 1, 1, 16);
+    CHECK(rsaprng_pool_battery(pool, pb.data(), pb.size(), bat, &c16, st) == RSAPRNG_OK,
+          "pool_battery, 16 per lane asked");
     CHECK(rsaprng_battery_values(o.r, 100000, bat, st) == RSAPRNG_OK, "battery_values");
     CHECK(rsaprng_check_device_error(st) == RSAPRNG_OK, "device error");
     fakehip::drain();
