@@ -186,7 +186,9 @@ def tile_kernel_name(cfg, exponent=0, mode="generate") -> str:
     16 indices per lane; consume: 256 lanes, one chunk of 16, any unrolled
     exponent), else the per-chain exponent dispatch ((256 or 512, 8, 2) in
     generate mode, (256, 8, 2) in consume mode), with 16 indices per lane
-    taken as two chunks of 8 where no kernel of 16 is built."""
+    taken as two chunks of 8 where no kernel of 16 is built.  Two passes with
+    16 indices per lane (CRT generate) launch one kernel per exponent class,
+    named here with `e` when the launch holds several."""
     form = {0: "k_gen2", 1: "k_gen1", 2: "k_gen3"}[cfg.prefix]
     per, chunks, lanes = cfg.per_lane, cfg.chunks_per_wave, cfg.lanes_per_tile
     ek = ""
@@ -204,6 +206,12 @@ def tile_kernel_name(cfg, exponent=0, mode="generate") -> str:
                 ek = ", -1"
     elif cfg.prefix == 2 and per == 16:
         per, chunks = 8, 2
+    elif cfg.prefix == 0 and per == 16:
+        if cfg.variant == 2 and mode == "generate":
+            # one launch per exponent class, each specialised to its exponent
+            ek = ", %d" % exponent if exponent in (3, 5, 7, 17, 257, 65537) else ", e"
+        else:
+            per, chunks = 8, 4
     r = "" if cfg.prefix == 1 else ", %d" % chunks
     return "%s<%d, %d%s, %d, %d%s> (%s, %s)" % (
         form, lanes, per, r, cfg.variant, {"generate": 0, "consume": 1}.get(mode, 2),
@@ -588,7 +596,7 @@ def verify_served(srv, insts, inst, k0, cnt, threads=None):
 
 
 def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=26, chunk_log2=24,
-               verify=True, policy="sf", compare=True):
+               verify=True, policy="sf", compare=True, cfg=None):
     """Served workload: 100,000 device-resident instances, requests (instance
     uniform, k0 < 2^40, length log-uniform in [2^10, 2^24)) arriving as a Poisson
     stream; continuous batching with a 64 GiB output arena, iterations of
@@ -597,7 +605,8 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=26, c
     ("rr").  Offered load is a fraction rho of the server's own saturated
     capacity (every request of a trace submitted at once).  With compare, a
     round-robin server with iterations of 2^27 outputs runs the saturated trace
-    and the highest load of the sweep beside it."""
+    and the highest load of the sweep beside it.  cfg: the kernel configuration
+    (else the served autotuner's choice)."""
     import numpy as np
 
     import inputs
@@ -614,7 +623,10 @@ def run_served(R, torch, stream, rho_main=0.7, sweep=(0.5, 0.9), iter_log2=26, c
                 np.array([r.count for r in reqs], dtype=np.uint64))
 
     chunk = 1 << chunk_log2
-    cfg, tune_ms = tune_served(R, torch, stream, pool, *trace(64), chunk)
+    if cfg is None:
+        cfg, tune_ms = tune_served(R, torch, stream, pool, *trace(64), chunk)
+    else:
+        tune_ms = None
     pol = {"rr": R.SRV_ROUND_ROBIN, "sf": R.SRV_SHORTEST_FIRST}[policy]
     log("served config", cfg.as_dict(), "iteration 2^%d outputs, chunk 2^%d, %s" % (
         iter_log2, chunk_log2, {"rr": "round robin", "sf": "shortest first"}[policy]))
@@ -954,7 +966,8 @@ def main():
     ap.add_argument("--served-only", default="", metavar="ITER,CHUNK[,POLICY]",
                     help="only the served workload, with iterations of 2^ITER outputs, "
                          "per-request chunks of 2^CHUNK and POLICY sf (shortest first, the "
-                         "default) or rr (round robin) (no comparison with the oracle)")
+                         "default) or rr (round robin) (no comparison with the oracle; with "
+                         "--config: that configuration, no autotuning)")
     ap.add_argument("--batched-only", action="store_true",
                     help="only the batched uneven workload, without the plain per-request "
                          "launches (with --config: that configuration, no autotuning)")
@@ -1007,7 +1020,7 @@ def main():
         parts = args.served_only.split(",")
         it, ch = int(parts[0]), int(parts[1])
         res = run_served(R, torch, stream, iter_log2=it, chunk_log2=ch, verify=False,
-                         policy=parts[2] if len(parts) > 2 else "sf", compare=False)
+                         policy=parts[2] if len(parts) > 2 else "sf", compare=False, cfg=fixed)
         print(json.dumps(res))
         return
     if args.consume_only:

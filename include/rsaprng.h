@@ -232,7 +232,10 @@ typedef struct {
 typedef struct {
   int variant;          /* 0 auto, 1 Montgomery-64 integer path, 2 CRT with binary64 residues */
   int lanes_per_tile;   /* work-group size: 0 default, else 256 or 512 */
-  int per_lane;         /* consecutive indices per lane: 0 default, else 8 or 16 */
+  int per_lane;         /* consecutive indices per lane: 0 default, else 8 or 16 (two
+                           passes: 16 with 256 lanes and 2 chunks per wave for CRT
+                           generate launches, one tile launch per exponent class;
+                           other launches take 4 chunks of 8, the same tile) */
   int persistent;       /* 1: grid of resident work-groups looping over the tiles */
   int wg_per_cu;        /* persistent grid size per compute unit (0 = default) */
   int order;            /* 0 request order, 1 longest-first by exponent cost */

@@ -68,9 +68,18 @@ enum ChainFlags : uint32_t {
 // prefix kernels over `nlead` lead-in chains (stored after the `nout` output
 // chains, with tiles [0, lead_tiles)), which then hand each output chain its
 // start at its first tile with outputs.  nlead = 0: no lead-in pass.
+//
+// A two-pass CRT generate launch with 16 indices per lane has its chains
+// ordered by exponent class: class j holds the tiles [class_end[j-1],
+// class_end[j]) (from 0) and exponent class_e[j] (0: any exponent outside the
+// unrolled ladders, dual-exponent instances included), and takes the tile
+// kernel specialised to it.  nclass = 0: one tile launch.
 struct LeadIn {
   uint32_t nout = 0, nlead = 0;
   uint64_t lead_tiles = 0;
+  uint32_t nclass = 0;
+  uint32_t class_e[7] = {};
+  uint64_t class_end[7] = {};
 };
 
 // Computed on the device per chain: the skip at S and the message before S,
@@ -108,6 +117,7 @@ struct LaunchArgs {
   uint32_t excl_res;       // two passes, CRT: k_scan leaves the residues of each
                            // chunk's message, mod p in agg and mod q in excl
                            // (binary64 bits), instead of the message in excl
+  uint32_t tile0;          // two-pass tile kernel: its tiles are [tile0, ntiles)
   uint32_t* tile_chain;    // per tile: owning chain (k_chain_setup)
   ChainStart* cstart;      // per chain (k_chain_setup)
   uint64_t* s_tile;        // per tile: skip at the tile start (k_sums)

@@ -445,16 +445,30 @@ rsaprng_config resolve_config(const rsaprng_config* cfg) {
     }
   } else if (c.prefix == kPrefixTwoPass) {
     // shapes built for two passes: (256, 8, r) for r = 1, 2, 4 and (512, 8, 2)
-    c.per_lane = 8;
+    // and (256, 16, 2) for CRT generate launches (fit_mode)
     if (c.lanes_per_tile != 512) c.lanes_per_tile = 256;
-    if (c.lanes_per_tile == 512) c.chunks_per_wave = 2;
-    else if (c.chunks_per_wave != 1 && c.chunks_per_wave != 4) c.chunks_per_wave = 2;
+    if (c.per_lane == 16 && c.lanes_per_tile == 256) {
+      c.chunks_per_wave = 2;
+    } else {
+      c.per_lane = 8;
+      if (c.lanes_per_tile == 512) c.chunks_per_wave = 2;
+      else if (c.chunks_per_wave != 1 && c.chunks_per_wave != 4) c.chunks_per_wave = 2;
+    }
   } else {
     // one pass: (256, 8), (512, 8), (256, 16)
     c.chunks_per_wave = 1;
     if (c.lanes_per_tile != 256 && c.lanes_per_tile != 512) c.lanes_per_tile = 256;
     if (c.per_lane != 8 && c.per_lane != 16) c.per_lane = 8;
     if (c.lanes_per_tile == 512) c.per_lane = 8;
+  }
+  return c;
+}
+
+rsaprng_config fit_mode(rsaprng_config c, int mode) {
+  if (c.prefix == kPrefixTwoPass && c.per_lane == 16 &&
+      !(c.variant == kVariantCrt && mode == kModeGenerate)) {
+    c.per_lane = 8;
+    c.chunks_per_wave = 4;
   }
   return c;
 }
@@ -540,6 +554,39 @@ int split_leadin(std::vector<Chain>& chains, const rsaprng_config& c, int mode, 
   const int rc = plan_split_leadin(chains.data(), n, 2 * n, tile_size(c), li);
   chains.resize(n + li->nlead);
   return rc;
+}
+
+// The unrolled ladders, in the order of the exponent classes.
+static const uint32_t kClassE[6] = {3, 5, 7, 17, 257, 65537};
+
+void group_by_exponent(std::vector<Chain>& chains, const rsaprng_config& c, int mode,
+                       const rsaprng_params* inst, LeadIn* li) {
+  li->nclass = 0;
+  if (!(c.prefix == kPrefixTwoPass && c.variant == kVariantCrt && mode == kModeGenerate &&
+        c.per_lane == 16) ||
+      chains.empty())
+    return;
+  auto cls = [&](const Chain& ch) {
+    const uint32_t e = inst[ch.inst].e;
+    for (int j = 0; j < 6; ++j)
+      if (e == kClassE[j]) return j;
+    return 6;
+  };
+  // chains are independent in the two-pass form: any order gives the same
+  // outputs; the tiles are renumbered in the new order
+  std::stable_sort(chains.begin(), chains.end(),
+                   [&](const Chain& x, const Chain& y) { return cls(x) < cls(y); });
+  u64h t = 0;
+  for (size_t i = 0; i < chains.size(); ++i) {
+    const int j = cls(chains[i]);
+    chains[i].first = (uint32_t)t;
+    t += chains[i].ntiles;
+    if (li->nclass == 0 || li->class_e[li->nclass - 1] != (j < 6 ? kClassE[j] : 0u)) {
+      li->class_e[li->nclass] = j < 6 ? kClassE[j] : 0u;
+      ++li->nclass;
+    }
+    li->class_end[li->nclass - 1] = t;
+  }
 }
 
 static int grid_for(Device* d, const KernelShape& shape, const rsaprng_config& c, u64h ntiles) {
@@ -709,7 +756,26 @@ int enqueue_launch_in(Device* d, const ScratchView& sc, const rsaprng_config& c,
     if ((rc = launch_begin(sc.ctl, stream))) return rc;
   }
   if ((rc = mark(2))) return rc;
-  if ((rc = launch_tiles(shape, a, stream)) || (rc = mark(3))) return rc;
+  if (li && li->nclass && c.prefix == kPrefixTwoPass && shape.v == 16) {
+    // one tile launch per exponent class, each over the class's tiles
+    u64h t0 = 0;
+    for (uint32_t j = 0; j < li->nclass; ++j) {
+      const u64h t1 = li->class_end[j];
+      if (t1 <= t0 || t1 > ntiles) return RSAPRNG_E_ARG;
+      KernelShape sj = shape;
+      sj.e = li->class_e[j];
+      sj.grid = grid_for(d, sj, c, t1 - t0);
+      LaunchArgs aj = a;
+      aj.tile0 = (uint32_t)t0;
+      aj.ntiles = (uint32_t)t1;
+      if ((rc = launch_tiles(sj, aj, stream))) return rc;
+      t0 = t1;
+    }
+    if (t0 != ntiles) return RSAPRNG_E_ARG;
+  } else if ((rc = launch_tiles(shape, a, stream))) {
+    return rc;
+  }
+  if ((rc = mark(3))) return rc;
   if (mode == kModeConsume && (rc = launch_stats_finalize(stats, nstats, stream))) return rc;
   return mark(4);
 }
@@ -1102,13 +1168,13 @@ const rsaprng_params* pool_dev(rsaprng_pool_t pool) { return pool->dev; }
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i) { return pool->host[i]; }
 int pool_device(rsaprng_pool_t pool) { return pool->device; }
 
-rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg) {
+rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg, int mode) {
   rsaprng_config c = resolve_config(cfg);
   if (pool->dual && c.variant != kVariantCrt) {
     c.variant = kVariantCrt;
     c = resolve_config(&c);
   }
-  return c;
+  return fit_mode(c, mode);
 }
 
 int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, int mode,
@@ -1124,8 +1190,10 @@ int pool_plan(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, in
     if (mode == kModeConsume && reqs[i].out_off > 0xffffffffull) return RSAPRNG_E_ARG;
   }
   if (shared_e) *shared_e = shared_exponent(in.data(), nreq);
-  const int rc = plan_chains(in.data(), nreq, c, mode, plan, ntiles);
-  return rc ? rc : split_leadin(plan, c, mode, li);
+  int rc = plan_chains(in.data(), nreq, c, mode, plan, ntiles);
+  if (!rc) rc = split_leadin(plan, c, mode, li);
+  if (!rc) group_by_exponent(plan, c, mode, pool->host.data(), li);
+  return rc;
 }
 
 static size_t stats_records(const rsaprng_pool_req* reqs, size_t nreq) {
@@ -1164,6 +1232,7 @@ int pool_launch(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size_t nreq, 
     c2.per_lane = 8;
     c = resolve_config(&c2);
   }
+  c = fit_mode(c, mode);
   std::vector<Chain> plan;
   u64h ntiles;
   uint32_t se = 0;
@@ -1446,7 +1515,7 @@ int rsaprng_batch_create(rsaprng_pool_t pool, const rsaprng_pool_req* reqs, size
   Device* d;
   int rc;
   if ((rc = device_get(&d))) return rc;
-  rsaprng_config c = config_for_pool(pool, cfg);
+  rsaprng_config c = config_for_pool(pool, cfg, mode);
   std::vector<Chain> plan;
   u64h ntiles;
   uint32_t se = 0;
@@ -1607,7 +1676,8 @@ std::vector<rsaprng_config> tune_space() {
                                   {kPrefixLookback, 256, 8, 1}, {kPrefixLookback, 512, 8, 1},
                                   {kPrefixLookback, 256, 16, 1}, {kPrefixSerial, 256, 8, 2},
                                   {kPrefixSerial, 256, 8, 4}, {kPrefixSerial, 512, 8, 2},
-                                  {kPrefixSerial, 256, 16, 1}, {kPrefixSerial, 512, 16, 1}};
+                                  {kPrefixSerial, 256, 16, 1}, {kPrefixSerial, 512, 16, 1},
+                                  {kPrefixTwoPass, 256, 16, 2}};
   std::vector<rsaprng_config> out;
   for (int var : {kVariantCrt, kVariantMont})
     for (const auto& s : shapes)

@@ -110,6 +110,16 @@ const rsaprng_params* pool_dev(rsaprng_pool_t pool);
 const rsaprng_params& pool_host(rsaprng_pool_t pool, size_t i);
 int pool_device(rsaprng_pool_t pool);
 // The configuration a launch over `pool` uses (CRT for dual-exponent pools).
-rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg);
+rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg, int mode);
+// Two passes with 16 indices per lane are built for CRT generate launches only;
+// other launches of that configuration take four chunks of 8 per wave (the
+// same tile).
+rsaprng_config fit_mode(rsaprng_config c, int mode);
+// Two-pass CRT generate launches with 16 indices per lane: the planned chains
+// ordered by exponent class (stable), their tiles renumbered in that order,
+// and the class boundaries in li (inst: the pool's host records); other
+// launches are left as planned (li->nclass = 0).
+void group_by_exponent(std::vector<Chain>& chains, const rsaprng_config& c, int mode,
+                       const rsaprng_params* inst, LeadIn* li);
 
 }  // namespace rsaprng

@@ -89,10 +89,10 @@ extern "C" int rsaprng_pool_generate_noalloc(rsaprng_pool_t pool, const rsaprng_
   // the pool's creation set this device up, so this only looks it up
   if ((rc = device_get(&d))) return rc;
   // two passes or chain-serial (the one-pass form needs look-back words)
-  rsaprng_config c = config_for_pool(pool, cfg);
+  rsaprng_config c = config_for_pool(pool, cfg, kModeGenerate);
   if (c.prefix == kPrefixLookback) {
     c.prefix = kPrefixTwoPass;
-    c = config_for_pool(pool, &c);
+    c = config_for_pool(pool, &c, kModeGenerate);
   }
   const u64h T = tile_size(c);
   const u64h chunks_per_tile = T / (64ull * c.per_lane);

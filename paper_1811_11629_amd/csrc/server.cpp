@@ -103,7 +103,7 @@ rsaprng_server_s::~rsaprng_server_s() {
 
 int rsaprng_server_s::init() {
   t0 = Clock::now();
-  cfg = config_for_pool(pool, &opts.cfg);
+  cfg = config_for_pool(pool, &opts.cfg, kModeGenerate);
   if (!opts.iter_outputs) opts.iter_outputs = 1ull << 26;
   if (!opts.chunk_outputs) opts.chunk_outputs = 1ull << 22;
   if (!opts.max_queue) opts.max_queue = 1u << 20;
@@ -133,6 +133,7 @@ int rsaprng_server_s::launch_next() {
   int rc = plan_chains(plan.data(), plan.size(), cfg, kModeGenerate, chains, &ntiles);
   LeadIn li;
   if (!rc) rc = split_leadin(chains, cfg, kModeGenerate, &li);
+  if (!rc && !chains.empty()) group_by_exponent(chains, cfg, kModeGenerate, &pool_host(pool, 0), &li);
   void* dch = nullptr;
   int slot = 0;
   if (!rc) rc = sc.upload(chains.data(), chains.size() * sizeof(Chain), stream, &dch, &slot);

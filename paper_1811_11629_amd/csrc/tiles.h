@@ -1053,17 +1053,86 @@ __device__ __forceinline__ void chain_end(const LaunchArgs& a, const Chain& C, u
   }
 }
 
+// Exponent dispatch of the tile kernels: EK > 0, the kernel's paths are
+// specialised to that exponent; EK = kEKPerChain, each chain (or tile) takes
+// the path specialised to its own exponent (the common ones; any other, and
+// dual-exponent instances, take the general path, EK = 0).
+constexpr int kEKPerChain = -1;
+
 // Two passes: each wave owns R consecutive chunks of 64 V indices of the tile
 // (T = WG V R) and processes them one after the other; the message before a
 // chunk comes from k_scan (for CRT as its two residues) and its start skip
 // from the tile's skip, a^(64 V q) for the chunk (wave-uniform) and a^(V lane),
-// so waves never wait on each other.
-template <int WG, int V, int R, int VAR, int MODE>
-__global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
+// so waves never wait on each other.  EK as for k_gen3: with EK != 0 the
+// fast path takes any 8-byte-aligned output (AL = -1).
+template <int WG, int V, int R, int VAR, int MODE, int EK>
+__device__ __forceinline__ void tile2(const LaunchArgs& a, TileShared<WG, MODE>& sh, u32 t,
+                                      u64 pl, int lane, u32 wave) {
   constexpr int NW = WG / 64;
   constexpr int CH = NW * R;  // chunks per tile
   constexpr u64 T = (u64)WG * V * R;
   constexpr u64 CHUNK = 64ull * V;
+  const u32 c = cst(a.tile_chain)[t];
+  const Chain C = load_cst(a.chain + c);
+  const rsaprng_params P = load_cst(a.inst + C.inst);
+  const u64 n = P.n;
+  const u64 tileStart = C.S + (u64)(t - C.first) * T;
+  const u64 s_tile = cst(a.s_tile)[t];
+  const u32 q0 = wave * R;  // first chunk of this wave
+  const bool any_out = tileStart + (T - 1) >= C.k0;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const u64 chunkStart = tileStart + (u64)(q0 + r) * CHUNK;
+    const u64 laneStart = chunkStart + (u64)lane * V;
+    const bool outs = MODE == kModeConsume ? any_out : chunkStart + (CHUNK - 1) >= C.k0;
+    if (!outs && !(C.flags & kChainWriteEnd)) continue;
+    // the message before the chunk (CRT: its residues mod p and q), used
+    // after the walk and the scans
+    const u64 q = (u64)t * CH + q0 + r;
+    const u64 E1 = cst(a.excl)[q];
+    const u64 E2 = VAR == kVariantCrt ? cst(a.agg)[q] : 0;
+    // the chunk's first skip (wave-uniform, scalar arithmetic), then each lane's
+    const u64 s_chunk = mulmod_q(s_tile, cst(a.powv)[(u64)(q0 + r) * 64]);
+    const u64 s_first = mulmod_q(s_chunk, pl);
+    if constexpr (VAR == kVariantCrt) {
+      // lane totals as residues up to multiples of p and q, scanned in exact
+      // binary64 arithmetic: |tp| < 2^33 (Ht < 2^35, Lt < 2^32), so the
+      // partial sums stay below 2^39 and the sums formed for reduce_res
+      // below 2^40
+      u64 S[V];
+      double Ht, Lt;
+      walk_sum<V, true>(s_first, S, Ht, Lt);
+      const double tp = fold_p(Ht, P) + Lt;
+      const double tq = fold_q(Ht, P) + Lt;
+      const double ip = wave_scan_f64(tp, lane);
+      const double iq = wave_scan_f64(tq, lane);
+      const double Ep = __longlong_as_double((long long)E2);
+      const double Eq = __longlong_as_double((long long)E1);
+      const double bp = reduce_res(Ep + (ip - tp), P.pd, P.pinv);
+      const double bq = reduce_res(Eq + (iq - tq), P.qd, P.qinv);
+      const MsgRes<V> msg{S, bp, bq};
+      if (outs) chunk_outputs<WG, V, VAR, MODE, EK, -1>(a, sh, C, P, msg, chunkStart, laneStart);
+      chain_end_res<V>(a, C, P, s_first, bp, bq, laneStart);
+    } else {
+      u64 X[V];
+      const u64 x = walk<V>(s_first, n, X);
+      const u64 incl = wave_scan_mod(x, n);
+      const u64 pre = addmod(E1, submod(incl, x, n), n);
+      const MsgExact<V> msg{pre, n, X};
+      if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
+      chain_end<V>(a, C, n, pre, X, s_first, laneStart);
+    }
+  }
+  if constexpr (MODE == kModeConsume) {
+    if (any_out) consume_flush<WG>(a, sh, C.slot);
+  }
+}
+
+template <int WG, int V, int R, int VAR, int MODE, int EK = 0>
+__global__ __launch_bounds__(WG) __attribute__((amdgpu_waves_per_eu(EK != 0 ? 4 : 1)))
+void k_gen2(LaunchArgs a) {
+  static_assert(EK == 0 || (MODE == kModeGenerate && VAR == kVariantCrt),
+                "specialised paths: CRT generate");
   __shared__ TileShared<WG, MODE> sh;
   const int lane = threadIdx.x & 63;
   const u32 wave = uniform(threadIdx.x >> 6);
@@ -1073,60 +1142,20 @@ __global__ __launch_bounds__(WG) void k_gen2(LaunchArgs a) {
     for (int j = 0; j < 7; ++j) sh.acc[j * WG + threadIdx.x] = 0;
     __syncthreads();
   }
-  for (u32 t = blockIdx.x; t < a.ntiles; t += gridDim.x) {
-    const u32 c = cst(a.tile_chain)[t];
-    const Chain C = load_cst(a.chain + c);
-    const rsaprng_params P = load_cst(a.inst + C.inst);
-    const u64 n = P.n;
-    const u64 tileStart = C.S + (u64)(t - C.first) * T;
-    const u64 s_tile = cst(a.s_tile)[t];
-    const u32 q0 = wave * R;  // first chunk of this wave
-    const bool any_out = tileStart + (T - 1) >= C.k0;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const u64 chunkStart = tileStart + (u64)(q0 + r) * CHUNK;
-      const u64 laneStart = chunkStart + (u64)lane * V;
-      const bool outs = MODE == kModeConsume ? any_out : chunkStart + (CHUNK - 1) >= C.k0;
-      if (!outs && !(C.flags & kChainWriteEnd)) continue;
-      // the message before the chunk (CRT: its residues mod p and q), used
-      // after the walk and the scans
-      const u64 q = (u64)t * CH + q0 + r;
-      const u64 E1 = cst(a.excl)[q];
-      const u64 E2 = VAR == kVariantCrt ? cst(a.agg)[q] : 0;
-      // the chunk's first skip (wave-uniform, scalar arithmetic), then each lane's
-      const u64 s_chunk = mulmod_q(s_tile, cst(a.powv)[(u64)(q0 + r) * 64]);
-      const u64 s_first = mulmod_q(s_chunk, pl);
-      if constexpr (VAR == kVariantCrt) {
-        // lane totals as residues up to multiples of p and q, scanned in exact
-        // binary64 arithmetic: |tp| < 2^33 (Ht < 2^35, Lt < 2^32), so the
-        // partial sums stay below 2^39 and the sums formed for reduce_res
-        // below 2^40
-        u64 S[V];
-        double Ht, Lt;
-        walk_sum<V, true>(s_first, S, Ht, Lt);
-        const double tp = fold_p(Ht, P) + Lt;
-        const double tq = fold_q(Ht, P) + Lt;
-        const double ip = wave_scan_f64(tp, lane);
-        const double iq = wave_scan_f64(tq, lane);
-        const double Ep = __longlong_as_double((long long)E2);
-        const double Eq = __longlong_as_double((long long)E1);
-        const double bp = reduce_res(Ep + (ip - tp), P.pd, P.pinv);
-        const double bq = reduce_res(Eq + (iq - tq), P.qd, P.qinv);
-        const MsgRes<V> msg{S, bp, bq};
-        if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-        chain_end_res<V>(a, C, P, s_first, bp, bq, laneStart);
-      } else {
-        u64 X[V];
-        const u64 x = walk<V>(s_first, n, X);
-        const u64 incl = wave_scan_mod(x, n);
-        const u64 pre = addmod(E1, submod(incl, x, n), n);
-        const MsgExact<V> msg{pre, n, X};
-        if (outs) chunk_outputs<WG, V, VAR, MODE>(a, sh, C, P, msg, chunkStart, laneStart);
-        chain_end<V>(a, C, n, pre, X, s_first, laneStart);
+  for (u32 t = a.tile0 + blockIdx.x; t < a.ntiles; t += gridDim.x) {
+    if constexpr (EK == kEKPerChain) {
+      const u32 inst = cst(&a.chain[cst(a.tile_chain)[t]].inst)[0];
+      switch (cst(&a.inst[inst].e)[0]) {
+        case 3: tile2<WG, V, R, VAR, MODE, 3>(a, sh, t, pl, lane, wave); break;
+        case 5: tile2<WG, V, R, VAR, MODE, 5>(a, sh, t, pl, lane, wave); break;
+        case 7: tile2<WG, V, R, VAR, MODE, 7>(a, sh, t, pl, lane, wave); break;
+        case 17: tile2<WG, V, R, VAR, MODE, 17>(a, sh, t, pl, lane, wave); break;
+        case 257: tile2<WG, V, R, VAR, MODE, 257>(a, sh, t, pl, lane, wave); break;
+        case 65537: tile2<WG, V, R, VAR, MODE, 65537>(a, sh, t, pl, lane, wave); break;
+        default: tile2<WG, V, R, VAR, MODE, 0>(a, sh, t, pl, lane, wave); break;
       }
-    }
-    if constexpr (MODE == kModeConsume) {
-      if (any_out) consume_flush<WG>(a, sh, C.slot);
+    } else {
+      tile2<WG, V, R, VAR, MODE, EK>(a, sh, t, pl, lane, wave);
     }
   }
 }
@@ -1221,7 +1250,6 @@ __global__ __launch_bounds__(WG) void k_gen1(LaunchArgs a) {
 // dual-exponent instances, take the general path), with the fast path taking
 // any 8-byte-aligned output (AL = -1).  Each path is its own loop nest, so the
 // kernel's register budget is the largest one's, not their sum.
-constexpr int kEKPerChain = -1;
 
 template <int WG, int V, int R, int VAR, int MODE, int EK, int AL>
 __device__ __forceinline__ void chain3(const LaunchArgs& a, TileShared<WG, MODE>& sh,
@@ -1434,18 +1462,18 @@ static int launch3(const LaunchArgs& a, int grid, void* stream, int* occ) {
   return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
-template <int WG, int V, int R, int VAR, int MODE>
+template <int WG, int V, int R, int VAR, int MODE, int EK = 0>
 static int launch2(const LaunchArgs& a, int grid, void* stream, int* occ) {
   if (occ) {
     int blocks = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen2<WG, V, R, VAR, MODE>, WG, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, k_gen2<WG, V, R, VAR, MODE, EK>, WG,
+                                                     0) != hipSuccess)
       blocks = 1;
     *occ = blocks > 0 ? blocks : 1;
     return RSAPRNG_OK;
   }
-  hipLaunchKernelGGL((k_gen2<WG, V, R, VAR, MODE>), dim3(grid), dim3(WG), 0, (hipStream_t)stream,
-                     a);
+  hipLaunchKernelGGL((k_gen2<WG, V, R, VAR, MODE, EK>), dim3(grid), dim3(WG), 0,
+                     (hipStream_t)stream, a);
   return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
 }
 
@@ -1478,6 +1506,21 @@ int launch_family(const KernelShape& s, const LaunchArgs& a, void* stream, int* 
       if (s.wg == 256 && s.v == 8 && s.r == 2) return launch2<256, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
       if (s.wg == 256 && s.v == 8 && s.r == 4) return launch2<256, 8, 4, VAR, MODE>(a, s.grid, stream, occ);
       if (s.wg == 512 && s.v == 8 && s.r == 2) return launch2<512, 8, 2, VAR, MODE>(a, s.grid, stream, occ);
+      if constexpr (MODE == kModeGenerate && VAR == kVariantCrt) {
+        // 16 indices per lane: the kernel specialised to the launch's (or the
+        // exponent class's) exponent, else each tile takes its own
+        if (s.wg == 256 && s.v == 16 && s.r == 2) {
+          switch (s.e) {
+            case 3: return launch2<256, 16, 2, VAR, MODE, 3>(a, s.grid, stream, occ);
+            case 5: return launch2<256, 16, 2, VAR, MODE, 5>(a, s.grid, stream, occ);
+            case 7: return launch2<256, 16, 2, VAR, MODE, 7>(a, s.grid, stream, occ);
+            case 17: return launch2<256, 16, 2, VAR, MODE, 17>(a, s.grid, stream, occ);
+            case 257: return launch2<256, 16, 2, VAR, MODE, 257>(a, s.grid, stream, occ);
+            case 65537: return launch2<256, 16, 2, VAR, MODE, 65537>(a, s.grid, stream, occ);
+            default: return launch2<256, 16, 2, VAR, MODE, kEKPerChain>(a, s.grid, stream, occ);
+          }
+        }
+      }
       return RSAPRNG_E_ARG;
     }
     if (s.prefix == kPrefixSerial) {

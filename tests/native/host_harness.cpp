@@ -182,12 +182,25 @@ int launch_tiles(const KernelShape& s, const LaunchArgs& a, void* stream) {
             "no chain-serial kernel (%d, 16, %d) for variant %d mode %d e = %u", s.wg, s.r,
             s.variant, s.mode, s.e);
     if (s.prefix == kPrefixSerial) CHECK(s.v == 8 || s.v == 16, "indices per lane %d", s.v);
+    // two passes with 16 indices per lane: CRT generate only; the launch may
+    // cover one exponent class's tiles [tile0, ntiles)
+    if (s.prefix == kPrefixTwoPass && s.v == 16)
+      CHECK(s.variant == kVariantCrt && s.mode == kModeGenerate && s.r == 2,
+            "no two-pass kernel (%d, 16, %d) for variant %d mode %d", s.wg, s.r, s.variant, s.mode);
+    CHECK(a.tile0 < a.ntiles, "empty tile range [%u, %u)", a.tile0, a.ntiles);
+    CHECK(a.tile0 == 0 || (s.prefix == kPrefixTwoPass && s.v == 16),
+          "a tile range from %u outside the exponent classes", a.tile0);
     if (s.prefix == kPrefixLookback) {
       (void)rd(a.ctl, "look-back ctl");
       fakehip::need_device(a.lb, (size_t)a.ntiles * 32, "look-back words");
     }
     for (uint32_t c = 0; c < a.nchain; ++c) {
       const Chain C = chain_at(a, c, "tile chain");
+      // chains outside this launch's tile range belong to another class's launch
+      if (C.first + C.ntiles <= a.tile0 || C.first >= a.ntiles) continue;
+      CHECK(C.first >= a.tile0 && C.first + C.ntiles <= a.ntiles,
+            "chain %u tiles [%u, +%u) straddle the launch's range [%u, %u)", c, C.first, C.ntiles,
+            a.tile0, a.ntiles);
       const rsaprng_params P = rd(a.inst + C.inst, "tile instance");
       if (s.e) CHECK(P.e == s.e, "launch specialised to e = %u holds e = %u", s.e, P.e);
       for (uint32_t t = C.first; t < C.first + C.ntiles; ++t) {
@@ -457,7 +470,7 @@ rsaprng_config cfg_of(int variant, int prefix, int lanes, int r, int persistent,
 }
 
 // (prefix, lanes, chunks per wave, indices per lane)
-const int kShapes[][4] = {{0, 256, 1, 8}, {0, 256, 2, 8}, {0, 256, 4, 8}, {0, 512, 2, 8},
+const int kShapes[][4] = {{0, 256, 1, 8}, {0, 256, 2, 8}, {0, 256, 4, 8}, {0, 512, 2, 8}, {0, 256, 2, 16},
                           {1, 256, 1, 8}, {1, 512, 1, 8}, {1, 256, 1, 16}, {2, 256, 2, 8},
                           {2, 256, 4, 8}, {2, 512, 2, 8}, {2, 256, 1, 16}, {2, 512, 1, 16}};
 
@@ -681,8 +694,10 @@ int main(int argc, char** argv) {
           "autotune left device objects behind");
   }
 
-  // 6. the server: requests arriving in waves, read back and released; then a replay
-  {
+  // 6. the server: requests arriving in waves, read back and released; then a
+  //    replay.  Two passes with 8 indices per lane, then with 16 (iterations
+  //    grouped by exponent class)
+  for (int per : {8, 16}) {
     const size_t d0 = fakehip::live_device_allocations(), s0 = fakehip::live_streams(),
                  e0 = fakehip::live_events();
     rsaprng_server_opts opts;
@@ -690,7 +705,7 @@ int main(int argc, char** argv) {
     opts.arena_bytes = (size_t)16 << 20;  // 2^20 outputs
     opts.iter_outputs = 1 << 16;
     opts.chunk_outputs = 1 << 14;
-    opts.cfg = cfg_of(2, 0, 256, 2, 0);
+    opts.cfg = cfg_of(2, 0, 256, 2, 0, per);
     rsaprng_server_t srv;
     CHECK(rsaprng_server_create(pool, &opts, &srv) == RSAPRNG_OK, "server_create");
     uint64_t total;

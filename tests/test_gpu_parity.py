@@ -30,7 +30,7 @@ def R():
 
 # Every kernel shape the library builds: (lanes, per_lane, chunks_per_wave, prefix),
 # prefix 0 two passes, 1 one pass with look-back, 2 chain-serial.
-SHAPES = ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0),
+SHAPES = ((256, 8, 1, 0), (256, 8, 2, 0), (256, 8, 4, 0), (512, 8, 2, 0), (256, 16, 2, 0),
           (256, 8, 1, 1), (512, 8, 1, 1), (256, 16, 1, 1), (256, 8, 2, 2), (256, 8, 4, 2),
           (512, 8, 2, 2), (256, 16, 1, 2), (512, 16, 1, 2))
 
@@ -123,6 +123,14 @@ def test_every_exponent(R):
         log("every exponent", name, len(insts))
         c, r, _ = _gen_pool(R, insts, ranges, R.config(variant=var))
         _check_ranges(insts, ranges, c, r, "exponents " + name)
+    # two passes with 16 indices per lane: one launch per exponent class (the
+    # unrolled ladders, then every other exponent in one class), ranges packed
+    # so that about half start at odd output elements
+    odd = [(j, k0, 3001 + 2 * j) for j in range(len(insts)) for k0 in (7, 2 * B - 4000)]
+    log("every exponent, exponent classes", len(insts))
+    c, r, _ = _gen_pool(R, insts, odd, R.config(variant=R.VARIANT_CRT, lanes_per_tile=256,
+                                                  per_lane=16, chunks_per_wave=2, prefix=0))
+    _check_ranges(insts, odd, c, r, "exponent classes")
 
 
 def test_exponent_one_is_message(R):

@@ -78,6 +78,8 @@ CFGS = {
     "crt-serial": dict(variant=2, prefix=2),
     "mont-serial-512": dict(variant=1, lanes_per_tile=512, prefix=2),
     "crt-twopass-shortest-first": dict(variant=2),
+    "crt-twopass-16-exponent-classes": dict(variant=2, lanes_per_tile=256, per_lane=16,
+                                            chunks_per_wave=2, prefix=0),
 }
 
 
