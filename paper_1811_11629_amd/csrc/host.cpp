@@ -566,11 +566,24 @@ void group_by_exponent(std::vector<Chain>& chains, const rsaprng_config& c, int 
         c.per_lane == 16) ||
       chains.empty())
     return;
-  auto cls = [&](const Chain& ch) {
+  auto ladder = [&](const Chain& ch) {
     const uint32_t e = inst[ch.inst].e;
     for (int j = 0; j < 6; ++j)
       if (e == kClassE[j]) return j;
     return 6;
+  };
+  // a class of fewer tiles than min_tiles (16 waves of tiles on 1024
+  // resident work-groups; RSAPRNG_CLASS_MIN_TILES) joins the general class:
+  // its own launch would leave most of the device idle in its last wave.  A
+  // launch of one class keeps it whatever its size.
+  const u64h min_tiles = (u64h)env_int("RSAPRNG_CLASS_MIN_TILES", 16384);
+  u64h tiles[7] = {};
+  for (const Chain& ch : chains) tiles[ladder(ch)] += ch.ntiles;
+  int present = 0;
+  for (u64h x : tiles) present += x > 0;
+  auto cls = [&](const Chain& ch) {
+    const int j = ladder(ch);
+    return present == 1 || tiles[j] >= min_tiles ? j : 6;
   };
   // chains are independent in the two-pass form: any order gives the same
   // outputs; the tiles are renumbered in the new order

@@ -117,8 +117,11 @@ rsaprng_config config_for_pool(rsaprng_pool_t pool, const rsaprng_config* cfg, i
 rsaprng_config fit_mode(rsaprng_config c, int mode);
 // Two-pass CRT generate launches with 16 indices per lane: the planned chains
 // ordered by exponent class (stable), their tiles renumbered in that order,
-// and the class boundaries in li (inst: the pool's host records); other
-// launches are left as planned (li->nclass = 0).
+// and the class boundaries in li (inst: the pool's host records).  In a launch
+// of several classes, a class of fewer than 16384 tiles (the environment
+// variable RSAPRNG_CLASS_MIN_TILES overrides it) joins the general class,
+// which takes one launch of the per-tile dispatch kernel.  Other launches are
+// left as planned (li->nclass = 0).
 void group_by_exponent(std::vector<Chain>& chains, const rsaprng_config& c, int mode,
                        const rsaprng_params* inst, LeadIn* li);
 

@@ -484,6 +484,9 @@ hipStream_t new_stream() {
 
 int main(int argc, char** argv) {
   const char* cache = argc > 1 ? argv[1] : "/tmp/rsaprng_harness_tune.jsonl";
+  // every exponent class of a grouped two-pass launch takes a launch of its
+  // own, however few its tiles (the harness's launches are small)
+  setenv("RSAPRNG_CLASS_MIN_TILES", "0", 1);
   std::remove(cache);
   std::vector<uint32_t> es;
   rsaprng_pool_t pool = make_pool(300, &es);

@@ -109,7 +109,7 @@ def test_edge_moduli_and_cribs(R):
                 assert int(c[2 * j * 5000]) == i.m0
 
 
-def test_every_exponent(R):
+def test_every_exponent(R, monkeypatch):
     base = inputs.config3(2)
     es = [1, 3, 5, 7, 17, 257, 65537, 9, 11, 13, 101, 2 ** 31 + 11]
     insts = []
@@ -124,13 +124,18 @@ def test_every_exponent(R):
         c, r, _ = _gen_pool(R, insts, ranges, R.config(variant=var))
         _check_ranges(insts, ranges, c, r, "exponents " + name)
     # two passes with 16 indices per lane: one launch per exponent class (the
-    # unrolled ladders, then every other exponent in one class), ranges packed
-    # so that about half start at odd output elements
+    # unrolled ladders, then every other exponent in one class; the library
+    # gives small classes no launch of their own unless told to), or all in
+    # the per-tile dispatch kernel; ranges packed so that about half start at
+    # odd output elements
     odd = [(j, k0, 3001 + 2 * j) for j in range(len(insts)) for k0 in (7, 2 * B - 4000)]
-    log("every exponent, exponent classes", len(insts))
-    c, r, _ = _gen_pool(R, insts, odd, R.config(variant=R.VARIANT_CRT, lanes_per_tile=256,
-                                                  per_lane=16, chunks_per_wave=2, prefix=0))
-    _check_ranges(insts, odd, c, r, "exponent classes")
+    cfg16 = R.config(variant=R.VARIANT_CRT, lanes_per_tile=256, per_lane=16, chunks_per_wave=2,
+                     prefix=0)
+    for min_tiles in ("0", "16384"):
+        monkeypatch.setenv("RSAPRNG_CLASS_MIN_TILES", min_tiles)
+        log("every exponent, exponent classes of at least", min_tiles, "tiles", len(insts))
+        c, r, _ = _gen_pool(R, insts, odd, cfg16)
+        _check_ranges(insts, odd, c, r, "exponent classes, min %s" % min_tiles)
 
 
 def test_exponent_one_is_message(R):

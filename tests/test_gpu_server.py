@@ -78,13 +78,18 @@ CFGS = {
     "crt-serial": dict(variant=2, prefix=2),
     "mont-serial-512": dict(variant=1, lanes_per_tile=512, prefix=2),
     "crt-twopass-shortest-first": dict(variant=2),
+    "crt-twopass-16": dict(variant=2, lanes_per_tile=256, per_lane=16, chunks_per_wave=2,
+                           prefix=0),
     "crt-twopass-16-exponent-classes": dict(variant=2, lanes_per_tile=256, per_lane=16,
                                             chunks_per_wave=2, prefix=0),
 }
 
 
 @pytest.mark.parametrize("name", list(CFGS))
-def test_mix_matches_oracle_and_alone(R, pool_insts, name):
+def test_mix_matches_oracle_and_alone(R, pool_insts, name, monkeypatch):
+    # "exponent-classes": every iteration's exponent classes take launches of
+    # their own (the default keeps small classes in one per-tile launch)
+    monkeypatch.setenv("RSAPRNG_CLASS_MIN_TILES", "0" if "exponent-classes" in name else "16384")
     cfg = R.config(**CFGS[name])
     reqs = make_requests(90, 777 + len(name), len(pool_insts))
     log("server mix", name, "requests", len(reqs), "outputs", sum(r[2] for r in reqs))
