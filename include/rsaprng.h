@@ -228,7 +228,17 @@ typedef struct {
   uint64_t out_off;     /* generate: output element offset; consume: stats record index */
 } rsaprng_pool_req;
 
-/* Kernel configuration.  Outputs never depend on it. */
+/* Kernel configuration.  Outputs never depend on it.
+ * Environment variables read by the library (performance and diagnostics only):
+ *   RSAPRNG_VARIANT          variant taken when variant is 0 (default 2, CRT)
+ *   RSAPRNG_PREFIX           prefix form taken when prefix is not 0, 1 or 2
+ *                            (default 0, two passes)
+ *   RSAPRNG_SPIN_LIMIT       polls of a look-back word before the one-pass kernel
+ *                            reports RSAPRNG_E_DEVICE (default 2^22)
+ *   RSAPRNG_CLASS_MIN_TILES  in a two-pass launch with 16 indices per lane, the
+ *                            fewest tiles an exponent class takes a launch of its
+ *                            own for (default 16384)
+ *   RSAPRNG_TUNE_LOG         set: the autotuner prints each trial to stderr */
 typedef struct {
   int variant;          /* 0 auto, 1 Montgomery-64 integer path, 2 CRT with binary64 residues */
   int lanes_per_tile;   /* work-group size: 0 default, else 256 or 512 */
