@@ -67,7 +67,7 @@ def _run(R, fn, pool, reqs, total, cfg, stream):
     return oc, orr
 
 
-def test_noalloc_matches_pool_generate(R):
+def test_noalloc_matches_pool_generate(R, monkeypatch):
     import torch
     insts = _instances()
     pool = R.Pool.from_instances(insts)
@@ -78,7 +78,14 @@ def test_noalloc_matches_pool_generate(R):
             R.config(variant=2, prefix=0, lanes_per_tile=512, chunks_per_wave=2, persistent=1),
             R.config(variant=2, prefix=2, lanes_per_tile=512, chunks_per_wave=2),
             R.config(variant=1, prefix=2, lanes_per_tile=256, chunks_per_wave=4, persistent=1),
-            R.config(variant=2, prefix=1, lanes_per_tile=256)]           # one pass -> two passes
+            R.config(variant=2, prefix=1, lanes_per_tile=256),           # one pass -> two passes
+            # 16 indices per lane: two passes, where the reference gives every
+            # exponent class a launch of its own and the no-allocation call
+            # (which plans no classes) takes the per-tile dispatch kernel; and
+            # chain-serial, run as two chunks of 8 for mixed exponents
+            R.config(variant=2, prefix=0, lanes_per_tile=256, per_lane=16, chunks_per_wave=2),
+            R.config(variant=2, prefix=2, lanes_per_tile=256, per_lane=16, chunks_per_wave=1)]
+    monkeypatch.setenv("RSAPRNG_CLASS_MIN_TILES", "0")
     for ci, cfg in enumerate(cfgs):
         # two calls in a row on one stream, the second smaller, both left in flight
         # before either is read back
