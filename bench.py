@@ -526,7 +526,8 @@ def run_batched_uneven(R, torch, stream, steps, cfg=None, plain=True, verify_cap
            "verified": ver,
            "roofline": roofline_of(by_e, ms / 1e3, False, tile_kernel_name(best),
                                    "one graph replay (chain setup, prefix pass over the "
-                                   "lead-in, tile kernel)")}
+                                   "lead-in, tile kernel; with two passes of 16 indices "
+                                   "per lane one tile launch per exponent class)")}
     log("batched uneven: %.1f Gnum/s graph" % batched +
         (" vs %.1f plain" % res["plain_per_request_gnumbers_per_s"] if plain_s else ""))
     del b, oc, orr
