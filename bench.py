@@ -396,7 +396,39 @@ def run_plain_config2(R, gens, oc, orr, torch, reps=2):
     return best
 
 
-def run_consume_sweep(R, torch, stream, steps, exponents=None, cfg=None):
+def verify_consume(R, st, insts, count, threads=None):
+    """Untimed: records of the last timed replay against the oracle's statistics
+    of the same instances (whole 2^18-index ranges), at the ends of the record
+    array and spread through it."""
+    import concurrent.futures as cf
+    from fractions import Fraction
+
+    import numpy as np
+
+    import oracle
+    got = R.stats_decode(st)
+    m = len(insts)
+    idx = sorted({0, 1, m // 2, m - 1} | {(j * 613) % m for j in range(1, 5)})
+    threads = threads or min(16, os.cpu_count() or 1)
+
+    def ref(i):
+        it = insts[i]
+        return oracle.consume(it.p, it.q, it.e, it.m0, it.s0, 0, count)
+
+    t0 = time.perf_counter()
+    with cf.ThreadPoolExecutor(threads) as ex:
+        refs = list(ex.map(ref, idx))
+    ok = True
+    for i, r in zip(idx, refs):
+        g = got[i]
+        ok = ok and (g["count"] == count and g["sum_fx"] == r["sum_fx"] and
+                     g["lt_half"] == r["lt_half"] and np.array_equal(g["hist"], r["hist"]) and
+                     g["sum"] == float(Fraction(r["sum_fx"], 1 << 128)))
+    return {"records_compared": len(idx), "record_indices": idx, "all_equal": bool(ok),
+            "seconds": time.perf_counter() - t0}
+
+
+def run_consume_sweep(R, torch, stream, steps, exponents=None, cfg=None, verify=True):
     import inputs
     base = inputs.config3()
     out = {}
@@ -414,13 +446,18 @@ def run_consume_sweep(R, torch, stream, steps, exponents=None, cfg=None):
         b.check()
         n = len(insts) << 18
         ms = sum(kms) / len(kms)
+        ver = verify_consume(R, st, insts, 1 << 18) if verify else None
         out["e%d" % e] = {"gnumbers_per_s": n / (ms / 1e3) / 1e9, "ms_per_launch": ms,
+                          "verified": ver,
                           "variant": int(best.variant), "config": best.as_dict(),
                           "roofline": roofline_of({e: n}, ms / 1e3, True,
                                                   tile_kernel_name(best, exponent=e, mode="consume"),
                                                   "one graph replay (statistics zeroing, chain "
                                                   "setup, prefix pass, tile kernel, finalisation)")}
-        log("consume e=%d: %.1f Gnum/s (%.3f ms)" % (e, out["e%d" % e]["gnumbers_per_s"], ms))
+        log("consume e=%d: %.1f Gnum/s (%.3f ms)%s" % (
+            e, out["e%d" % e]["gnumbers_per_s"], ms,
+            "" if ver is None else "; %d records equal the oracle's: %s" % (
+                ver["records_compared"], ver["all_equal"])))
         del b, pool
     return out
 
