@@ -963,7 +963,11 @@ def run_issue_probe(R, torch, stream, iters=1 << 16, store_elems=1 << 30):
             name, rate / 1e12, rate / (VALU_PEAK_TOPS * 1e12), ms))
     oc = torch.empty(store_elems, dtype=torch.int64, device="cuda")
     orr = torch.empty(store_elems, dtype=torch.float64, device="cuda")
-    for name, kind in (("tile_pattern", R.PROBE_STORE_TILE), ("linear", R.PROBE_STORE_LINEAR)):
+    for name, kind in (("tile_pattern", R.PROBE_STORE_TILE),
+                       ("tile_pattern_regular_stores", R.PROBE_STORE_TILE_PLAIN),
+                       ("block16_pattern", R.PROBE_STORE_BLOCK16),
+                       ("block16_pattern_regular_stores", R.PROBE_STORE_BLOCK16_PLAIN),
+                       ("linear", R.PROBE_STORE_LINEAR)):
         R.rsaprng_probe(kind, store_elems, oc, orr, stream=stream)
         times = []
         for _ in range(5):

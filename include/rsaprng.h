@@ -537,10 +537,16 @@ int rsaprng_debug_encrypt(uint64_t p, uint64_t q, uint64_t e, int variant, const
  *    1 <= n <= 2^32.  *work = the lane-instructions of the class issued.
  *  - Store probes: n elements written to each of out_u64 and out_f64
  *    (device, 16-byte aligned, n a positive multiple of 2^20, n <= 2^36) with
- *    the chain-serial tile kernels' store pattern (RSAPRNG_PROBE_STORE_TILE:
- *    one 512-lane work-group per 2^20 elements, 16-byte non-temporal stores,
- *    each store instruction covering 1 KiB) or a plain linear write
- *    (RSAPRNG_PROBE_STORE_LINEAR).  *work = the bytes written, 16 n.
+ *    the chain-serial tile kernels' store patterns: one work-group per 2^20
+ *    elements, 16-byte stores, each store instruction covering 1 KiB; 512
+ *    lanes with c and r stores alternating (RSAPRNG_PROBE_STORE_TILE,
+ *    non-temporal, as the kernels of two chunks of 8 indices per lane;
+ *    RSAPRNG_PROBE_STORE_TILE_PLAIN, regular stores), or 256 lanes with a
+ *    wave's eight c stores before its eight r stores
+ *    (RSAPRNG_PROBE_STORE_BLOCK16, non-temporal, as the kernels of 16 indices
+ *    per lane; RSAPRNG_PROBE_STORE_BLOCK16_PLAIN, regular stores); or a plain
+ *    linear write (RSAPRNG_PROBE_STORE_LINEAR).  *work = the bytes written,
+ *    16 n.
  * Enqueued on `stream`; the caller times the launch.  RSAPRNG_E_ARG for an
  * unknown kind or a bad n, RSAPRNG_E_ALIGN for misaligned store buffers.
  * ------------------------------------------------------------------------ */
@@ -557,6 +563,9 @@ int rsaprng_debug_encrypt(uint64_t p, uint64_t q, uint64_t e, int variant, const
 #define RSAPRNG_PROBE_MUL_U32_U24 10
 #define RSAPRNG_PROBE_STORE_TILE 16
 #define RSAPRNG_PROBE_STORE_LINEAR 17
+#define RSAPRNG_PROBE_STORE_TILE_PLAIN 18
+#define RSAPRNG_PROBE_STORE_BLOCK16 19
+#define RSAPRNG_PROBE_STORE_BLOCK16_PLAIN 20
 int rsaprng_probe(int kind, uint64_t n, uint64_t* out_u64, double* out_f64, double* work,
                   void* stream);
 

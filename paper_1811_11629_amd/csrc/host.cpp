@@ -1897,7 +1897,9 @@ int rsaprng_probe(int kind, uint64_t n, uint64_t* out_u64, double* out_f64, doub
     *work = (double)probe_threads(d->ncu) * (double)probe_ops_per_thread(n);
     return launch_probe(kind, d->ncu, n, sink, nullptr, stream);
   }
-  if (kind == RSAPRNG_PROBE_STORE_TILE || kind == RSAPRNG_PROBE_STORE_LINEAR) {
+  if (kind == RSAPRNG_PROBE_STORE_TILE || kind == RSAPRNG_PROBE_STORE_LINEAR ||
+      kind == RSAPRNG_PROBE_STORE_TILE_PLAIN || kind == RSAPRNG_PROBE_STORE_BLOCK16 ||
+      kind == RSAPRNG_PROBE_STORE_BLOCK16_PLAIN) {
     if (!out_u64 || !out_f64) return RSAPRNG_E_NULL;
     if (((uintptr_t)out_u64 & 15) || ((uintptr_t)out_f64 & 15)) return RSAPRNG_E_ALIGN;
     if (n == 0 || (n & ((1ull << 20) - 1)) || n > (1ull << 36)) return RSAPRNG_E_ARG;

@@ -84,27 +84,47 @@ __global__ __launch_bounds__(kProbeWG) void k_probe_issue(u64 iters, u32 m, doub
   sink[tid] = acc;
 }
 
-// The store pattern of the chain-serial tile kernels: one work-group of 512
-// lanes per 2^20-element chain, steps of 8192 elements, each wave storing two
-// 512-element chunks per array per step as 16-byte non-temporal pairs (store
-// j of a chunk writes elements 128 j + 2 lane and the next).  The values are
-// the element indices.
+// The store patterns of the chain-serial tile kernels: one work-group of WG
+// lanes per 2^20-element chain, in steps of WG / 64 wave chunks of 1024
+// elements; store j of a wave writes elements 128 j + 2 lane and the next of
+// its chunk (1 KiB per store instruction), j = 0 .. 7, for c and for r, as
+// 16-byte pairs, non-temporal (NT) or not.  SEQ: the wave's eight c stores,
+// then its eight r stores (the kernels of 16 indices per lane, whose c and r
+// take one transpose block in turn); otherwise c and r alternate (the kernels
+// of two chunks of 8).  The values are the element indices.
 typedef u64 u64x2 __attribute__((ext_vector_type(2)));
 
-__global__ __launch_bounds__(512) void k_probe_store_tile(u64* oc, double* orr) {
+template <bool NT>
+__device__ __forceinline__ void put2(u64* p, u64 a, u64 b) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(u64x2{a, b}, reinterpret_cast<u64x2*>(p));
+  else
+    *reinterpret_cast<u64x2*>(p) = u64x2{a, b};
+}
+
+__device__ __forceinline__ u64 bits(u64 e) { return (u64)__double_as_longlong((double)e); }
+
+template <int WG, bool NT, bool SEQ>
+__global__ __launch_bounds__(WG) void k_probe_store_tile(u64* oc, double* orr) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const u64 chain0 = (u64)blockIdx.x << 20;
-  for (u64 step = 0; step < (1u << 20); step += 8192) {
+  u64* const r = reinterpret_cast<u64*>(orr);
+  for (u64 step = 0; step < (1u << 20); step += (WG / 64) * 1024) {
+    const u64 w0 = chain0 + step + (u64)wave * 1024 + 2 * lane;
+    if constexpr (SEQ) {
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
-      const u64 chunk = chain0 + step + ((u64)wave * 2 + r) * 512;
+      for (int j = 0; j < 8; ++j) put2<NT>(oc + w0 + j * 128, w0 + j * 128, w0 + j * 128 + 1);
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const u64 e = chunk + (u64)j * 128 + 2 * lane;
-        __builtin_nontemporal_store(u64x2{e, e + 1}, reinterpret_cast<u64x2*>(oc + e));
-        __builtin_nontemporal_store(
-            u64x2{(u64)__double_as_longlong((double)e), (u64)__double_as_longlong((double)(e + 1))},
-            reinterpret_cast<u64x2*>(reinterpret_cast<u64*>(orr) + e));
+      for (int j = 0; j < 8; ++j) {
+        const u64 e = w0 + j * 128;
+        put2<NT>(r + e, bits(e), bits(e + 1));
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const u64 e = w0 + j * 128;
+        put2<NT>(oc + e, e, e + 1);
+        put2<NT>(r + e, bits(e), bits(e + 1));
       }
     }
   }
@@ -148,8 +168,20 @@ int launch_probe(int kind, int ncu, u64 n, u64* out_u64, double* out_f64, void* 
     case RSAPRNG_PROBE_LSHL_ADD_U64: return launch_issue<RSAPRNG_PROBE_LSHL_ADD_U64>(grid, n, out_u64, stream);
     case RSAPRNG_PROBE_MUL_U32_U24: return launch_issue<RSAPRNG_PROBE_MUL_U32_U24>(grid, n, out_u64, stream);
     case RSAPRNG_PROBE_STORE_TILE:
-      hipLaunchKernelGGL(k_probe_store_tile, dim3((unsigned)(n >> 20)), dim3(512), 0,
-                         (hipStream_t)stream, out_u64, out_f64);
+      hipLaunchKernelGGL((k_probe_store_tile<512, true, false>), dim3((unsigned)(n >> 20)),
+                         dim3(512), 0, (hipStream_t)stream, out_u64, out_f64);
+      return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
+    case RSAPRNG_PROBE_STORE_TILE_PLAIN:
+      hipLaunchKernelGGL((k_probe_store_tile<512, false, false>), dim3((unsigned)(n >> 20)),
+                         dim3(512), 0, (hipStream_t)stream, out_u64, out_f64);
+      return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
+    case RSAPRNG_PROBE_STORE_BLOCK16:
+      hipLaunchKernelGGL((k_probe_store_tile<256, true, true>), dim3((unsigned)(n >> 20)),
+                         dim3(256), 0, (hipStream_t)stream, out_u64, out_f64);
+      return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
+    case RSAPRNG_PROBE_STORE_BLOCK16_PLAIN:
+      hipLaunchKernelGGL((k_probe_store_tile<256, false, true>), dim3((unsigned)(n >> 20)),
+                         dim3(256), 0, (hipStream_t)stream, out_u64, out_f64);
       return hipGetLastError() == hipSuccess ? RSAPRNG_OK : RSAPRNG_E_HIP;
     case RSAPRNG_PROBE_STORE_LINEAR:
       hipLaunchKernelGGL(k_probe_store_linear, dim3(grid), dim3(256), 0, (hipStream_t)stream,

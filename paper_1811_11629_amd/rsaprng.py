@@ -566,6 +566,7 @@ PROBES = {"v_fma_f64": 0, "v_mul_f64": 1, "v_add_f64": 2, "v_rndne_f64": 3,
           "v_mad_u64_u32": 4, "v_mul_lo_u32": 5, "v_mul_hi_u32": 6, "v_add_u32": 7,
           "v_cvt_f64_u32": 8, "v_lshl_add_u64": 9, "v_mul_u32_u24": 10}
 PROBE_STORE_TILE, PROBE_STORE_LINEAR = 16, 17
+PROBE_STORE_TILE_PLAIN, PROBE_STORE_BLOCK16, PROBE_STORE_BLOCK16_PLAIN = 18, 19, 20
 
 
 def rsaprng_probe(kind: int, n: int, out_u64=None, out_f64=None, stream=None) -> float:
